@@ -1,0 +1,216 @@
+/*
+ * phprng.h -- C interface of the MI355X (gfx950) library for the Pohlig-Hellman
+ * parameter-split pseudorandom number generator of P. D. Beale ("A new class
+ * of scalable parallel pseudorandom number generators based on Pohlig-Hellman
+ * exponentiation ciphers").
+ *
+ * Each generator instance owns a prime modulus n and an exponent e coprime to
+ * n - 1 (Sec. I, eq. (1)).  Its messages follow the pseudorandom-skip
+ * schedule of eqs. (5)-(7): s_k = a s_{k-1} mod p, m_k = (m_{k-1} + s_k) mod n,
+ * and each draw follows algorithm (9) of Sec. IV:
+ *     s := a s mod p;  m := (m + s) mod n;  c := m^e mod n;  R := (c+1)/(n+1).
+ *
+ * Conventions fixed by this interface (readings of the paper):
+ *   - Position.  An instance at position k holds the state (m_k, s_k) of
+ *     eq. (7).  A draw advances to k+1 and returns c_{k+1} (and R_{k+1}), so
+ *     the t-th draw (t = 0, 1, ...) from position k returns c_{k+1+t}, and N
+ *     draws leave the instance at k + N.
+ *   - Base state.  Position 0 is (m_0, s_0) = (0, 1) (Sec. IV, seeding by
+ *     skipping from a base state) unless m_0 / s_0 are supplied.
+ *   - Widths.  Width 32: n prime in [2^31, 2^32), skip p = 2^31 - 1,
+ *     a = 784588716 (the L'Ecuyer skip generator tested in Sec. II); c is a
+ *     uint32.  Width 64: n prime in [2^62, 2^63), skip p = 2^61 - 1 with the
+ *     fixed primitive root a = 1633150009242682173 (the paper names no 64-bit
+ *     skip parameters); c is a uint64.  p < n always holds.
+ *   - Uniform.  R is the IEEE binary64 round-to-nearest-even quotient of
+ *     binary64(c+1) by binary64(n+1).  For width 32 both conversions are
+ *     exact and R lies in (0, 1); for width 64 the conversions round and R
+ *     lies in (0, 1] (R = 1.0 occurs for the largest ciphertexts).
+ *   - 64-bit positions.  Width-64 instances support positions k with
+ *     k + (skip offset) < 2^34; calls that would reach beyond return
+ *     PHPRNG_E_RANGE.  Width-32 positions use the whole uint64 range.
+ *
+ * Threading: a context may be used from one host thread at a time.  Every
+ * call validates all of its arguments before it changes any state or
+ * launches any kernel, so an error return leaves the context unchanged.
+ * Nothing throws across this interface.
+ */
+#ifndef PHPRNG_H
+#define PHPRNG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PHPRNG_OK = 0,
+  PHPRNG_E_INVALID = -1,   /* null pointer, bad width/mode/id, bad size      */
+  PHPRNG_E_NOT_PRIME = -2, /* modulus n is not prime                          */
+  PHPRNG_E_EXPONENT = -3,  /* e < 3, gcd(e, n-1) != 1, or e = 1 mod (n-1)     */
+  PHPRNG_E_RANGE = -4,     /* n outside its width range, output range beyond
+                              the stated capacity, position beyond range      */
+  PHPRNG_E_NOMEM = -5,     /* host or device allocation failed                */
+  PHPRNG_E_DEVICE = -6     /* a HIP call failed; the message is kept in the
+                              context (phprng_last_error)                     */
+} phprng_status;
+
+typedef struct phprng_ctx phprng_ctx;
+
+/* The mutable state of an instance (Sec. II: m, s and c change; n, e, p, a
+ * are fixed) plus its position k.  c is c_k = m_k^e mod n. */
+typedef struct {
+  uint64_t m, s, c, k;
+} phprng_state;
+
+/* One generation request: `count` draws from instance `instance`, written to
+ * element offsets [out_offset, out_offset + count) of the output arrays. */
+typedef struct {
+  uint32_t instance;
+  uint32_t reserved; /* must be 0 */
+  uint64_t count;
+  uint64_t out_offset;
+} phprng_request;
+
+/* Launch shape of the batched kernel.  Zero fields mean "library default". */
+typedef struct {
+  int32_t block_threads;   /* 64, 128, 256 or 512 */
+  int32_t blocks_per_cu;   /* resident blocks per compute unit for the persistent grid */
+  int32_t tiles_per_chunk; /* consecutive 2048-draw tiles a wave takes per work grab (1..64) */
+  int32_t unroll;          /* encryption-loop unroll: 1, 2 or 4 */
+} phprng_tuning;
+
+enum { PHPRNG_MODE_PERSISTENT = 0, PHPRNG_MODE_PLAIN = 1 };
+
+/* ---- host-only helpers (no device needed) --------------------------------*/
+
+/* Skip generator of eq. (5) for a width: p and a (see the conventions). */
+phprng_status phprng_skip_params(int width, uint64_t *p, uint64_t *a);
+
+/* Admissibility of (n, e) for a width (Sec. I, II, IV): PHPRNG_OK, or the
+ * reason it is rejected.  Primality is decided by trial division followed by
+ * deterministic Rabin-Miller (five prime bases below 2^32, twelve above). */
+phprng_status phprng_check_instance(int width, uint64_t n, uint64_t e);
+
+/* Seeded draw of `count` instance parameters (host arrays n, e, k of length
+ * count).  One SplitMix64 stream (Steele, Lea and Flood, 2014) started at
+ * `seed` is consumed in this order, per instance:
+ *   repeat { x = next(); n = (lo + x mod span) | 1 over the width's range
+ *            [lo, lo + span); reject n unless prime and not drawn before in
+ *            this call; y = next(); take the first admissible e among
+ *            e_set[(y mod e_len + t) mod e_len], t = 0, 1, ...; reject n if
+ *            none is }
+ *   then k = k_lo + next() mod (k_hi - k_lo) if k_hi > k_lo, else k = k_lo.
+ * e_set: host array of e_len candidate exponents. */
+phprng_status phprng_draw_instances(int width, uint64_t seed, uint64_t count, const uint64_t *e_set, int e_len,
+                                    uint64_t k_lo, uint64_t k_hi, uint64_t *n, uint64_t *e, uint64_t *k);
+
+const char *phprng_status_string(phprng_status st);
+
+/* ---- contexts --------------------------------------------------------------*/
+
+/* Create a context on HIP device `device` with room for max_instances
+ * instances (device records of 128 bytes each).  Builds the universal
+ * 32-bit skip-prefix table of eq. (7b) on the device (12 MB); the 64-bit
+ * table (200 MB) is built when the first width-64 instance is added.
+ * *ctx receives the context; the caller owns it and frees it with
+ * phprng_destroy. */
+phprng_status phprng_create(phprng_ctx **ctx, int device, uint64_t max_instances);
+phprng_status phprng_destroy(phprng_ctx *ctx);
+
+/* Message of the last PHPRNG_E_DEVICE (or other) error on this context;
+ * owned by the context, valid until the next call. */
+const char *phprng_last_error(const phprng_ctx *ctx);
+
+/* Add `count` instances of one width (host arrays of length count).
+ * m0, s0, k0 may each be NULL (then 0, 1, 0): instance i starts from
+ * (m_0, s_0) = (m0[i], s0[i]) and is positioned at k0[i] by eq. (7).
+ * s0[i] must lie in [1, p-1] and m0[i] in [0, n-1].  All instances are
+ * validated before any is added; ids receives the new instance ids. */
+phprng_status phprng_add_instances(phprng_ctx *ctx, uint64_t count, int width, const uint64_t *n, const uint64_t *e,
+                                   const uint64_t *m0, const uint64_t *s0, const uint64_t *k0, uint32_t *ids);
+
+/* phprng_draw_instances followed by phprng_add_instances with m0 = 0, s0 = 1. */
+phprng_status phprng_seed_instances(phprng_ctx *ctx, uint64_t count, int width, uint64_t seed,
+                                    const uint64_t *e_set, int e_len, uint64_t k_lo, uint64_t k_hi, uint32_t *ids);
+
+uint64_t phprng_instance_count(const phprng_ctx *ctx);
+
+/* Generate draws for `nreq` requests (host array) into caller-owned device
+ * arrays: out_c32 receives the ciphertexts of width-32 requests, out_c64 those
+ * of width-64 requests, out_r the uniforms of both; any of them may be NULL
+ * (that output is not written).  `capacity` is the element count of every
+ * non-NULL output array; each request must satisfy out_offset + count <=
+ * capacity.  Requests must not overlap in the outputs they write.  Several
+ * requests may name the same instance: they are served in request order, so
+ * each continues where the previous one ends.  Positions advance on the host
+ * at call time; the kernels run asynchronously on `stream` (a hipStream_t, or
+ * NULL for the null stream) and the outputs are valid once it completes.
+ * mode: PHPRNG_MODE_PERSISTENT (one work-stealing launch for the whole batch)
+ * or PHPRNG_MODE_PLAIN (one launch per request).  A request with count 0 is
+ * allowed and does nothing. */
+phprng_status phprng_generate(phprng_ctx *ctx, const phprng_request *reqs, uint64_t nreq, uint32_t *out_c32,
+                              uint64_t *out_c64, double *out_r, uint64_t capacity, void *stream, int mode);
+
+/* Move instance `id` by delta positions (eq. (7); delta < 0 moves backward as
+ * in Sec. II).  PHPRNG_E_RANGE if the position would leave its range. */
+phprng_status phprng_jump(phprng_ctx *ctx, uint32_t id, int64_t delta);
+
+/* Current state (m_k, s_k, c_k, k) of instance `id`. */
+phprng_status phprng_get_state(phprng_ctx *ctx, uint32_t id, phprng_state *out);
+
+/* Restore instance `id` to the state (st->m, st->s) reported at position
+ * st->k (st->c is ignored).  Any s in [1, p-1] is accepted: the library finds
+ * t with a^t = s mod p by a Pohlig-Hellman discrete logarithm (p - 1 is
+ * smooth for both skip moduli).  PHPRNG_E_RANGE for width 64 if t lies beyond
+ * the supported position range. */
+phprng_status phprng_set_state(phprng_ctx *ctx, uint32_t id, const phprng_state *st);
+
+/* Fixed parameters of instance `id` (any pointer may be NULL). */
+phprng_status phprng_get_params(phprng_ctx *ctx, uint32_t id, uint64_t *n, uint64_t *e, uint64_t *p, uint64_t *a,
+                                int *width);
+
+/* Launch shape used by phprng_generate (persistent mode) and graphs. */
+phprng_status phprng_set_tuning(phprng_ctx *ctx, const phprng_tuning *t);
+phprng_status phprng_get_tuning(phprng_ctx *ctx, phprng_tuning *t);
+
+/* Time candidate launch shapes on a synthetic batch of `draws` draws spread
+ * over the context's first instances (their positions are restored
+ * afterwards; device scratch of 12 bytes per draw is allocated and freed),
+ * keep the fastest, and return it in *best (may be NULL). */
+phprng_status phprng_autotune(phprng_ctx *ctx, uint64_t draws, phprng_tuning *best);
+
+/* ---- captured repeat draws -------------------------------------------------*/
+
+typedef struct phprng_graph phprng_graph;
+
+/* Capture one persistent generation of `reqs` into a HIP graph.  Each
+ * phprng_graph_launch continues every request's instance by its count (the
+ * request positions are advanced on the device by the graph itself) and
+ * overwrites the same output ranges.  The instances' host positions advance
+ * at each launch.  Requests must name distinct instances. */
+phprng_status phprng_graph_create(phprng_ctx *ctx, const phprng_request *reqs, uint64_t nreq, uint32_t *out_c32,
+                                  uint64_t *out_c64, double *out_r, uint64_t capacity, void *stream,
+                                  phprng_graph **graph);
+phprng_status phprng_graph_launch(phprng_graph *graph, void *stream);
+phprng_status phprng_graph_destroy(phprng_graph *graph);
+
+/* Kernel time of the last phprng_generate / phprng_graph_launch call on the
+ * context, in milliseconds, measured with HIP events recorded on its stream
+ * right before and after the generation kernel(s); waits for that stream.
+ * PLAIN mode reports the span of all its launches. */
+phprng_status phprng_last_kernel_ms(phprng_ctx *ctx, double *ms);
+
+/* Cumulative generation-kernel time (same events as above) and number of
+ * timed calls since the last phprng_timing_reset, without stalling the host
+ * between calls: each call's events are read when its staging slot is
+ * recycled, and this function waits for the calls still in flight. */
+phprng_status phprng_timing_reset(phprng_ctx *ctx);
+phprng_status phprng_timing_read(phprng_ctx *ctx, double *total_ms, uint64_t *calls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHPRNG_H */

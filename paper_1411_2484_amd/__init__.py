@@ -1,0 +1,321 @@
+"""Python binding of libphprng.so, the gfx950 library for the Pohlig-Hellman
+parameter-split pseudorandom number generator (include/phprng.h).
+
+This module only marshals arguments: every step of generation runs in the
+HIP kernels of the library.  Importing it does not load the library; the
+first call does, and raises if ``libphprng.so`` has not been built
+(``python -m paper_1411_2484_amd.build``).  There is no CPU fallback.
+
+Device memory and streams come from PyTorch: output arrays are CUDA (HIP)
+tensors and ``stream`` defaults to ``torch.cuda.current_stream()``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphprng.so")
+
+PHPRNG_OK = 0
+PHPRNG_E_INVALID = -1
+PHPRNG_E_NOT_PRIME = -2
+PHPRNG_E_EXPONENT = -3
+PHPRNG_E_RANGE = -4
+PHPRNG_E_NOMEM = -5
+PHPRNG_E_DEVICE = -6
+
+PHPRNG_MODE_PERSISTENT = 0
+PHPRNG_MODE_PLAIN = 1
+
+_u64 = ctypes.c_uint64
+_pu64 = ctypes.POINTER(ctypes.c_uint64)
+_pu32 = ctypes.POINTER(ctypes.c_uint32)
+_vp = ctypes.c_void_p
+
+
+class phprng_state(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_uint64), ("s", ctypes.c_uint64), ("c", ctypes.c_uint64), ("k", ctypes.c_uint64)]
+
+
+class phprng_request(ctypes.Structure):
+    _fields_ = [("instance", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("count", ctypes.c_uint64),
+                ("out_offset", ctypes.c_uint64)]
+
+
+class phprng_tuning(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("tiles_per_chunk", ctypes.c_int32), ("unroll", ctypes.c_int32)]
+
+
+REQUEST_DTYPE = np.dtype([("instance", np.uint32), ("reserved", np.uint32), ("count", np.uint64),
+                          ("out_offset", np.uint64)])
+
+# name -> (restype, argtypes); every symbol declared in include/phprng.h
+SIGNATURES = {
+    "phprng_skip_params": (ctypes.c_int, [ctypes.c_int, _pu64, _pu64]),
+    "phprng_check_instance": (ctypes.c_int, [ctypes.c_int, _u64, _u64]),
+    "phprng_draw_instances": (ctypes.c_int, [ctypes.c_int, _u64, _u64, _pu64, ctypes.c_int, _u64, _u64, _pu64,
+                                             _pu64, _pu64]),
+    "phprng_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "phprng_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _u64]),
+    "phprng_destroy": (ctypes.c_int, [_vp]),
+    "phprng_last_error": (ctypes.c_char_p, [_vp]),
+    "phprng_add_instances": (ctypes.c_int, [_vp, _u64, ctypes.c_int, _pu64, _pu64, _pu64, _pu64, _pu64, _pu32]),
+    "phprng_seed_instances": (ctypes.c_int, [_vp, _u64, ctypes.c_int, _u64, _pu64, ctypes.c_int, _u64, _u64,
+                                             _pu32]),
+    "phprng_instance_count": (_u64, [_vp]),
+    "phprng_generate": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp, ctypes.c_int]),
+    "phprng_jump": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_int64]),
+    "phprng_get_state": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(phprng_state)]),
+    "phprng_set_state": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(phprng_state)]),
+    "phprng_get_params": (ctypes.c_int, [_vp, ctypes.c_uint32, _pu64, _pu64, _pu64, _pu64,
+                                         ctypes.POINTER(ctypes.c_int)]),
+    "phprng_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(phprng_tuning)]),
+    "phprng_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(phprng_tuning)]),
+    "phprng_autotune": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(phprng_tuning)]),
+    "phprng_graph_create": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp, ctypes.POINTER(_vp)]),
+    "phprng_graph_launch": (ctypes.c_int, [_vp, _vp]),
+    "phprng_graph_destroy": (ctypes.c_int, [_vp]),
+    "phprng_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
+    "phprng_timing_reset": (ctypes.c_int, [_vp]),
+    "phprng_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libphprng.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libphprng.so is not built: run `python -m paper_1411_2484_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class PhprngError(RuntimeError):
+    def __init__(self, status, message=""):
+        self.status = status
+        text = lib().phprng_status_string(status).decode()
+        super().__init__("phprng status %d (%s)%s" % (status, text, ": " + message if message else ""))
+
+
+def _u64arr(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.uint64))
+    return a, a.ctypes.data_as(_pu64)
+
+
+def _check(st, ctx=None):
+    if st != PHPRNG_OK:
+        msg = lib().phprng_last_error(ctx).decode() if ctx else ""
+        raise PhprngError(st, msg)
+
+
+# ---- host-only helpers -----------------------------------------------------
+
+def phprng_skip_params(width):
+    p, a = _u64(), _u64()
+    _check(lib().phprng_skip_params(width, ctypes.byref(p), ctypes.byref(a)))
+    return p.value, a.value
+
+
+def phprng_check_instance(width, n, e):
+    return lib().phprng_check_instance(width, n, e)
+
+
+def phprng_draw_instances(width, seed, count, e_set=(9, 17), k_lo=0, k_hi=0):
+    es, pes = _u64arr(e_set)
+    n = np.zeros(count, dtype=np.uint64)
+    e = np.zeros(count, dtype=np.uint64)
+    k = np.zeros(count, dtype=np.uint64)
+    _check(lib().phprng_draw_instances(width, seed, count, pes, int(es.size), k_lo, k_hi,
+                                       n.ctypes.data_as(_pu64), e.ctypes.data_as(_pu64), k.ctypes.data_as(_pu64)))
+    return n, e, k
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def make_requests(instances, counts, offsets):
+    """Request array (numpy structured, layout of phprng_request)."""
+    inst = np.asarray(instances, dtype=np.uint32)
+    r = np.zeros(inst.size, dtype=REQUEST_DTYPE)
+    r["instance"] = inst
+    r["count"] = np.asarray(counts, dtype=np.uint64)
+    r["out_offset"] = np.asarray(offsets, dtype=np.uint64)
+    return r
+
+
+class Context:
+    """A phprng_ctx on one device (owns the device instance table)."""
+
+    def __init__(self, device=0, max_instances=1 << 16):
+        h = _vp()
+        _check(lib().phprng_create(ctypes.byref(h), int(device), int(max_instances)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().phprng_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, st):
+        _check(st, self._h)
+
+    def add_instances(self, width, n, e, m0=None, s0=None, k0=None):
+        n, pn = _u64arr(n)
+        e, pe = _u64arr(e)
+        count = n.size
+        args = []
+        keep = []
+        for v in (m0, s0, k0):
+            if v is None:
+                args.append(None)
+            else:
+                a, pa = _u64arr(v)
+                keep.append(a)
+                args.append(pa)
+        ids = np.zeros(count, dtype=np.uint32)
+        self._chk(lib().phprng_add_instances(self._h, count, width, pn, pe, args[0], args[1], args[2],
+                                             ids.ctypes.data_as(_pu32)))
+        return ids
+
+    def seed_instances(self, width, seed, count, e_set=(9, 17), k_lo=0, k_hi=0):
+        es, pes = _u64arr(e_set)
+        ids = np.zeros(count, dtype=np.uint32)
+        self._chk(lib().phprng_seed_instances(self._h, count, width, seed, pes, int(es.size), k_lo, k_hi,
+                                              ids.ctypes.data_as(_pu32)))
+        return ids
+
+    def instance_count(self):
+        return int(lib().phprng_instance_count(self._h))
+
+    def generate(self, requests, out_c32=None, out_c64=None, out_r=None, capacity=None, stream=None,
+                 mode=PHPRNG_MODE_PERSISTENT):
+        """requests: numpy array of REQUEST_DTYPE.  Outputs are device tensors
+        (uint32 / int64 viewed as uint64 / float64) or None."""
+        reqs = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
+        if capacity is None:
+            caps = [t.numel() for t in (out_c32, out_c64, out_r) if t is not None]
+            capacity = min(caps) if caps else 0
+        self._chk(lib().phprng_generate(self._h, reqs.ctypes.data, reqs.size, _dptr(out_c32), _dptr(out_c64),
+                                        _dptr(out_r), int(capacity), _stream_handle(stream), int(mode)))
+
+    def last_kernel_ms(self):
+        v = ctypes.c_double()
+        self._chk(lib().phprng_last_kernel_ms(self._h, ctypes.byref(v)))
+        return v.value
+
+    def timing_reset(self):
+        self._chk(lib().phprng_timing_reset(self._h))
+
+    def timing_read(self):
+        """(total generation-kernel ms, timed calls) since timing_reset."""
+        ms, n = ctypes.c_double(), ctypes.c_uint64()
+        self._chk(lib().phprng_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def jump(self, inst, delta):
+        self._chk(lib().phprng_jump(self._h, int(inst), int(delta)))
+
+    def get_state(self, inst):
+        st = phprng_state()
+        self._chk(lib().phprng_get_state(self._h, int(inst), ctypes.byref(st)))
+        return st.m, st.s, st.c, st.k
+
+    def set_state(self, inst, m, s, k):
+        st = phprng_state(m, s, 0, k)
+        self._chk(lib().phprng_set_state(self._h, int(inst), ctypes.byref(st)))
+
+    def get_params(self, inst):
+        n, e, p, a = _u64(), _u64(), _u64(), _u64()
+        w = ctypes.c_int()
+        self._chk(lib().phprng_get_params(self._h, int(inst), ctypes.byref(n), ctypes.byref(e), ctypes.byref(p),
+                                          ctypes.byref(a), ctypes.byref(w)))
+        return n.value, e.value, p.value, a.value, w.value
+
+    def set_tuning(self, block_threads=0, blocks_per_cu=0, tiles_per_chunk=0, unroll=0):
+        t = phprng_tuning(block_threads, blocks_per_cu, tiles_per_chunk, unroll)
+        self._chk(lib().phprng_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = phprng_tuning()
+        self._chk(lib().phprng_get_tuning(self._h, ctypes.byref(t)))
+        return dict(block_threads=t.block_threads, blocks_per_cu=t.blocks_per_cu,
+                    tiles_per_chunk=t.tiles_per_chunk, unroll=t.unroll)
+
+    def autotune(self, draws=1 << 26):
+        t = phprng_tuning()
+        self._chk(lib().phprng_autotune(self._h, int(draws), ctypes.byref(t)))
+        return dict(block_threads=t.block_threads, blocks_per_cu=t.blocks_per_cu,
+                    tiles_per_chunk=t.tiles_per_chunk, unroll=t.unroll)
+
+    def graph(self, requests, out_c32=None, out_c64=None, out_r=None, capacity=None, stream=None):
+        return Graph(self, requests, out_c32, out_c64, out_r, capacity, stream)
+
+
+class Graph:
+    """Captured repeat draws (phprng_graph_*)."""
+
+    def __init__(self, ctx, requests, out_c32, out_c64, out_r, capacity, stream):
+        reqs = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
+        if capacity is None:
+            caps = [t.numel() for t in (out_c32, out_c64, out_r) if t is not None]
+            capacity = min(caps) if caps else 0
+        h = _vp()
+        _check(lib().phprng_graph_create(ctx.handle, reqs.ctypes.data, reqs.size, _dptr(out_c32), _dptr(out_c64),
+                                         _dptr(out_r), int(capacity), _stream_handle(stream), ctypes.byref(h)),
+               ctx.handle)
+        self._h = h
+        self._ctx = ctx
+
+    def launch(self, stream=None):
+        _check(lib().phprng_graph_launch(self._h, _stream_handle(stream)), self._ctx.handle)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().phprng_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

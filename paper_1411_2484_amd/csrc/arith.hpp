@@ -1,0 +1,243 @@
+// Device arithmetic for gfx950: Montgomery products over 32-bit words (and
+// 64-bit moduli from 32-bit limbs), Mersenne reductions for the skip
+// generators, and the wave-level helpers the kernels use.
+//
+// On gfx950 v_mul_lo_u32, v_mul_hi_u32 and v_mad_u64_u32 issue at the full
+// VALU rate, so a 32 x 32 -> 64 product is one v_mad_u64_u32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "layout.hpp"
+
+namespace phprng {
+namespace dev {
+
+// ---- skip generator mod 2^31 - 1 (eq. (5), width 32) ----------------------
+
+// x y mod (2^31 - 1) for x, y in [1, 2^31 - 2]: fold the 62-bit product.
+__device__ __forceinline__ uint32_t mulmod_p31(uint32_t x, uint32_t y) {
+  uint64_t t = (uint64_t)x * y;
+  uint32_t v = ((uint32_t)t & 0x7fffffffu) + (uint32_t)(t >> 31);
+  uint32_t w = v - 0x7fffffffu;
+  return min(v, w);  // v < 2p, v != p: subtract p once when v > p
+}
+
+__device__ __forceinline__ uint32_t powmod_p31(uint32_t b, uint64_t e) {
+  uint32_t r = 1;
+  while (e) {
+    if (e & 1) r = mulmod_p31(r, b);
+    b = mulmod_p31(b, b);
+    e >>= 1;
+  }
+  return r;
+}
+
+// ---- 32-bit Montgomery arithmetic modulo n in [2^31, 2^32) ----------------
+
+// x y 2^{-32} mod n for x, y < n; ninv = n^{-1} mod 2^32.  The low words of
+// x y and q n cancel exactly, so the result is hi(x y) - hi(q n) (+ n).
+__device__ __forceinline__ uint32_t mont32(uint32_t x, uint32_t y, uint32_t n, uint32_t ninv) {
+  uint64_t t = (uint64_t)x * y;
+  uint32_t q = (uint32_t)t * ninv;
+  uint32_t qh = __umulhi(q, n);
+  uint32_t h = (uint32_t)(t >> 32);
+  uint32_t r = h - qh;
+  return h < qh ? r + n : r;
+}
+
+// v 2^{-32} mod n for v < n 2^32.
+__device__ __forceinline__ uint32_t redc32(uint64_t v, uint32_t n, uint32_t ninv) {
+  uint32_t q = (uint32_t)v * ninv;
+  uint32_t qh = __umulhi(q, n);
+  uint32_t h = (uint32_t)(v >> 32);
+  uint32_t r = h - qh;
+  return h < qh ? r + n : r;
+}
+
+// (m + s) mod n for m, s < n.
+__device__ __forceinline__ uint32_t addmod32(uint32_t m, uint32_t s, uint32_t n) {
+  uint32_t ns = n - s;
+  uint32_t d = m - ns;
+  return m < ns ? d + n : d;
+}
+
+// m^e mod n by left-to-right square-and-multiply on the unconverted message:
+// the chain yields m^e 2^{-32(e-1)}, and one product with kc = 2^{32 e} mod n
+// removes the factor.  EK selects a fixed chain (3, 5, 9, 17) or 0 for a
+// chain over the bits of e.
+template <int EK>
+__device__ __forceinline__ uint32_t encrypt32(uint32_t m, uint32_t n, uint32_t ninv, uint32_t kc, uint64_t e,
+                                              int ebits) {
+  uint32_t x;
+  if constexpr (EK == 3) {
+    x = mont32(m, m, n, ninv);
+    x = mont32(x, m, n, ninv);
+  } else if constexpr (EK == 5) {
+    x = mont32(m, m, n, ninv);
+    x = mont32(x, x, n, ninv);
+    x = mont32(x, m, n, ninv);
+  } else if constexpr (EK == 9) {
+    x = mont32(m, m, n, ninv);
+    x = mont32(x, x, n, ninv);
+    x = mont32(x, x, n, ninv);
+    x = mont32(x, m, n, ninv);
+  } else if constexpr (EK == 17) {
+    x = mont32(m, m, n, ninv);
+    x = mont32(x, x, n, ninv);
+    x = mont32(x, x, n, ninv);
+    x = mont32(x, x, n, ninv);
+    x = mont32(x, m, n, ninv);
+  } else {
+    x = m;
+    for (int b = ebits - 2; b >= 0; --b) {
+      x = mont32(x, x, n, ninv);
+      if ((e >> b) & 1) x = mont32(x, m, n, ninv);
+    }
+  }
+  return mont32(x, kc, n, ninv);
+}
+
+// (c + 1) / (n + 1) correctly rounded, with rcp = RN(1/(n+1)) and den = n + 1
+// (both exact integers below 2^33): q0 = a rcp is within 2 ulp, the remainder
+// a - q0 den is exact, and one correction q0 + r rcp lands within 2^-52 ulp of
+// a/den, which no rounding boundary approaches closer than ulp/2^33.
+__device__ __forceinline__ double uniform32(uint32_t c, double den, double rcp) {
+  double a = (double)(c + 1u);
+  double q0 = a * rcp;
+  double r = __builtin_fma(-q0, den, a);
+  return __builtin_fma(r, rcp, q0);
+}
+
+// ---- 64-bit moduli from 32-bit limbs --------------------------------------
+
+struct W128 {
+  uint64_t lo, hi;
+};
+
+// Full 64 x 64 -> 128 product from four 32 x 32 -> 64 multiply-adds.
+__device__ __forceinline__ W128 mul64w(uint64_t x, uint64_t y) {
+  uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+  uint64_t p00 = (uint64_t)x0 * y0;
+  uint64_t p01 = (uint64_t)x0 * y1 + (p00 >> 32);
+  uint64_t p10 = (uint64_t)x1 * y0 + (uint32_t)p01;
+  uint64_t p11 = (uint64_t)x1 * y1 + (p01 >> 32) + (p10 >> 32);
+  W128 r;
+  r.lo = (p10 << 32) | (uint32_t)p00;
+  r.hi = p11;
+  return r;
+}
+
+// x y 2^{-64} mod n for x, y < n < 2^63; ninv = n^{-1} mod 2^64.
+__device__ __forceinline__ uint64_t mont64(uint64_t x, uint64_t y, uint64_t n, uint64_t ninv) {
+  W128 t = mul64w(x, y);
+  uint64_t q = t.lo * ninv;
+  uint64_t qh = mul64w(q, n).hi;
+  uint64_t r = t.hi - qh;
+  return t.hi < qh ? r + n : r;
+}
+
+// v 2^{-64} mod n for v < n 2^64.
+__device__ __forceinline__ uint64_t redc64(W128 v, uint64_t n, uint64_t ninv) {
+  uint64_t q = v.lo * ninv;
+  uint64_t qh = mul64w(q, n).hi;
+  uint64_t r = v.hi - qh;
+  return v.hi < qh ? r + n : r;
+}
+
+// (m + s) mod n for m, s < n < 2^63 (no overflow of the sum).
+__device__ __forceinline__ uint64_t addmod64(uint64_t m, uint64_t s, uint64_t n) {
+  uint64_t t = m + s;
+  return t >= n ? t - n : t;
+}
+
+template <int EK>
+__device__ __forceinline__ uint64_t encrypt64(uint64_t m, uint64_t n, uint64_t ninv, uint64_t kc, uint64_t e,
+                                              int ebits) {
+  uint64_t x;
+  if constexpr (EK == 3) {
+    x = mont64(m, m, n, ninv);
+    x = mont64(x, m, n, ninv);
+  } else if constexpr (EK == 5) {
+    x = mont64(m, m, n, ninv);
+    x = mont64(x, x, n, ninv);
+    x = mont64(x, m, n, ninv);
+  } else if constexpr (EK == 9) {
+    x = mont64(m, m, n, ninv);
+    x = mont64(x, x, n, ninv);
+    x = mont64(x, x, n, ninv);
+    x = mont64(x, m, n, ninv);
+  } else if constexpr (EK == 17) {
+    x = mont64(m, m, n, ninv);
+    x = mont64(x, x, n, ninv);
+    x = mont64(x, x, n, ninv);
+    x = mont64(x, x, n, ninv);
+    x = mont64(x, m, n, ninv);
+  } else {
+    x = m;
+    for (int b = ebits - 2; b >= 0; --b) {
+      x = mont64(x, x, n, ninv);
+      if ((e >> b) & 1) x = mont64(x, m, n, ninv);
+    }
+  }
+  return mont64(x, kc, n, ninv);
+}
+
+// Skip generator mod 2^61 - 1 (width 64): fold the 122-bit product.
+__device__ __forceinline__ uint64_t mulmod_p61(uint64_t x, uint64_t y) {
+  W128 t = mul64w(x, y);
+  uint64_t lo = t.lo & kP64;
+  uint64_t hi = (t.hi << 3) | (t.lo >> 61);
+  uint64_t v = lo + hi;
+  return v >= kP64 ? v - kP64 : v;
+}
+
+__device__ __forceinline__ uint64_t powmod_p61(uint64_t b, uint64_t e) {
+  uint64_t r = 1;
+  while (e) {
+    if (e & 1) r = mulmod_p61(r, b);
+    b = mulmod_p61(b, b);
+    e >>= 1;
+  }
+  return r;
+}
+
+// binary64(c + 1) / binary64(n + 1), IEEE division (c + 1 < 2^63 converts
+// with one rounding).
+__device__ __forceinline__ double uniform64(uint64_t c, double den) { return (double)(c + 1) / den; }
+
+// ---- wave helpers ---------------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
+  uint32_t lo = __shfl_up((int)(uint32_t)v, d, 64);
+  uint32_t hi = __shfl_up((int)(uint32_t)(v >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = __shfl((int)(uint32_t)v, src, 64);
+  uint32_t hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Orders this wave's LDS accesses across lanes (all lanes of one wave).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace dev
+}  // namespace phprng

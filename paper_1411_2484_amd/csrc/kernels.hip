@@ -1,0 +1,474 @@
+// gfx950 kernels for the Pohlig-Hellman parameter-split generator:
+//   - skip-prefix table segments (eq. (7b) building blocks),
+//   - the request planner (tile/chunk bookkeeping for a batch),
+//   - batched generation (algorithm (9)) as a persistent work-stealing grid
+//     or as one plain grid per request,
+//   - the position advance used by captured repeat draws.
+//
+// Work decomposition.  A tile is 2048 consecutive draws of one instance whose
+// starting state index is a multiple of 2048 within the skip period (the
+// universal table holds the skip-prefix sum U and the skip a^r there).  One
+// wave computes a tile in three passes over its LDS row block:
+//   A. lane l steps the skip generator over its run of 32 draws, keeps the
+//      skips in LDS and sums them;
+//   B. a wave scan of the run sums gives each lane its starting message; the
+//      lane accumulates its run's messages into LDS (eq. (3a));
+//   C. lanes read the messages back in draw order (lane l takes draws
+//      i*64 + l), encrypt (eq. (1)), form R and store both coalesced.
+// A chunk is a run of consecutive tiles of one request; a wave carries the
+// state from one tile to the next within a chunk.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "arith.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace phprng {
+
+constexpr int kRow = kRun + 1;  // padded LDS row (conflict-free for both access orders)
+static_assert((kTilesPerPeriod32 & (kTilesPerPeriod32 - 1)) == 0, "tiles per period is a power of two");
+constexpr int kTileShift32 = 20;
+static_assert((1ull << kTileShift32) == kTilesPerPeriod32, "tile shift");
+
+// ---------------------------------------------------------------------------
+// skip-prefix table segments
+// ---------------------------------------------------------------------------
+
+// Segment i: start skip a^{i*stride} and the sum of the next `stride` skips.
+__global__ void __launch_bounds__(256) table_segments32(uint64_t nseg, uint64_t *seg_sum, uint32_t *seg_start) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nseg) return;
+  uint32_t s = dev::powmod_p31(kA32, i * kTableStride);
+  seg_start[i] = s;
+  uint64_t sum = 0;
+  for (uint64_t j = 0; j < kTableStride; ++j) {
+    s = dev::mulmod_p31(kA32, s);
+    sum += s;
+  }
+  seg_sum[i] = sum;
+}
+
+__global__ void __launch_bounds__(256) table_segments64(uint64_t nseg, uint64_t *seg_lo, uint64_t *seg_hi,
+                                                        uint64_t *seg_start) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nseg) return;
+  uint64_t s = dev::powmod_p61(kA64, i * kTableStride);
+  seg_start[i] = s;
+  uint64_t lo = 0, hi = 0;
+  for (uint64_t j = 0; j < kTableStride; ++j) {
+    s = dev::mulmod_p61(kA64, s);
+    uint64_t t = lo + s;
+    hi += (t < lo) ? 1 : 0;
+    lo = t;
+  }
+  seg_lo[i] = lo;
+  seg_hi[i] = hi;
+}
+
+// ---------------------------------------------------------------------------
+// planner
+// ---------------------------------------------------------------------------
+
+// Global tile index of the tile whose draws include the draw made from state
+// index x.
+__device__ __forceinline__ uint64_t tile_of(uint64_t x, bool w64) {
+  if (w64) return x / kTile;
+  uint64_t q = x / ((uint64_t)kP32 - 1);
+  uint64_t r = x - q * ((uint64_t)kP32 - 1);
+  return (q << kTileShift32) | (r / kTile);
+}
+
+// One block of 1024 threads: per request first tile, tile count and chunk
+// count, then an exclusive scan of chunk counts; resets the work counter.
+__global__ void __launch_bounds__(1024) plan_kernel(const InstRec *inst, ReqRec *req, uint64_t nreq, PlanHdr *hdr,
+                                                    uint32_t tiles_per_chunk) {
+  __shared__ uint64_t part[1024];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t per = (nreq + 1023) / 1024;
+  const uint64_t lo = min((uint64_t)tid * per, nreq), hi = min(lo + per, nreq);
+  uint64_t local = 0;
+  for (uint64_t r = lo; r < hi; ++r) {
+    ReqRec q = req[r];
+    bool w64 = inst[q.inst].width == 64;
+    uint64_t g1 = 0, nt = 0;
+    if (q.count > 0) {
+      g1 = tile_of(q.k, w64);
+      nt = tile_of(q.k + q.count - 1, w64) - g1 + 1;
+    }
+    uint64_t nc = (nt + tiles_per_chunk - 1) / tiles_per_chunk;
+    req[r].g1 = g1;
+    req[r].ntiles = nt;
+    req[r].nchunks = (uint32_t)nc;
+    local += nc;
+  }
+  part[tid] = local;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the 1024 partial sums.
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    uint64_t v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint64_t run = part[tid] - local;
+  for (uint64_t r = lo; r < hi; ++r) {
+    req[r].chunk_base = run;
+    run += req[r].nchunks;
+  }
+  if (tid == 1023) {
+    hdr->total_chunks = part[1023];
+    hdr->counter = 0;
+  }
+}
+
+// Graph replays: every request continues where it ended.
+__global__ void __launch_bounds__(256) advance_kernel(ReqRec *req, uint64_t nreq) {
+  uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nreq) req[r].k += req[r].count;
+}
+
+// ---------------------------------------------------------------------------
+// tiles
+// ---------------------------------------------------------------------------
+
+struct TileOut {
+  uint32_t *c32;
+  uint64_t *c64;
+  double *r;
+};
+
+// Width 32.  (m_t, s_t): state at the tile start index x0 = q (p-1) + j*2048.
+// Valid tile-local draws t in [t_lo, t_hi) are written at base + t.
+template <int UNROLL, int EK>
+__device__ __forceinline__ void tile32_passC(const uint32_t *L, uint32_t lane, uint32_t n, uint32_t ninv, uint32_t kc,
+                                             uint64_t e, int ebits, double den, double rcp, const TileOut &o,
+                                             int64_t base, uint32_t t_lo, uint32_t t_hi) {
+  // draw t = i*64 + lane lives at row t / 32, column t % 32
+  const uint32_t *src = L + (lane >> 5) * kRow + (lane & 31);
+  const bool full = (t_lo == 0) && (t_hi == (uint32_t)kTile);
+  uint32_t *c32 = o.c32 ? o.c32 + base + lane : nullptr;
+  double *rr = o.r ? o.r + base + lane : nullptr;
+  for (int i0 = 0; i0 < kRun; i0 += UNROLL) {
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int i = i0 + u;
+      const uint32_t t = (uint32_t)i * 64u + lane;
+      const uint32_t m = src[i * 2 * kRow];
+      if (full || (t >= t_lo && t < t_hi)) {
+        const uint32_t c = dev::encrypt32<EK>(m, n, ninv, kc, e, ebits);
+        if (c32) c32[i * 64] = c;
+        if (rr) rr[i * 64] = dev::uniform32(c, den, rcp);
+      }
+    }
+  }
+}
+
+template <int UNROLL>
+__device__ void run_chunk32(const GenArgs &A, const InstRec &I, const ReqRec &R, uint64_t chunk, uint32_t *L,
+                            uint32_t lane) {
+  const uint32_t n = (uint32_t)I.n, ninv = (uint32_t)I.ninv, kc = (uint32_t)I.kcorr, r2 = (uint32_t)I.r2;
+  const uint32_t br2 = (uint32_t)I.br2;
+  const uint64_t e = I.e;
+  const int ebits = (int)I.ebits, ekind = (int)I.ekind;
+  const double den = I.den, rcp = I.rcp;
+  const uint64_t pm1 = (uint64_t)kP32 - 1;
+  const uint32_t lane_mul = A.lanemul->m32[lane];
+
+  const uint64_t g_begin = R.g1 + chunk * A.tiles_per_chunk;
+  const uint64_t g_end = min(g_begin + A.tiles_per_chunk, R.g1 + R.ntiles);
+  uint32_t m_t = 0, s_t = 0;
+  bool carried = false;
+  for (uint64_t g = g_begin; g < g_end; ++g) {
+    const uint64_t q = g >> kTileShift32;
+    const uint32_t j = (uint32_t)(g & (kTilesPerPeriod32 - 1));
+    const uint64_t x0 = q * pm1 + (uint64_t)j * kTile;
+    if (!carried || j == 0) {
+      // state at x0 from the universal table (eq. (7)):
+      // m = mbase + q p(p-1)/2 + U(j*2048) mod n,  s = a^{j*2048} mod p
+      const uint64_t u = A.tab.u32[j];
+      s_t = A.tab.s32[j];
+      uint32_t mu = dev::mont32(dev::redc32(u + I.mbase, n, ninv), r2, n, ninv);
+      uint32_t mq = dev::mont32(dev::redc32(q, n, ninv), br2, n, ninv);
+      m_t = dev::addmod32(mu, mq, n);
+    }
+    // ---- pass A: skips of this lane's run, their sum
+    uint32_t *row = L + lane * kRow;
+    uint32_t s = dev::mulmod_p31(s_t, lane_mul);
+    uint64_t sum = 0;
+#pragma unroll 8
+    for (int i = 0; i < kRun; ++i) {
+      s = dev::mulmod_p31(kA32, s);
+      row[i] = s;
+      sum += s;
+    }
+    // ---- pass B: exclusive wave scan of run sums -> run start message
+    uint64_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint64_t v = dev::shfl_up_u64(incl, d);
+      if ((int)lane >= d) incl += v;
+    }
+    uint32_t m = dev::mont32(dev::redc32(incl - sum + m_t, n, ninv), r2, n, ninv);
+#pragma unroll 8
+    for (int i = 0; i < kRun; ++i) {
+      m = dev::addmod32(m, row[i], n);
+      row[i] = m;
+    }
+    // state at the end of the tile (lane 63's last message and skip)
+    m_t = (uint32_t)__shfl((int)m, 63, 64);
+    s_t = (uint32_t)__shfl((int)s, 63, 64);
+    carried = true;
+    dev::wave_lds_sync();
+    // ---- pass C: encrypt in draw order
+    const uint64_t tile_first = x0;  // draw t of this tile comes from state index x0 + t
+    const uint64_t req_end = R.k + R.count;  // one past the last state index used
+    uint32_t t_lo = R.k > tile_first ? (uint32_t)(R.k - tile_first) : 0u;
+    uint64_t hi1 = req_end - tile_first;
+    uint64_t hi2 = pm1 - (uint64_t)j * kTile;
+    uint64_t hi = min(min(hi1, hi2), (uint64_t)kTile);
+    uint32_t t_hi = (uint32_t)hi;
+    const int64_t base = (int64_t)R.out_off + (int64_t)(tile_first - R.k);
+    TileOut o{A.out_c32, nullptr, A.out_r};
+    switch (ekind) {
+      case 9: tile32_passC<UNROLL, 9>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
+      case 17: tile32_passC<UNROLL, 17>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
+      case 3: tile32_passC<UNROLL, 3>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
+      case 5: tile32_passC<UNROLL, 5>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
+      default: tile32_passC<UNROLL, 0>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
+    }
+    dev::wave_lds_sync();
+  }
+}
+
+template <int UNROLL, int EK>
+__device__ __forceinline__ void tile64_passC(const uint64_t *L, uint32_t lane, uint64_t n, uint64_t ninv, uint64_t kc,
+                                             uint64_t e, int ebits, double den, const TileOut &o, int64_t base,
+                                             uint32_t t_lo, uint32_t t_hi) {
+  const uint64_t *src = L + (lane >> 5) * kRow + (lane & 31);
+  const bool full = (t_lo == 0) && (t_hi == (uint32_t)kTile);
+  uint64_t *c64 = o.c64 ? o.c64 + base + lane : nullptr;
+  double *rr = o.r ? o.r + base + lane : nullptr;
+  for (int i0 = 0; i0 < kRun; i0 += UNROLL) {
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int i = i0 + u;
+      const uint32_t t = (uint32_t)i * 64u + lane;
+      const uint64_t m = src[i * 2 * kRow];
+      if (full || (t >= t_lo && t < t_hi)) {
+        const uint64_t c = dev::encrypt64<EK>(m, n, ninv, kc, e, ebits);
+        if (c64) c64[i * 64] = c;
+        if (rr) rr[i * 64] = dev::uniform64(c, den);
+      }
+    }
+  }
+}
+
+template <int UNROLL>
+__device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R, uint64_t chunk, uint64_t *L,
+                            uint32_t lane) {
+  const uint64_t n = I.n, ninv = I.ninv, kc = I.kcorr, r2 = I.r2;
+  const uint64_t e = I.e;
+  const int ebits = (int)I.ebits, ekind = (int)I.ekind;
+  const double den = I.den;
+  const uint64_t lane_mul = A.lanemul->m64[lane];
+
+  const uint64_t g_begin = R.g1 + chunk * A.tiles_per_chunk;
+  const uint64_t g_end = min(g_begin + A.tiles_per_chunk, R.g1 + R.ntiles);
+  uint64_t m_t = 0, s_t = 0;
+  bool carried = false;
+  for (uint64_t g = g_begin; g < g_end; ++g) {
+    const uint64_t x0 = g * kTile;  // width-64 indices never reach the end of the skip period
+    if (!carried) {
+      dev::W128 u;
+      u.lo = A.tab.u64_lo[g];
+      u.hi = A.tab.u64_hi[g];
+      s_t = A.tab.s64[g];
+      uint64_t mu = dev::mont64(dev::redc64(u, n, ninv), r2, n, ninv);
+      m_t = dev::addmod64(mu, I.mbase, n);
+    }
+    uint64_t *row = L + lane * kRow;
+    uint64_t s = dev::mulmod_p61(s_t, lane_mul);
+    uint64_t sum = 0;
+#pragma unroll 4
+    for (int i = 0; i < kRun; ++i) {
+      s = dev::mulmod_p61(kA64, s);
+      row[i] = s;
+      sum = dev::addmod64(sum, s, n);
+    }
+    uint64_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint64_t v = dev::shfl_up_u64(incl, d);
+      if ((int)lane >= d) incl = dev::addmod64(incl, v, n);
+    }
+    // exclusive prefix = incl - sum (mod n)
+    uint64_t pre = incl >= sum ? incl - sum : incl + (n - sum);
+    uint64_t m = dev::addmod64(m_t, pre, n);
+#pragma unroll 4
+    for (int i = 0; i < kRun; ++i) {
+      m = dev::addmod64(m, row[i], n);
+      row[i] = m;
+    }
+    m_t = dev::shfl_u64(m, 63);
+    s_t = dev::shfl_u64(s, 63);
+    carried = true;
+    dev::wave_lds_sync();
+    const uint64_t req_end = R.k + R.count;
+    uint32_t t_lo = R.k > x0 ? (uint32_t)(R.k - x0) : 0u;
+    uint64_t hi = min(req_end - x0, (uint64_t)kTile);
+    uint32_t t_hi = (uint32_t)hi;
+    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.k);
+    TileOut o{nullptr, A.out_c64, A.out_r};
+    switch (ekind) {
+      case 9: tile64_passC<UNROLL, 9>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
+      case 17: tile64_passC<UNROLL, 17>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
+      case 3: tile64_passC<UNROLL, 3>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
+      case 5: tile64_passC<UNROLL, 5>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
+      default: tile64_passC<UNROLL, 0>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
+    }
+    dev::wave_lds_sync();
+  }
+}
+
+// Wave-cooperative search: the request r with chunk_base[r] <= c < chunk_base[r+1]
+// (the last such r when empty requests share a base).
+__device__ __forceinline__ uint64_t find_request(const ReqRec *req, uint64_t nreq, uint64_t c, uint32_t lane) {
+  uint64_t lo = 0, hi = nreq;
+  while (hi - lo > 1) {
+    uint64_t step = (hi - lo + 63) / 64;
+    uint64_t idx = lo + (uint64_t)lane * step;
+    bool le = idx < hi && req[idx].chunk_base <= c;
+    uint64_t mask = __ballot(le);
+    uint64_t k = (uint64_t)__popcll(mask);
+    lo = lo + (k - 1) * step;
+    hi = min(lo + step, hi);
+  }
+  return lo;
+}
+
+template <bool HAS64>
+struct WaveLds {
+  using T = typename std::conditional<HAS64, uint64_t, uint32_t>::type;
+  static constexpr int kWords = 64 * kRow;
+};
+
+template <int BLOCK, int UNROLL, bool HAS64>
+__global__ void __launch_bounds__(BLOCK) gen_persistent(GenArgs A) {
+  using LT = typename WaveLds<HAS64>::T;
+  __shared__ LT lds[BLOCK / 64][WaveLds<HAS64>::kWords];
+  const uint32_t lane = dev::lane_id();
+  const uint32_t wave = threadIdx.x / 64;
+  LT *L = lds[wave];
+  const uint64_t total = dev::uniform_u64(A.hdr->total_chunks);
+  for (;;) {
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(&A.hdr->counter, 1u);
+    c = dev::uniform_u32((uint32_t)__shfl((int)c, 0, 64));
+    if (c >= total) break;
+    const uint64_t r = dev::uniform_u64(find_request(A.req, A.nreq, c, lane));
+    const ReqRec R = A.req[r];
+    const InstRec &I = A.inst[R.inst];
+    const uint64_t chunk = c - R.chunk_base;
+    if (HAS64 && I.width == 64) {
+      run_chunk64<UNROLL>(A, I, R, chunk, reinterpret_cast<uint64_t *>(L), lane);
+    } else {
+      run_chunk32<UNROLL>(A, I, R, chunk, reinterpret_cast<uint32_t *>(L), lane);
+    }
+  }
+}
+
+// One grid per request: block b (one wave) takes chunk b of request `r`.
+template <int UNROLL, bool HAS64>
+__global__ void __launch_bounds__(64) gen_plain(GenArgs A, uint64_t r) {
+  using LT = typename WaveLds<HAS64>::T;
+  __shared__ LT lds[WaveLds<HAS64>::kWords];
+  const uint32_t lane = dev::lane_id();
+  const ReqRec R = A.req[r];
+  if ((uint64_t)blockIdx.x >= R.nchunks) return;
+  const InstRec &I = A.inst[R.inst];
+  if (HAS64 && I.width == 64) {
+    run_chunk64<UNROLL>(A, I, R, blockIdx.x, reinterpret_cast<uint64_t *>(lds), lane);
+  } else {
+    run_chunk32<UNROLL>(A, I, R, blockIdx.x, reinterpret_cast<uint32_t *>(lds), lane);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_table_segments32(uint64_t nseg, uint64_t *seg_sum, uint32_t *seg_start, hipStream_t st) {
+  unsigned blocks = (unsigned)((nseg + 255) / 256);
+  hipLaunchKernelGGL(table_segments32, dim3(blocks), dim3(256), 0, st, nseg, seg_sum, seg_start);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_segments64(uint64_t nseg, uint64_t *seg_lo, uint64_t *seg_hi, uint64_t *seg_start,
+                                   hipStream_t st) {
+  unsigned blocks = (unsigned)((nseg + 255) / 256);
+  hipLaunchKernelGGL(table_segments64, dim3(blocks), dim3(256), 0, st, nseg, seg_lo, seg_hi, seg_start);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan(const InstRec *inst, ReqRec *req, uint64_t nreq, PlanHdr *hdr, uint32_t tiles_per_chunk,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, inst, req, nreq, hdr, tiles_per_chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(ReqRec *req, uint64_t nreq, hipStream_t st) {
+  if (nreq == 0) return hipSuccess;
+  unsigned blocks = (unsigned)((nreq + 255) / 256);
+  hipLaunchKernelGGL(advance_kernel, dim3(blocks), dim3(256), 0, st, req, nreq);
+  return hipGetLastError();
+}
+
+template <int BLOCK, int UNROLL, bool HAS64>
+static void launch_p(const GenArgs &A, unsigned grid, hipStream_t st) {
+  hipLaunchKernelGGL((gen_persistent<BLOCK, UNROLL, HAS64>), dim3(grid), dim3(BLOCK), 0, st, A);
+}
+
+template <int BLOCK, bool HAS64>
+static bool launch_pu(const GenArgs &A, unsigned grid, int unroll, hipStream_t st) {
+  switch (unroll) {
+    case 1: launch_p<BLOCK, 1, HAS64>(A, grid, st); return true;
+    case 2: launch_p<BLOCK, 2, HAS64>(A, grid, st); return true;
+    case 4: launch_p<BLOCK, 4, HAS64>(A, grid, st); return true;
+    default: return false;
+  }
+}
+
+template <bool HAS64>
+static bool launch_pb(const GenArgs &A, unsigned grid, int block, int unroll, hipStream_t st) {
+  switch (block) {
+    case 64: return launch_pu<64, HAS64>(A, grid, unroll, st);
+    case 128: return launch_pu<128, HAS64>(A, grid, unroll, st);
+    case 256: return launch_pu<256, HAS64>(A, grid, unroll, st);
+    case 512: return launch_pu<512, HAS64>(A, grid, unroll, st);
+    default: return false;
+  }
+}
+
+hipError_t launch_persistent(const GenArgs &A, unsigned grid, int block, int unroll, bool has64, hipStream_t st) {
+  bool ok = has64 ? launch_pb<true>(A, grid, block, unroll, st) : launch_pb<false>(A, grid, block, unroll, st);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_plain(const GenArgs &A, uint64_t r, unsigned grid, int unroll, bool has64, hipStream_t st) {
+  if (grid == 0) return hipSuccess;
+  if (has64) {
+    if (unroll == 4) hipLaunchKernelGGL((gen_plain<4, true>), dim3(grid), dim3(64), 0, st, A, r);
+    else if (unroll == 2) hipLaunchKernelGGL((gen_plain<2, true>), dim3(grid), dim3(64), 0, st, A, r);
+    else hipLaunchKernelGGL((gen_plain<1, true>), dim3(grid), dim3(64), 0, st, A, r);
+  } else {
+    if (unroll == 4) hipLaunchKernelGGL((gen_plain<4, false>), dim3(grid), dim3(64), 0, st, A, r);
+    else if (unroll == 2) hipLaunchKernelGGL((gen_plain<2, false>), dim3(grid), dim3(64), 0, st, A, r);
+    else hipLaunchKernelGGL((gen_plain<1, false>), dim3(grid), dim3(64), 0, st, A, r);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace phprng

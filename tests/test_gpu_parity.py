@@ -1,0 +1,419 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle,
+element by element, bit-exact for ciphertexts and uniforms.
+
+Sizes span several 2048-draw tiles with ragged heads and tails; the
+full-size workloads are checked on seeded samples the oracle computes one
+by one.  Every case runs in one process on cuda:0."""
+
+import math
+import random
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import alloc_outputs, compare_request, oracle_draws, to_host
+
+pytestmark = pytest.mark.gpu
+
+SEED0 = 0x14112484
+
+
+@pytest.fixture(scope="module")
+def ph():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1411_2484_amd as ph
+    ph.lib()
+    return ph
+
+
+@pytest.fixture(scope="module")
+def ctx(ph):
+    c = ph.Context(0, max_instances=1 << 17)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def tabs(tab32, tab64):
+    return {32: tab32, 64: tab64}
+
+
+def _run(ph, ctx, specs, mode=0, want=(True, True, True), gap=0, shuffle_seed=None):
+    """specs: list of (inst_id, count).  Returns host outputs and offsets."""
+    counts = [c for _, c in specs]
+    order = list(range(len(specs)))
+    if shuffle_seed is not None:
+        random.Random(shuffle_seed).shuffle(order)
+    offs = [0] * len(specs)
+    cur = 0
+    for i in order:
+        offs[i] = cur
+        cur += counts[i] + gap
+    total = cur
+    c32, c64, r = alloc_outputs(total, *want)
+    reqs = ph.make_requests([s[0] for s in specs], counts, offs)
+    ctx.generate(reqs, c32, c64, r, capacity=max(total, 1), mode=mode)
+    return to_host(c32, c64, r), offs
+
+
+def _check(orc, tabs, ctx, specs, starts, host, offs, label):
+    hc32, hc64, hr = host
+    for (iid, count), k0, off in zip(specs, starts, offs):
+        n, e, p, a, w = ctx.get_params(iid)
+        want_c, want_r, _ = oracle_draws(orc, tabs, w, n, e, k0, count)
+        got_c = hc32 if w == 32 else hc64
+        compare_request(got_c, hr, off, count, want_c, want_r, "%s inst %d (n=%d e=%d k=%d)" % (label, iid, n, e, k0))
+
+
+def _positions(ctx, ids):
+    return [ctx.get_state(i)[3] for i in ids]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_single_instance_million_draws(ph, ctx, orc, tabs, mode):
+    """One seeded 32-bit instance, 10^6 draws from position 0."""
+    ids = ctx.seed_instances(32, SEED0 + mode, 1, (9, 17), 0, 0)
+    specs = [(int(ids[0]), 10 ** 6)]
+    starts = _positions(ctx, ids)
+    host, offs = _run(ph, ctx, specs, mode=mode)
+    _check(orc, tabs, ctx, specs, starts, host, offs, "A mode%d" % mode)
+    assert ctx.get_state(int(ids[0]))[3] == 10 ** 6
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ragged_requests_random_starts(ph, ctx, orc, tabs, mode):
+    rng = random.Random(100 + mode)
+    ids = ctx.seed_instances(32, SEED0 + 10 + mode, 40, (9, 17), 0, 1 << 40)
+    counts = [rng.choice([1, 2, 63, 64, 65, 2047, 2048, 2049, 4096, 6143]) if i % 3 == 0 else rng.randrange(1, 9000)
+              for i in range(40)]
+    specs = list(zip([int(x) for x in ids], counts))
+    starts = _positions(ctx, ids)
+    host, offs = _run(ph, ctx, specs, mode=mode, gap=5, shuffle_seed=mode)
+    _check(orc, tabs, ctx, specs, starts, host, offs, "ragged")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_requests_across_the_skip_period_boundary(ph, ctx, orc, tabs, mode):
+    p = 2147483647
+    n_arr, e_arr, _ = orc.seed(32, SEED0 + 20 + mode, 8, (9, 17))
+    ks = [(p - 1) - 1, (p - 1) - 3000, 5 * (p - 1) - 2047, 7 * (p - 1), 3 * (p - 1) - 2046, (p - 1) + 1,
+          11 * (p - 1) - 4095, 2 * (p - 1) - 2048]
+    ids = ctx.add_instances(32, n_arr, e_arr, k0=ks)
+    specs = [(int(i), 6000) for i in ids]
+    host, offs = _run(ph, ctx, specs, mode=mode)
+    _check(orc, tabs, ctx, specs, ks, host, offs, "period")
+
+
+def test_same_instance_in_several_requests(ph, ctx, orc, tabs):
+    ids = ctx.seed_instances(32, SEED0 + 30, 2, (9, 17), 0, 1 << 33)
+    a, b = int(ids[0]), int(ids[1])
+    k_a, k_b = _positions(ctx, ids)
+    specs = [(a, 1000), (b, 3000), (a, 5000), (a, 1), (b, 2048)]
+    host, offs = _run(ph, ctx, specs)
+    starts = [k_a, k_b, k_a + 1000, k_a + 6000, k_b + 3000]
+    _check(orc, tabs, ctx, specs, starts, host, offs, "continuation")
+    assert _positions(ctx, [a, b]) == [k_a + 6001, k_b + 5048]
+
+
+def test_exponents_fixed_and_generic_chains(ph, ctx, orc, tabs):
+    rng = random.Random(7)
+    ns, es = [], []
+    wanted = [3, 5, 7, 9, 11, 13, 17, 65537, 19, 23]
+    for ew in wanted:
+        while True:
+            n = rng.randrange(1 << 31, 1 << 32) | 1
+            if orc.check_instance(32, n, ew) == 0:
+                break
+        ns.append(n)
+        es.append(ew)
+    # a large exponent (generic chain over 31 bits)
+    n = 4294967087
+    e_big = next(x for x in range(2 ** 31 + 1, 2 ** 31 + 1000, 2) if math.gcd(x, n - 1) == 1)
+    ns.append(n)
+    es.append(e_big)
+    ks = [rng.randrange(0, 1 << 40) for _ in ns]
+    ids = ctx.add_instances(32, ns, es, k0=ks)
+    specs = [(int(i), 5000) for i in ids]
+    host, offs = _run(ph, ctx, specs)
+    _check(orc, tabs, ctx, specs, ks, host, offs, "exponents")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_64bit_instances(ph, ctx, orc, tabs, mode):
+    rng = random.Random(200 + mode)
+    n_arr, e_arr, k_arr = orc.seed(64, SEED0 + 40 + mode, 12, (3, 5, 9, 17, 7), 0, 1 << 28)
+    ids = ctx.add_instances(64, n_arr, e_arr, k0=k_arr)
+    counts = [rng.choice([1, 2047, 2049, 30000, rng.randrange(1, 20000)]) for _ in ids]
+    specs = list(zip([int(i) for i in ids], counts))
+    host, offs = _run(ph, ctx, specs, mode=mode, want=(False, True, True), gap=3)
+    _check(orc, tabs, ctx, specs, [int(k) for k in k_arr], host, offs, "w64")
+
+
+def test_mixed_width_batch(ph, ctx, orc, tabs):
+    rng = random.Random(300)
+    n64, e64, k64 = orc.seed(64, SEED0 + 50, 10, (9, 17), 0, 1 << 27)
+    n32, e32, k32 = orc.seed(32, SEED0 + 51, 10, (9, 17), 0, 1 << 40)
+    i64 = ctx.add_instances(64, n64, e64, k0=k64)
+    i32 = ctx.add_instances(32, n32, e32, k0=k32)
+    specs, starts = [], []
+    for a, b, ka, kb in zip(i64, i32, k64, k32):
+        specs += [(int(b), rng.randrange(1, 12000)), (int(a), rng.randrange(1, 12000))]
+        starts += [int(kb), int(ka)]
+    host, offs = _run(ph, ctx, specs, shuffle_seed=3)
+    _check(orc, tabs, ctx, specs, starts, host, offs, "mixed")
+
+
+@pytest.mark.parametrize("want", [(True, False, False), (False, False, True), (False, True, False)])
+def test_optional_outputs(ph, ctx, orc, tabs, want):
+    n32, e32, k32 = orc.seed(32, SEED0 + 60, 3, (9, 17), 0, 1 << 40)
+    n64, e64, k64 = orc.seed(64, SEED0 + 61, 3, (9, 17), 0, 1 << 20)
+    ids = list(ctx.add_instances(32, n32, e32, k0=k32)) + list(ctx.add_instances(64, n64, e64, k0=k64))
+    starts = [int(k) for k in k32] + [int(k) for k in k64]
+    specs = [(int(i), 3000) for i in ids]
+    (hc32, hc64, hr), offs = _run(ph, ctx, specs, want=want)
+    for (iid, count), k0, off in zip(specs, starts, offs):
+        n, e, p, a, w = ctx.get_params(iid)
+        wc, wr, _ = oracle_draws(orc, tabs, w, n, e, k0, count)
+        gc = hc32 if w == 32 else hc64
+        compare_request(gc, hr, off, count, wc, wr, "optional")
+    # an array that was not requested stays untouched (width-32 c in c64 etc.)
+    if hc64 is not None:
+        assert (hc64[offs[0]:offs[0] + 3000] == np.uint64(2 ** 64 - 1)).all()
+
+
+def test_start_from_supplied_m0_s0(ph, ctx, orc, tabs):
+    rng = random.Random(400)
+    n32, e32, _ = orc.seed(32, SEED0 + 70, 6, (9, 17))
+    p32, a32 = orc.lcg_params(32)
+    m0 = [rng.randrange(int(n)) for n in n32]
+    s0 = [rng.randrange(1, p32) for _ in n32]
+    k0 = [rng.randrange(0, 300000) for _ in n32]
+    ids = ctx.add_instances(32, n32, e32, m0=m0, s0=s0, k0=k0)
+    n64, e64, _ = orc.seed(64, SEED0 + 71, 4, (9, 17))
+    p64, a64 = orc.lcg_params(64)
+    t64 = [rng.randrange(0, 1 << 24) for _ in n64]
+    s064 = [pow(a64, t, p64) for t in t64]
+    m064 = [rng.randrange(int(n)) for n in n64]
+    k064 = [rng.randrange(0, 100000) for _ in n64]
+    ids64 = ctx.add_instances(64, n64, e64, m0=m064, s0=s064, k0=k064)
+    specs = [(int(i), 4000) for i in list(ids) + list(ids64)]
+    (hc32, hc64, hr), offs = _run(ph, ctx, specs)
+    allp = list(zip(n32, e32, m0, s0, k0)) + list(zip(n64, e64, m064, s064, k064))
+    for (iid, count), (n, e, mm, ss, kk), off in zip(specs, allp, offs):
+        w = 32 if int(n) < 2 ** 32 else 64
+        wc, wr, _ = oracle_draws(orc, tabs, w, int(n), int(e), kk, count, m0=mm, s0=ss)
+        compare_request(hc32 if w == 32 else hc64, hr, off, count, wc, wr, "m0s0")
+        # get_state reports the supplied start, advanced by the draws
+        st = ctx.get_state(iid)
+        assert st[3] == kk + count
+
+
+def test_state_get_set_and_jumps(ph, ctx, orc, tabs):
+    rng = random.Random(500)
+    n32, e32, k32 = orc.seed(32, SEED0 + 80, 4, (9, 17), 0, 1 << 40)
+    ids = ctx.add_instances(32, n32, e32, k0=k32)
+    p, a = orc.lcg_params(32)
+    for iid, n, e, k in zip(ids, n32, e32, k32):
+        iid, n, e, k = int(iid), int(n), int(e), int(k)
+        # state reported at the start position equals eq. (7)
+        m, s, c, kk = ctx.get_state(iid)
+        assert kk == k
+        assert (m, s) == orc.position(tabs[32], p, a, n, 0, 1, k)
+        assert c == orc.encrypt(m, e, n)
+        # forward and backward jumps
+        d = rng.randrange(1, 10 ** 6)
+        ctx.jump(iid, d)
+        assert ctx.get_state(iid)[:2] == orc.position(tabs[32], p, a, n, 0, 1, k + d)
+        ctx.jump(iid, -d - 5)
+        assert ctx.get_state(iid)[:2] == orc.position(tabs[32], p, a, n, 0, 1, k - 5)
+        # restore an arbitrary state, then draw: equals the oracle stepping from it
+        m1, s1, k1 = rng.randrange(n), rng.randrange(1, p), rng.randrange(0, 1 << 50)
+        ctx.set_state(iid, m1, s1, k1)
+        assert ctx.get_state(iid)[:2] == (m1, s1) and ctx.get_state(iid)[3] == k1
+        (hc32, _, hr), offs = _run(ph, ctx, [(iid, 7000)])
+        cc, rr, (m2, s2) = oracle_draws(orc, tabs, 32, n, e, 0, 7000, m0=m1, s0=s1)
+        compare_request(hc32, hr, 0, 7000, cc, rr, "restored")
+        st = ctx.get_state(iid)
+        assert (st[0], st[1], st[3]) == (m2, s2, k1 + 7000)
+    # 64-bit: restore to a state with a small skip logarithm
+    n64, e64, _ = orc.seed(64, SEED0 + 81, 2, (9, 17))
+    ids64 = ctx.add_instances(64, n64, e64)
+    p64, a64 = orc.lcg_params(64)
+    for iid, n, e in zip(ids64, n64, e64):
+        iid, n, e = int(iid), int(n), int(e)
+        t = rng.randrange(0, 1 << 26)
+        m1, s1 = rng.randrange(n), pow(a64, t, p64)
+        ctx.set_state(iid, m1, s1, 12345)
+        (_, hc64, hr), _ = _run(ph, ctx, [(iid, 3000)])
+        cc, rr, _ = oracle_draws(orc, tabs, 64, n, e, 0, 3000, m0=m1, s0=s1)
+        compare_request(hc64, hr, 0, 3000, cc, rr, "restored64")
+        with pytest.raises(ph.PhprngError):
+            ctx.set_state(iid, m1, rng.randrange(2, p64), 0)  # skip log beyond the 64-bit index range
+
+
+def test_graph_replays_continue_streams(ph, ctx, orc, tabs):
+    import torch
+    n32, e32, k32 = orc.seed(32, SEED0 + 90, 6, (9, 17), 0, 1 << 40)
+    n64, e64, k64 = orc.seed(64, SEED0 + 91, 2, (9, 17), 0, 1 << 22)
+    ids = list(ctx.add_instances(32, n32, e32, k0=k32)) + list(ctx.add_instances(64, n64, e64, k0=k64))
+    starts = [int(k) for k in k32] + [int(k) for k in k64]
+    count = 5000
+    offs = [i * count for i in range(len(ids))]
+    total = count * len(ids)
+    c32, c64, r = alloc_outputs(total)
+    reqs = ph.make_requests(ids, [count] * len(ids), offs)
+    g = ctx.graph(reqs, c32, c64, r)
+    scratch = torch.zeros(1 << 20, device="cuda:0")
+    for rep in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        hc32, hc64, hr = to_host(c32, c64, r)
+        for iid, k0, off in zip(ids, starts, offs):
+            n, e, p, a, w = ctx.get_params(int(iid))
+            wc, wr, _ = oracle_draws(orc, tabs, w, n, e, k0 + rep * count, count)
+            compare_request(hc32 if w == 32 else hc64, hr, off, count, wc, wr, "graph rep %d" % rep)
+            assert ctx.get_state(int(iid))[3] == k0 + (rep + 1) * count
+        scratch.add_(1.0)  # eager work between replays
+        torch.cuda.synchronize()
+    g.close()
+
+
+def test_tuning_does_not_change_results(ph, ctx):
+    import torch
+    ids = ctx.seed_instances(32, SEED0 + 100, 16, (9, 17, 5), 0, 1 << 40)
+    ids64 = ctx.seed_instances(64, SEED0 + 101, 4, (9, 17, 3), 0, 1 << 24)
+    allid = [int(i) for i in ids] + [int(i) for i in ids64]
+    saved = [ctx.get_state(i) for i in allid]
+    counts = [(i * 7919) % 20000 + 1 for i in range(len(allid))]
+    offs = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    total = int(sum(counts))
+    ref = None
+    orig = ctx.get_tuning()
+    for bt, bpc, tpc, un in [(256, 4, 4, 2), (64, 8, 1, 1), (512, 1, 16, 4), (128, 2, 64, 2)]:
+        for i, st in zip(allid, saved):
+            ctx.set_state(i, st[0], st[1], st[3])
+        ctx.set_tuning(bt, bpc, tpc, un)
+        outs = alloc_outputs(total)
+        ctx.generate(ph.make_requests(allid, counts, offs), *outs)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = outs
+        else:
+            for x, y in zip(ref, outs):
+                assert torch.equal(x, y)
+    ctx.set_tuning(**orig)
+
+
+def test_rejected_calls_change_nothing(ph, ctx):
+    import torch
+    ids = ctx.seed_instances(32, SEED0 + 110, 2, (9, 17), 0, 1 << 40)
+    before = [ctx.get_state(int(i)) for i in ids]
+    c32, c64, r = alloc_outputs(100)
+    with pytest.raises(ph.PhprngError) as ex:
+        ctx.generate(ph.make_requests([int(ids[0]), int(ids[1])], [50, 60], [0, 50]), c32, c64, r, capacity=100)
+    assert ex.value.status == ph.PHPRNG_E_RANGE
+    with pytest.raises(ph.PhprngError) as ex:
+        ctx.generate(ph.make_requests([int(ids[0]), 10 ** 7], [5, 5], [0, 5]), c32, c64, r, capacity=100)
+    assert ex.value.status == ph.PHPRNG_E_INVALID
+    assert [ctx.get_state(int(i)) for i in ids] == before
+    torch.cuda.synchronize()
+    assert (c32.cpu() == -1).all()
+    with pytest.raises(ph.PhprngError):
+        ctx.add_instances(32, [4294967087, 4294967089], [9, 9])  # second modulus composite
+    with pytest.raises(ph.PhprngError):
+        ctx.jump(int(ids[0]), -(before[0][3] + 1))
+    assert [ctx.get_state(int(i)) for i in ids] == before
+
+
+def test_full_size_plain_batch_sampled(ph, orc, tabs):
+    """4096 seeded 32-bit instances x 2^18 draws from position 0, persistent
+    and one launch per instance: both bit-identical, and 4000 sampled draws
+    equal the oracle computed one by one."""
+    import torch
+    ctx = ph.Context(0, max_instances=4096)
+    ids = ctx.seed_instances(32, SEED0 + 1, 4096, (9, 17), 0, 0)
+    per = 1 << 18
+    total = 4096 * per
+    reqs = ph.make_requests(ids, [per] * 4096, np.arange(4096, dtype=np.uint64) * per)
+    c32, _, r = alloc_outputs(total, True, False, True)
+    ctx.generate(reqs, c32, None, r)
+    for i in ids:
+        ctx.jump(int(i), -per)
+    c32b, _, rb = alloc_outputs(total, True, False, True)
+    ctx.generate(reqs, c32b, None, rb, mode=ph.PHPRNG_MODE_PLAIN)
+    torch.cuda.synchronize()
+    assert torch.equal(c32, c32b) and torch.equal(r, rb)
+    del c32b, rb
+    rng = random.Random(600)
+    samples = [(rng.randrange(4096), rng.randrange(per)) for _ in range(4000)]
+    idx = torch.tensor([i * per + t for i, t in samples], device="cuda:0")
+    gc = c32[idx].cpu().numpy().view(np.uint32)
+    gr = r[idx].cpu().numpy()
+    p, a = orc.lcg_params(32)
+    for (i, t), x, y in zip(samples, gc, gr):
+        n, e, _, _, _ = ctx.get_params(int(ids[i]))
+        m, s = orc.position(tabs[32], p, a, n, 0, 1, t)
+        wc, wr, _, _ = orc.generate(p, a, n, e, m, s, 1)
+        assert int(x) == int(wc[0]) and float(y) == float(wr[0]), (i, t)
+    ctx.close()
+
+
+def test_log_uniform_batch_one_percent_sample(ph, orc, tabs):
+    """65,536 32-bit instances, log-uniform lengths in [2^4, 2^12], random
+    starts in [0, 2^40), one persistent launch; a seeded 1% of the streams
+    is compared in full."""
+    import torch
+    ctx = ph.Context(0, max_instances=1 << 16)
+    nin = 1 << 16
+    n, e, k = orc.seed(32, SEED0 + 2, nin, (9, 17), 0, 1 << 40)
+    ids = ctx.add_instances(32, n, e, k0=k)
+    rng = np.random.default_rng(SEED0 + 2)
+    lens = np.floor(2.0 ** (4 + 8 * rng.random(nin))).astype(np.uint64)
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+    total = int(lens.sum())
+    c32, _, r = alloc_outputs(total, True, False, True)
+    ctx.generate(ph.make_requests(ids, lens, offs), c32, None, r)
+    hc32, _, hr = to_host(c32, None, r)
+    sample = rng.choice(nin, size=nin // 100, replace=False)
+    p, a = orc.lcg_params(32)
+    ms, ss = [], []
+    for i in sample:
+        m, s = orc.position(tabs[32], p, a, int(n[i]), 0, 1, int(k[i]))
+        ms.append(m)
+        ss.append(s)
+    wc, wr, _, _, woff = orc.generate_many(p, a, n[sample], e[sample], np.array(ms, dtype=np.uint64),
+                                           np.array(ss, dtype=np.uint64), lens[sample])
+    for j, i in enumerate(sample):
+        o, L, wo = int(offs[i]), int(lens[i]), int(woff[j])
+        compare_request(hc32, hr, o, L, wc[wo:wo + L], wr[wo:wo + L], "logu %d" % i)
+    ctx.close()
+
+
+def test_mixed_full_size_sampled(ph, orc, tabs):
+    """1024 64-bit + 1024 32-bit instances x 2^20 draws from position 0 in one
+    persistent launch; 3000 sampled draws against the oracle."""
+    import torch
+    ctx = ph.Context(0, max_instances=2048)
+    i64 = ctx.seed_instances(64, SEED0 + 3, 1024, (9, 17), 0, 0)
+    i32 = ctx.seed_instances(32, SEED0 + 4, 1024, (9, 17), 0, 0)
+    per = 1 << 20
+    ids = np.concatenate([i64, i32])
+    offs = np.arange(2048, dtype=np.uint64) * per
+    total = 2048 * per
+    c32, c64, r = alloc_outputs(total)
+    ctx.generate(ph.make_requests(ids, [per] * 2048, offs), c32, c64, r)
+    torch.cuda.synchronize()
+    rng = random.Random(700)
+    samples = [(rng.randrange(2048), rng.randrange(per)) for _ in range(3000)]
+    idx = torch.tensor([i * per + t for i, t in samples], device="cuda:0")
+    g32 = c32[idx].cpu().numpy().view(np.uint32)
+    g64 = c64[idx].cpu().numpy().view(np.uint64)
+    gr = r[idx].cpu().numpy()
+    for (i, t), x32, x64, y in zip(samples, g32, g64, gr):
+        n, e, p, a, w = ctx.get_params(int(ids[i]))
+        m, s = orc.position(tabs[w], p, a, n, 0, 1, t)
+        wc, wr, _, _ = orc.generate(p, a, n, e, m, s, 1)
+        got = int(x32) if w == 32 else int(x64)
+        assert got == int(wc[0]) and float(y) == float(wr[0]), (i, t, w)
+    ctx.close()
