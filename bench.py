@@ -4,7 +4,7 @@
 Headline workload: 4096 seeded 32-bit instances (distinct admissible primes
 n in [2^31, 2^32), e drawn from {9, 17} coprime to n - 1, start position 0),
 2^18 draws each per step -- 1,073,741,824 uniforms per step written to HBM as
-u32 ciphertexts plus FP64 uniforms.  A step is one batched persistent
+FP64 uniforms (a variant also writes the u32 ciphertexts).  A step is one batched persistent
 launch over all 4096 streams; each step continues every stream where the
 previous one ended and overwrites the same output arrays.  The same
 workload is also timed in the plain form (one launch per instance), and the
@@ -48,28 +48,26 @@ def log(msg):
 
 def cpu_baseline(e_arr, n_arr, target_s=12.0):
     """The oracle on the host's cores over a bounded sample of the headline
-    workload (the first M instances, 2^18 draws each from position 0)."""
+    workload: batches of 256 of the instances, 2^18 draws each from position
+    0, cycling over the 4096 instances until about target_s seconds."""
     import oracle
     nthreads = min(os.cpu_count() or 1, 16)
     p, a = oracle.lcg_params(32)
-    # calibrate on 8 instances
+    done_inst = 0
     t0 = time.perf_counter()
-    oracle.generate_many(p, a, n_arr[:8], e_arr[:8], 0, 1, np.full(8, PER, dtype=np.uint64), nthreads=min(8, nthreads))
-    dt = time.perf_counter() - t0
-    per_inst_thread_s = dt * min(8, nthreads) / 8
-    m = int(max(nthreads, min(N_INST, target_s * nthreads / max(per_inst_thread_s, 1e-9))))
-    m = (m // nthreads) * nthreads or nthreads
-    done = 0
-    t0 = time.perf_counter()
-    while done < m:
-        b = min(256, m - done)
-        oracle.generate_many(p, a, n_arr[done:done + b], e_arr[done:done + b], 0, 1,
-                             np.full(b, PER, dtype=np.uint64), want_c=True, want_r=True, nthreads=nthreads)
-        done += b
-    el = time.perf_counter() - t0
-    draws = m * PER
+    while True:
+        lo = done_inst % N_INST
+        b = min(256, N_INST - lo)
+        oracle.generate_many(p, a, n_arr[lo:lo + b], e_arr[lo:lo + b], 0, 1, np.full(b, PER, dtype=np.uint64),
+                             want_c=True, want_r=True, nthreads=nthreads)
+        done_inst += b
+        el = time.perf_counter() - t0
+        if el >= target_s:
+            break
+    draws = done_inst * PER
     return {"value": draws / el / 1e9, "unit": "Guniforms/s", "cores": nthreads, "kind": "oracle",
-            "sample": "%d of the 4096 instances x 2^18 draws from position 0 (%d draws), %.1f s" % (m, draws, el)}
+            "sample": "%d instance-streams of the headline workload (2^18 draws each from position 0, "
+                      "%d draws) in %.1f s" % (done_inst, draws, el)}
 
 
 def main():
@@ -80,7 +78,10 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-ciphertexts", action="store_true", help="skip the u32 + f64 output variant")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="first run one device copy of this many GiB (known-size kernel for traffic counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -102,54 +103,63 @@ def main():
     n_arr = np.array([p[0] for p in params], dtype=np.uint64)
     e_arr = np.array([p[1] for p in params], dtype=np.uint64)
     total = N_INST * PER
-    c32 = torch.empty(total, dtype=torch.int32, device=dev)
     r = torch.empty(total, dtype=torch.float64, device=dev)
     reqs = ph.make_requests(ids, [PER] * N_INST, np.arange(N_INST, dtype=np.uint64) * PER)
+    if args.calib_copy_gib > 0:
+        nel = int(args.calib_copy_gib * (1 << 30) / 8)
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (nel * 8, nel * 8))
+        del src, dst
     if args.autotune:
         log("autotune: %s" % ctx.autotune(1 << 27))
     tuning = ctx.get_tuning()
 
-    def step(mode=ph.PHPRNG_MODE_PERSISTENT):
-        ctx.generate(reqs, c32, None, r, capacity=total, mode=mode)
+    def measure(steps, warmup, mode, c32=None):
+        """Time `steps` generation calls; returns (wall ms/step, kernel ms/call)."""
+        for _ in range(warmup):
+            ctx.generate(reqs, c32, None, r, capacity=total, mode=mode)
+        torch.cuda.synchronize()
+        ctx.timing_reset()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.generate(reqs, c32, None, r, capacity=total, mode=mode)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms, kcalls = ctx.timing_read()
+        return wall * 1e3 / steps, kms / max(kcalls, 1)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.timing_reset()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kms, kcalls = ctx.timing_read()
-    ms_per_step = wall * 1e3 / args.steps
-    value = total * args.steps / wall / 1e9
-    kernel_ms = kms / max(kcalls, 1)
+    # headline: FP64 uniforms only, as the workload defines its output
+    ms_per_step, kernel_ms = measure(args.steps, args.warmup, ph.PHPRNG_MODE_PERSISTENT)
+    value = total / (ms_per_step * 1e-3) / 1e9
     log("persistent: %.3f ms/step wall, %.3f ms kernel, %.1f Guniforms/s" % (ms_per_step, kernel_ms, value))
 
     plain = None
     if not args.no_plain:
-        step(ph.PHPRNG_MODE_PLAIN)
-        torch.cuda.synchronize()
-        ctx.timing_reset()
-        t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            step(ph.PHPRNG_MODE_PLAIN)
-        torch.cuda.synchronize()
-        pw = time.perf_counter() - t0
-        pk, pc = ctx.timing_read()
-        plain = {"value": total * args.plain_steps / pw / 1e9, "unit": "Guniforms/s",
-                 "ms_per_step": pw * 1e3 / args.plain_steps, "kernel_ms": pk / max(pc, 1),
-                 "launches_per_step": N_INST}
+        pms, pk = measure(args.plain_steps, 1, ph.PHPRNG_MODE_PLAIN)
+        plain = {"value": total / (pms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": pms,
+                 "kernel_ms": pk, "launches_per_step": N_INST, "speedup_of_batched": pms / ms_per_step}
         log("plain: %s" % plain)
+
+    with_c = None
+    if not args.no_ciphertexts:
+        c32 = torch.empty(total, dtype=torch.int32, device=dev)
+        cms, ck = measure(max(args.steps // 2, 1), 1, ph.PHPRNG_MODE_PERSISTENT, c32)
+        with_c = {"value": total / (cms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": cms,
+                  "kernel_ms": ck, "outputs": "u32 c + f64 R (12 B per draw)",
+                  "hbm_gbs": total * 12.0 / (ck * 1e-3) / 1e9}
+        log("with ciphertexts: %s" % with_c)
+        del c32
 
     # roofline of the generation kernel: algorithmic bytes / ops per launch
     ops_per_draw = float(np.mean([algorithmic_ops_32(e) for e in e_arr]))
-    bytes_per_draw = 12.0
+    bytes_per_draw = 8.0
     achieved_gbs = total * bytes_per_draw / (kernel_ms * 1e-3) / 1e9
     achieved_ops = total * ops_per_draw / (kernel_ms * 1e-3)
     hbm = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None}
+           "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_draw": bytes_per_draw}
     alu = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Top/s",
            "frac": achieved_ops / ALU_PEAK_OPS, "ops_per_draw": ops_per_draw}
     roof, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
@@ -174,15 +184,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u32/f64",
         "data": "synthetic",
         "config": {
-            "workload": "4096 seeded 32-bit instances x 2^18 draws per step (u32 c + f64 R to HBM), "
+            "workload": "4096 seeded 32-bit instances x 2^18 draws per step (1.07e9 FP64 uniforms to HBM), "
                         "one batched persistent launch per step",
             "instances": N_INST, "draws_per_instance": PER, "width": 32, "e_set": [9, 17],
             "start_position": 0, "tuning": tuning,
         },
         "plain": plain,
+        "with_ciphertexts": with_c,
         "roofline": roof,
         "roofline_other": other,
         "cpu_baseline": cpu,

@@ -38,22 +38,24 @@ __device__ __forceinline__ uint32_t powmod_p31(uint32_t b, uint64_t e) {
 
 // x y 2^{-32} mod n for x, y < n; ninv = n^{-1} mod 2^32.  The low words of
 // x y and q n cancel exactly, so the result is hi(x y) - hi(q n) (+ n).
+// Six VALU instructions: v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32,
+// v_sub_co_u32 (borrow), v_cndmask_b32, v_add_u32.
 __device__ __forceinline__ uint32_t mont32(uint32_t x, uint32_t y, uint32_t n, uint32_t ninv) {
   uint64_t t = (uint64_t)x * y;
   uint32_t q = (uint32_t)t * ninv;
   uint32_t qh = __umulhi(q, n);
-  uint32_t h = (uint32_t)(t >> 32);
-  uint32_t r = h - qh;
-  return h < qh ? r + n : r;
+  uint32_t r;
+  bool borrow = __builtin_usub_overflow((uint32_t)(t >> 32), qh, &r);
+  return r + (borrow ? n : 0u);
 }
 
 // v 2^{-32} mod n for v < n 2^32.
 __device__ __forceinline__ uint32_t redc32(uint64_t v, uint32_t n, uint32_t ninv) {
   uint32_t q = (uint32_t)v * ninv;
   uint32_t qh = __umulhi(q, n);
-  uint32_t h = (uint32_t)(v >> 32);
-  uint32_t r = h - qh;
-  return h < qh ? r + n : r;
+  uint32_t r;
+  bool borrow = __builtin_usub_overflow((uint32_t)(v >> 32), qh, &r);
+  return r + (borrow ? n : 0u);
 }
 
 // (m + s) mod n for m, s < n.
@@ -135,16 +137,18 @@ __device__ __forceinline__ uint64_t mont64(uint64_t x, uint64_t y, uint64_t n, u
   W128 t = mul64w(x, y);
   uint64_t q = t.lo * ninv;
   uint64_t qh = mul64w(q, n).hi;
-  uint64_t r = t.hi - qh;
-  return t.hi < qh ? r + n : r;
+  unsigned long r;
+  bool borrow = __builtin_usubl_overflow(t.hi, qh, &r);
+  return (uint64_t)r + (borrow ? n : 0ull);
 }
 
 // v 2^{-64} mod n for v < n 2^64.
 __device__ __forceinline__ uint64_t redc64(W128 v, uint64_t n, uint64_t ninv) {
   uint64_t q = v.lo * ninv;
   uint64_t qh = mul64w(q, n).hi;
-  uint64_t r = v.hi - qh;
-  return v.hi < qh ? r + n : r;
+  unsigned long r;
+  bool borrow = __builtin_usubl_overflow(v.hi, qh, &r);
+  return (uint64_t)r + (borrow ? n : 0ull);
 }
 
 // (m + s) mod n for m, s < n < 2^63 (no overflow of the sum).

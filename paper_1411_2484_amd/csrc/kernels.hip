@@ -133,35 +133,51 @@ __global__ void __launch_bounds__(256) advance_kernel(ReqRec *req, uint64_t nreq
 // tiles
 // ---------------------------------------------------------------------------
 
-struct TileOut {
-  uint32_t *c32;
-  uint64_t *c64;
-  double *r;
+// Which outputs a pass writes (bit 0: ciphertexts, bit 1: uniforms).
+enum { kOutC = 1, kOutR = 2 };
+
+struct Enc32 {
+  uint32_t n, ninv, kc;
+  uint64_t e;
+  int ebits;
+  double den, rcp;
 };
 
-// Width 32.  (m_t, s_t): state at the tile start index x0 = q (p-1) + j*2048.
-// Valid tile-local draws t in [t_lo, t_hi) are written at base + t.
-template <int UNROLL, int EK>
-__device__ __forceinline__ void tile32_passC(const uint32_t *L, uint32_t lane, uint32_t n, uint32_t ninv, uint32_t kc,
-                                             uint64_t e, int ebits, double den, double rcp, const TileOut &o,
-                                             int64_t base, uint32_t t_lo, uint32_t t_hi) {
-  // draw t = i*64 + lane lives at row t / 32, column t % 32
+// Pass C, width 32: draw t = i*64 + lane of the tile lives at LDS row t / 32,
+// column t % 32.  MASKED tiles write only t in [t_lo, t_hi).
+template <int UNROLL, int EK, int OUT, bool MASKED>
+__device__ __forceinline__ void passC32(const uint32_t *L, uint32_t lane, const Enc32 &K, uint32_t *c32, double *rr,
+                                        uint32_t t_lo, uint32_t t_hi) {
   const uint32_t *src = L + (lane >> 5) * kRow + (lane & 31);
-  const bool full = (t_lo == 0) && (t_hi == (uint32_t)kTile);
-  uint32_t *c32 = o.c32 ? o.c32 + base + lane : nullptr;
-  double *rr = o.r ? o.r + base + lane : nullptr;
-  for (int i0 = 0; i0 < kRun; i0 += UNROLL) {
-#pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
-      const int i = i0 + u;
-      const uint32_t t = (uint32_t)i * 64u + lane;
-      const uint32_t m = src[i * 2 * kRow];
-      if (full || (t >= t_lo && t < t_hi)) {
-        const uint32_t c = dev::encrypt32<EK>(m, n, ninv, kc, e, ebits);
-        if (c32) c32[i * 64] = c;
-        if (rr) rr[i * 64] = dev::uniform32(c, den, rcp);
-      }
+  const uint32_t span = t_hi - t_lo;
+#pragma unroll UNROLL
+  for (int i = 0; i < kRun; ++i) {
+    const uint32_t m = src[i * 2 * kRow];
+    if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
+      const uint32_t c = dev::encrypt32<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
+      if (OUT & kOutC) c32[i * 64] = c;
+      if (OUT & kOutR) rr[i * 64] = dev::uniform32(c, K.den, K.rcp);
     }
+  }
+}
+
+template <int UNROLL, int EK, bool MASKED>
+__device__ __forceinline__ void passC32_out(const uint32_t *L, uint32_t lane, const Enc32 &K, uint32_t *c32,
+                                            double *rr, uint32_t t_lo, uint32_t t_hi) {
+  if (c32 && rr) passC32<UNROLL, EK, kOutC | kOutR, MASKED>(L, lane, K, c32, rr, t_lo, t_hi);
+  else if (rr) passC32<UNROLL, EK, kOutR, MASKED>(L, lane, K, c32, rr, t_lo, t_hi);
+  else if (c32) passC32<UNROLL, EK, kOutC, MASKED>(L, lane, K, c32, rr, t_lo, t_hi);
+}
+
+template <int UNROLL, bool MASKED>
+__device__ __forceinline__ void passC32_e(int ekind, const uint32_t *L, uint32_t lane, const Enc32 &K, uint32_t *c32,
+                                          double *rr, uint32_t t_lo, uint32_t t_hi) {
+  switch (ekind) {
+    case 9: passC32_out<UNROLL, 9, MASKED>(L, lane, K, c32, rr, t_lo, t_hi); break;
+    case 17: passC32_out<UNROLL, 17, MASKED>(L, lane, K, c32, rr, t_lo, t_hi); break;
+    case 3: passC32_out<UNROLL, 3, MASKED>(L, lane, K, c32, rr, t_lo, t_hi); break;
+    case 5: passC32_out<UNROLL, 5, MASKED>(L, lane, K, c32, rr, t_lo, t_hi); break;
+    default: passC32_out<UNROLL, 0, MASKED>(L, lane, K, c32, rr, t_lo, t_hi); break;
   }
 }
 
@@ -229,39 +245,57 @@ __device__ void run_chunk32(const GenArgs &A, const InstRec &I, const ReqRec &R,
     uint64_t hi2 = pm1 - (uint64_t)j * kTile;
     uint64_t hi = min(min(hi1, hi2), (uint64_t)kTile);
     uint32_t t_hi = (uint32_t)hi;
-    const int64_t base = (int64_t)R.out_off + (int64_t)(tile_first - R.k);
-    TileOut o{A.out_c32, nullptr, A.out_r};
-    switch (ekind) {
-      case 9: tile32_passC<UNROLL, 9>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
-      case 17: tile32_passC<UNROLL, 17>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
-      case 3: tile32_passC<UNROLL, 3>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
-      case 5: tile32_passC<UNROLL, 5>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
-      default: tile32_passC<UNROLL, 0>(L, lane, n, ninv, kc, e, ebits, den, rcp, o, base, t_lo, t_hi); break;
-    }
+    const int64_t base = (int64_t)R.out_off + (int64_t)(tile_first - R.k) + (int64_t)lane;
+    uint32_t *c32 = A.out_c32 ? A.out_c32 + base : nullptr;
+    double *rr = A.out_r ? A.out_r + base : nullptr;
+    const Enc32 K{n, ninv, kc, e, ebits, den, rcp};
+    if (t_lo == 0 && t_hi == (uint32_t)kTile)
+      passC32_e<UNROLL, false>(ekind, L, lane, K, c32, rr, t_lo, t_hi);
+    else
+      passC32_e<1, true>(ekind, L, lane, K, c32, rr, t_lo, t_hi);
     dev::wave_lds_sync();
   }
 }
 
-template <int UNROLL, int EK>
-__device__ __forceinline__ void tile64_passC(const uint64_t *L, uint32_t lane, uint64_t n, uint64_t ninv, uint64_t kc,
-                                             uint64_t e, int ebits, double den, const TileOut &o, int64_t base,
-                                             uint32_t t_lo, uint32_t t_hi) {
+struct Enc64 {
+  uint64_t n, ninv, kc, e;
+  int ebits;
+  double den;
+};
+
+template <int UNROLL, int EK, int OUT, bool MASKED>
+__device__ __forceinline__ void passC64(const uint64_t *L, uint32_t lane, const Enc64 &K, uint64_t *c64, double *rr,
+                                        uint32_t t_lo, uint32_t t_hi) {
   const uint64_t *src = L + (lane >> 5) * kRow + (lane & 31);
-  const bool full = (t_lo == 0) && (t_hi == (uint32_t)kTile);
-  uint64_t *c64 = o.c64 ? o.c64 + base + lane : nullptr;
-  double *rr = o.r ? o.r + base + lane : nullptr;
-  for (int i0 = 0; i0 < kRun; i0 += UNROLL) {
-#pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
-      const int i = i0 + u;
-      const uint32_t t = (uint32_t)i * 64u + lane;
-      const uint64_t m = src[i * 2 * kRow];
-      if (full || (t >= t_lo && t < t_hi)) {
-        const uint64_t c = dev::encrypt64<EK>(m, n, ninv, kc, e, ebits);
-        if (c64) c64[i * 64] = c;
-        if (rr) rr[i * 64] = dev::uniform64(c, den);
-      }
+  const uint32_t span = t_hi - t_lo;
+#pragma unroll UNROLL
+  for (int i = 0; i < kRun; ++i) {
+    const uint64_t m = src[i * 2 * kRow];
+    if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
+      const uint64_t c = dev::encrypt64<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
+      if (OUT & kOutC) c64[i * 64] = c;
+      if (OUT & kOutR) rr[i * 64] = dev::uniform64(c, K.den);
     }
+  }
+}
+
+template <int UNROLL, int EK, bool MASKED>
+__device__ __forceinline__ void passC64_out(const uint64_t *L, uint32_t lane, const Enc64 &K, uint64_t *c64,
+                                            double *rr, uint32_t t_lo, uint32_t t_hi) {
+  if (c64 && rr) passC64<UNROLL, EK, kOutC | kOutR, MASKED>(L, lane, K, c64, rr, t_lo, t_hi);
+  else if (rr) passC64<UNROLL, EK, kOutR, MASKED>(L, lane, K, c64, rr, t_lo, t_hi);
+  else if (c64) passC64<UNROLL, EK, kOutC, MASKED>(L, lane, K, c64, rr, t_lo, t_hi);
+}
+
+template <int UNROLL, bool MASKED>
+__device__ __forceinline__ void passC64_e(int ekind, const uint64_t *L, uint32_t lane, const Enc64 &K, uint64_t *c64,
+                                          double *rr, uint32_t t_lo, uint32_t t_hi) {
+  switch (ekind) {
+    case 9: passC64_out<UNROLL, 9, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
+    case 17: passC64_out<UNROLL, 17, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
+    case 3: passC64_out<UNROLL, 3, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
+    case 5: passC64_out<UNROLL, 5, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
+    default: passC64_out<UNROLL, 0, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
   }
 }
 
@@ -319,15 +353,14 @@ __device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R,
     uint32_t t_lo = R.k > x0 ? (uint32_t)(R.k - x0) : 0u;
     uint64_t hi = min(req_end - x0, (uint64_t)kTile);
     uint32_t t_hi = (uint32_t)hi;
-    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.k);
-    TileOut o{nullptr, A.out_c64, A.out_r};
-    switch (ekind) {
-      case 9: tile64_passC<UNROLL, 9>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
-      case 17: tile64_passC<UNROLL, 17>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
-      case 3: tile64_passC<UNROLL, 3>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
-      case 5: tile64_passC<UNROLL, 5>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
-      default: tile64_passC<UNROLL, 0>(L, lane, n, ninv, kc, e, ebits, den, o, base, t_lo, t_hi); break;
-    }
+    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.k) + (int64_t)lane;
+    uint64_t *c64 = A.out_c64 ? A.out_c64 + base : nullptr;
+    double *rr = A.out_r ? A.out_r + base : nullptr;
+    const Enc64 K{n, ninv, kc, e, ebits, den};
+    if (t_lo == 0 && t_hi == (uint32_t)kTile)
+      passC64_e<UNROLL, false>(ekind, L, lane, K, c64, rr, t_lo, t_hi);
+    else
+      passC64_e<1, true>(ekind, L, lane, K, c64, rr, t_lo, t_hi);
     dev::wave_lds_sync();
   }
 }
