@@ -70,16 +70,162 @@ def cpu_baseline(e_arr, n_arr, target_s=12.0):
                       "%d draws) in %.1f s" % (done_inst, draws, el)}
 
 
+def common_line(metric_value, unit, steps, warmup, ms_per_step, config, **extra):
+    out = {
+        "metric": "Guniforms/s (32/64-bit moduli), batched vs plain launch; serve p50/p99 latency",
+        "value": metric_value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32/u64/f64", "data": "synthetic", "config": config,
+    }
+    out.update(extra)
+    return out
+
+
+def timed_steps(ctx, torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ctx.timing_reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, kc = ctx.timing_read()
+    return wall * 1e3 / steps, kms / max(kc, 1)
+
+
+def workload_a(args, torch, ph):
+    """One seeded 32-bit instance, 10^6 draws per step (u32 c + f64 R)."""
+    dev = torch.device("cuda:0")
+    ctx = ph.Context(0, max_instances=1)
+    ids = ctx.seed_instances(32, 0x14112484, 1, (9, 17), 0, 0)
+    N = 10 ** 6
+    c32 = torch.empty(N, dtype=torch.int32, device=dev)
+    r = torch.empty(N, dtype=torch.float64, device=dev)
+    reqs = ph.make_requests(ids, [N], [0])
+    res = {}
+    for name, mode in (("persistent", ph.PHPRNG_MODE_PERSISTENT), ("plain", ph.PHPRNG_MODE_PLAIN)):
+        ms, kms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, c32, None, r, mode=mode), args.steps,
+                              args.warmup)
+        res[name] = {"ms_per_step": ms, "kernel_ms": kms, "value": N / (ms * 1e-3) / 1e9}
+    ctx.close()
+    return common_line(res["persistent"]["value"], "Guniforms/s", args.steps, args.warmup,
+                       res["persistent"]["ms_per_step"],
+                       {"workload": "1 seeded 32-bit instance x 10^6 draws from position 0 (u32 c + f64 R)"},
+                       plain=res["plain"], persistent=res["persistent"])
+
+
+def workload_c(args, torch, ph):
+    """65,536 seeded 32-bit instances, log-uniform stream lengths in
+    [2^10, 2^22], random starts in [0, 2^40), one persistent launch per step.
+    Outputs (u32 c + f64 R) go to a reused arena of 2^32 elements: streams
+    are placed one after another and wrap to the start of the arena."""
+    dev = torch.device("cuda:0")
+    nin = 65536
+    ctx = ph.Context(0, max_instances=nin)
+    ids = ctx.seed_instances(32, 0x14112484 + 2, nin, (9, 17), 0, 1 << 40)
+    rng = np.random.default_rng(0x14112484 + 2)
+    lens = np.floor(2.0 ** (10 + 12 * rng.random(nin))).astype(np.uint64)
+    arena = 1 << 32
+    offs = np.zeros(nin, dtype=np.uint64)
+    cur = 0
+    for i in range(nin):
+        if cur + int(lens[i]) > arena:
+            cur = 0
+        offs[i] = cur
+        cur += int(lens[i])
+    total = int(lens.sum())
+    c32 = torch.empty(arena, dtype=torch.int32, device=dev)
+    r = torch.empty(arena, dtype=torch.float64, device=dev)
+    reqs = ph.make_requests(ids, lens, offs)
+    steps = max(2, args.steps // 5)
+    ms, kms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, c32, None, r, capacity=arena), steps, 1)
+    rms, rkms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, None, None, r, capacity=arena), steps, 1)
+    ctx.close()
+    value = total / (ms * 1e-3) / 1e9
+    return common_line(value, "Guniforms/s", steps, 1, ms,
+                       {"workload": "65536 seeded 32-bit instances, log-uniform lengths 2^10..2^22 (%d draws), "
+                                    "random starts in [0, 2^40), one persistent launch, u32 c + f64 R" % total},
+                       kernel_ms=kms, hbm_gbs=total * 12.0 / (kms * 1e-3) / 1e9,
+                       uniforms_only={"value": total / (rms * 1e-3) / 1e9, "kernel_ms": rkms})
+
+
+def workload_d(args, torch, ph):
+    """1024 64-bit + 1024 32-bit instances x 2^20 draws, mixed in one launch."""
+    dev = torch.device("cuda:0")
+    ctx = ph.Context(0, max_instances=2048)
+    i64 = ctx.seed_instances(64, 0x14112484 + 3, 1024, (9, 17), 0, 0)
+    i32 = ctx.seed_instances(32, 0x14112484 + 4, 1024, (9, 17), 0, 0)
+    per = 1 << 20
+    total = 2048 * per
+    c32 = torch.empty(total, dtype=torch.int32, device=dev)
+    c64 = torch.empty(total, dtype=torch.int64, device=dev)
+    r = torch.empty(total, dtype=torch.float64, device=dev)
+    steps = max(2, args.steps // 4)
+    res = {}
+    for name, ids in (("mixed", np.concatenate([i64, i32])), ("w64_only", i64), ("w32_only", i32)):
+        reqs = ph.make_requests(ids, [per] * len(ids), np.arange(len(ids), dtype=np.uint64) * per)
+        ms, kms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, c32, c64, r, capacity=total), steps, 1)
+        res[name] = {"value": len(ids) * per / (ms * 1e-3) / 1e9, "ms_per_step": ms, "kernel_ms": kms}
+    ctx.close()
+    return common_line(res["mixed"]["value"], "Guniforms/s", steps, 1, res["mixed"]["ms_per_step"],
+                       {"workload": "1024 64-bit (n in [2^62, 2^63)) + 1024 32-bit instances x 2^20 draws, one "
+                                    "mixed persistent launch, u32/u64 c + f64 R"}, **res)
+
+
+def workload_e(args, torch, ph):
+    """Serving: 10^6 resident instances (900,000 32-bit, 100,000 64-bit),
+    open-loop Poisson arrivals, each request log-uniform 2^8..2^20 FP64
+    uniforms from a uniformly chosen instance, continuous batching."""
+    n32, n64 = args.serve_instances * 9 // 10, args.serve_instances // 10
+    ctx = ph.Context(0, max_instances=n32 + n64)
+    t0 = time.perf_counter()
+    ctx.seed_instances(32, 0x14112484 + 5, n32, (9, 17), 0, 1 << 40)
+    ctx.seed_instances(64, 0x14112484 + 6, n64, (9, 17), 0, 1 << 32)
+    log("serve: %d instances seeded in %.1f s" % (n32 + n64, time.perf_counter() - t0))
+    srv = ph.Server(ctx, arena_doubles=args.serve_arena, streams=2)
+    rng = np.random.default_rng(0x14112484 + 7)
+    points = []
+    for lam in args.serve_rates:
+        n = int(min(args.serve_max_requests, max(2000, lam * args.serve_seconds)))
+        arr = np.zeros(n, dtype=ph.ARRIVAL_DTYPE)
+        arr["t_ns"] = np.cumsum(rng.exponential(1e9 / lam, n)).astype(np.int64)
+        arr["instance"] = rng.integers(0, n32 + n64, n)
+        arr["count"] = np.floor(2.0 ** (8 + 12 * rng.random(n))).astype(np.uint64)
+        lat, wall = srv.replay(arr)
+        draws = int(arr["count"].sum())
+        pt = {"rate_req_s": lam, "requests": n, "uniforms_per_s": draws / wall / 1e9,
+              "p50_ms": float(np.percentile(lat, 50)) / 1e6, "p99_ms": float(np.percentile(lat, 99)) / 1e6,
+              "offered_guniforms_s": draws / (arr["t_ns"][-1] * 1e-9) / 1e9, "wall_s": wall}
+        log("serve: %s" % pt)
+        points.append(pt)
+    srv.close()
+    ctx.close()
+    best = max(points, key=lambda p: p["uniforms_per_s"])
+    return common_line(best["uniforms_per_s"], "Guniforms/s", len(points), 0, None,
+                       {"workload": "serving: %d resident instances (90%% 32-bit, 10%% 64-bit), Poisson arrivals, "
+                                    "log-uniform 2^8..2^20 FP64 uniforms per request" % (n32 + n64)},
+                       serve=points)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-ciphertexts", action="store_true", help="skip the u32 + f64 output variant")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
+    ap.add_argument("--workload", default="B", choices=["A", "B", "C", "D", "E"],
+                    help="B (default): the headline batch; A, C, D, E: the other workload shapes")
+    ap.add_argument("--serve-instances", type=int, default=1000000)
+    ap.add_argument("--serve-arena", type=int, default=1 << 31, help="serving arena, FP64 uniforms")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[1e3, 1e4, 1e5, 1e6])
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-max-requests", type=int, default=200000)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="first run one device copy of this many GiB (known-size kernel for traffic counters)")
     args = ap.parse_args()
@@ -96,6 +242,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "B":
+        fn = {"A": workload_a, "C": workload_c, "D": workload_d, "E": workload_e}[args.workload]
+        print(json.dumps(fn(args, torch, ph)), flush=True)
+        return
     dev = torch.device("cuda:0")
     ctx = ph.Context(0, max_instances=N_INST)
     ids = ctx.seed_instances(32, SEED_B, N_INST, (9, 17), 0, 0)

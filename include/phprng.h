@@ -160,6 +160,9 @@ phprng_status phprng_jump(phprng_ctx *ctx, uint32_t id, int64_t delta);
 /* Current state (m_k, s_k, c_k, k) of instance `id`. */
 phprng_status phprng_get_state(phprng_ctx *ctx, uint32_t id, phprng_state *out);
 
+/* Current position k of instance `id` (cheap: no state is computed). */
+phprng_status phprng_get_position(phprng_ctx *ctx, uint32_t id, uint64_t *k);
+
 /* Restore instance `id` to the state (st->m, st->s) reported at position
  * st->k (st->c is ignored).  Any s in [1, p-1] is accepted: the library finds
  * t with a^t = s mod p by a Pohlig-Hellman discrete logarithm (p - 1 is
@@ -175,10 +178,13 @@ phprng_status phprng_get_params(phprng_ctx *ctx, uint32_t id, uint64_t *n, uint6
 phprng_status phprng_set_tuning(phprng_ctx *ctx, const phprng_tuning *t);
 phprng_status phprng_get_tuning(phprng_ctx *ctx, phprng_tuning *t);
 
-/* Time candidate launch shapes on a synthetic batch of `draws` draws spread
- * over the context's first instances (their positions are restored
- * afterwards; device scratch of 12 bytes per draw is allocated and freed),
- * keep the fastest, and return it in *best (may be NULL). */
+/* Time candidate launch shapes (block size, blocks per CU, tiles per chunk,
+ * unroll) on a synthetic batch of about `draws` draws spread over the
+ * context's first (up to 4096) instances, writing FP64 uniforms only, into a
+ * temporary device buffer of 8 bytes per draw.  Each shape is timed by the
+ * median of three kernel times after a 300 ms warm-up; the fastest is kept
+ * (if it beats the current shape on a re-run) and returned in *best (may be
+ * NULL).  Instance positions are restored afterwards. */
 phprng_status phprng_autotune(phprng_ctx *ctx, uint64_t draws, phprng_tuning *best);
 
 /* ---- captured repeat draws -------------------------------------------------*/
@@ -208,6 +214,72 @@ phprng_status phprng_last_kernel_ms(phprng_ctx *ctx, double *ms);
  * recycled, and this function waits for the calls still in flight. */
 phprng_status phprng_timing_reset(phprng_ctx *ctx);
 phprng_status phprng_timing_read(phprng_ctx *ctx, double *total_ms, uint64_t *calls);
+
+/* ---- serving: continuous batching over resident instances -------------------*/
+
+/* A server owns a device output arena and a scheduler thread that runs
+ * generation for queued requests on the instances of `ctx` (the instance
+ * table stays resident on the device; positions are reserved on the host at
+ * admission).  Requests are admitted in FIFO order while the arena has room
+ * for their FP64 uniforms and the batch limits allow; each admitted group is
+ * one batched launch on the next of `streams` HIP streams, so batches
+ * submitted while others run overlap on the device.  A request's output
+ * depends only on its instance and the position range reserved for it, not
+ * on what else is in its batch.  While a server exists, only the server may
+ * use `ctx`.  Zero fields take defaults (arena 2^28 uniforms, 2 streams,
+ * max_inflight = streams, 8192 requests / 2^28 draws per batch). */
+typedef struct phprng_server phprng_server;
+
+typedef struct {
+  uint64_t arena_doubles;      /* device arena capacity in FP64 uniforms */
+  int32_t streams;             /* 1..8 */
+  int32_t max_inflight;        /* batches on the device at once, 1..6 */
+  uint32_t max_batch_requests; /* requests per batched launch */
+  uint32_t reserved;           /* must be 0 */
+  uint64_t max_batch_draws;    /* draws per batched launch (a single larger request still runs) */
+} phprng_server_config;
+
+/* A finished request.  data points to `count` FP64 uniforms inside the arena
+ * (device memory), valid until phprng_server_release(ticket).  k is the
+ * instance position before the request's first draw.  Times are host
+ * steady-clock nanoseconds: submission, admission (launch), and completion
+ * as observed by the scheduler. */
+typedef struct {
+  uint64_t ticket, tag;
+  uint32_t instance;
+  int32_t status;
+  uint64_t count, k;
+  double *data;
+  int64_t t_submit_ns, t_admit_ns, t_done_ns;
+} phprng_completion;
+
+phprng_status phprng_server_create(phprng_ctx *ctx, const phprng_server_config *cfg, phprng_server **server);
+/* Queue `count` uniforms from `instance`; thread-safe.  *ticket identifies it. */
+phprng_status phprng_server_submit(phprng_server *server, uint32_t instance, uint64_t count, uint64_t tag,
+                                   uint64_t *ticket);
+/* Move up to `max` completions into out (host array); waits up to timeout_us
+ * microseconds when none is ready.  *n receives the number returned. */
+phprng_status phprng_server_poll(phprng_server *server, phprng_completion *out, uint64_t max, uint64_t *n,
+                                 int64_t timeout_us);
+/* Return a completed request's arena range. */
+phprng_status phprng_server_release(phprng_server *server, uint64_t ticket);
+phprng_status phprng_server_stats(phprng_server *server, uint64_t *pending, uint64_t *arena_used);
+/* Drains the batches on the device, stops the scheduler, frees the arena. */
+phprng_status phprng_server_destroy(phprng_server *server);
+
+/* Open-loop load: a native thread submits arrival i at t_ns nanoseconds after
+ * the start (non-decreasing), each completed result is released at once, and
+ * latency_ns[i] receives completion minus scheduled arrival (-1 on error).
+ * *wall_s receives the time from the start to the last completion. */
+typedef struct {
+  int64_t t_ns;
+  uint32_t instance;
+  uint32_t reserved;
+  uint64_t count;
+} phprng_arrival;
+
+phprng_status phprng_server_replay(phprng_server *server, const phprng_arrival *arrivals, uint64_t n,
+                                   int64_t *latency_ns, double *wall_s);
 
 #ifdef __cplusplus
 }

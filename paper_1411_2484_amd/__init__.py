@@ -51,6 +51,22 @@ class phprng_tuning(ctypes.Structure):
                 ("tiles_per_chunk", ctypes.c_int32), ("unroll", ctypes.c_int32)]
 
 
+class phprng_server_config(ctypes.Structure):
+    _fields_ = [("arena_doubles", ctypes.c_uint64), ("streams", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_batch_requests", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("max_batch_draws", ctypes.c_uint64)]
+
+
+class phprng_completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("instance", ctypes.c_uint32),
+                ("status", ctypes.c_int32), ("count", ctypes.c_uint64), ("k", ctypes.c_uint64),
+                ("data", ctypes.c_void_p), ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+ARRIVAL_DTYPE = np.dtype([("t_ns", np.int64), ("instance", np.uint32), ("reserved", np.uint32),
+                          ("count", np.uint64)])
+
 REQUEST_DTYPE = np.dtype([("instance", np.uint32), ("reserved", np.uint32), ("count", np.uint64),
                           ("out_offset", np.uint64)])
 
@@ -81,6 +97,15 @@ SIGNATURES = {
     "phprng_graph_launch": (ctypes.c_int, [_vp, _vp]),
     "phprng_graph_destroy": (ctypes.c_int, [_vp]),
     "phprng_last_kernel_ms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
+    "phprng_get_position": (ctypes.c_int, [_vp, ctypes.c_uint32, _pu64]),
+    "phprng_server_create": (ctypes.c_int, [_vp, ctypes.POINTER(phprng_server_config), ctypes.POINTER(_vp)]),
+    "phprng_server_submit": (ctypes.c_int, [_vp, ctypes.c_uint32, _u64, _u64, _pu64]),
+    "phprng_server_poll": (ctypes.c_int, [_vp, ctypes.POINTER(phprng_completion), _u64, _pu64, ctypes.c_int64]),
+    "phprng_server_release": (ctypes.c_int, [_vp, _u64]),
+    "phprng_server_stats": (ctypes.c_int, [_vp, _pu64, _pu64]),
+    "phprng_server_destroy": (ctypes.c_int, [_vp]),
+    "phprng_server_replay": (ctypes.c_int, [_vp, _vp, _u64, ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_double)]),
     "phprng_timing_reset": (ctypes.c_int, [_vp]),
     "phprng_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
 }
@@ -252,6 +277,11 @@ class Context:
         self._chk(lib().phprng_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def get_position(self, inst):
+        k = _u64()
+        self._chk(lib().phprng_get_position(self._h, int(inst), ctypes.byref(k)))
+        return k.value
+
     def jump(self, inst, delta):
         self._chk(lib().phprng_jump(self._h, int(inst), int(delta)))
 
@@ -312,6 +342,59 @@ class Graph:
     def close(self):
         if getattr(self, "_h", None):
             lib().phprng_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """phprng_server_*: continuous batching over the instances of a context.
+    While it exists, only the server uses the context."""
+
+    def __init__(self, ctx, arena_doubles=1 << 28, streams=2, max_inflight=0, max_batch_requests=0,
+                 max_batch_draws=0):
+        cfg = phprng_server_config(int(arena_doubles), int(streams), int(max_inflight), int(max_batch_requests), 0,
+                                   int(max_batch_draws))
+        h = _vp()
+        _check(lib().phprng_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), ctx.handle)
+        self._h = h
+        self._ctx = ctx
+
+    def submit(self, instance, count, tag=0):
+        t = _u64()
+        _check(lib().phprng_server_submit(self._h, int(instance), int(count), int(tag), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, max_items=256, timeout_us=1000):
+        buf = (phprng_completion * max_items)()
+        n = _u64()
+        _check(lib().phprng_server_poll(self._h, buf, max_items, ctypes.byref(n), int(timeout_us)))
+        return [buf[i] for i in range(n.value)]
+
+    def release(self, ticket):
+        _check(lib().phprng_server_release(self._h, int(ticket)))
+
+    def stats(self):
+        p, u = _u64(), _u64()
+        _check(lib().phprng_server_stats(self._h, ctypes.byref(p), ctypes.byref(u)))
+        return p.value, u.value
+
+    def replay(self, arrivals):
+        """arrivals: numpy array of ARRIVAL_DTYPE.  Returns (latency_ns array, wall seconds)."""
+        arr = np.ascontiguousarray(arrivals, dtype=ARRIVAL_DTYPE)
+        lat = np.zeros(arr.size, dtype=np.int64)
+        wall = ctypes.c_double()
+        _check(lib().phprng_server_replay(self._h, arr.ctypes.data, arr.size,
+                                          lat.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(wall)))
+        return lat, wall.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().phprng_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

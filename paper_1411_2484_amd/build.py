@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphprng.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "hostmath.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "hostmath.cpp", "server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -45,12 +45,20 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError("hipcc failed on " + src)
         objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link failed")
     os.replace(tmp, LIB)
+    # instruction-rate probe (a standalone executable)
+    probe = os.path.join(HERE, "probe_rates")
+    cmd = [hipcc, *HIPCC_FLAGS, "-o", probe + ".tmp", os.path.join(CSRC, "probe_rates.hip")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on probe_rates.hip")
+    os.replace(probe + ".tmp", probe)
     return LIB
 
 
