@@ -71,6 +71,8 @@ def lib():
             "pho_generate_many": (None, [ctypes.c_int, _u64, _pu64, _pu64, _pu64, _pu64, _pu64, _pu64, _pu64,
                                          _pu64, _pu64, _pdbl]),
             "pho_jump_forward": (None, [_u64, _u64, _u64, _pu64, _pu64, _u64]),
+            "pho_cskip_message": (_u64, [_u64, _u64, _u64, _u64]),
+            "pho_generate_cskip": (None, [_u64, _u64, _u64, _pu64, _u64, _pu64, _pdbl]),
             "pho_jump_backward": (None, [_u64, _u64, _u64, _pu64, _pu64, _u64]),
             "pho_splitmix64": (None, [_u64, _u64, _pu64]),
             "pho_seed": (ctypes.c_int, [ctypes.c_int, _u64, _u64, _pu64, ctypes.c_int, _u64, _u64, _pu64, _pu64,
@@ -224,6 +226,21 @@ def generate_many(p, a, n, e, m, s, count, want_c=True, want_r=True, nthreads=0)
     lib().pho_generate_many(nthreads, ninst, _p64(p), _p64(a), _p64(n), _p64(e), _p64(m), _p64(s), _p64(count),
                             _p64(off), _p64(c) if want_c else None, _pd(r) if want_r else None)
     return c, r, m, s, off
+
+
+def cskip_message(n, m0, b, k):
+    """Message at position k under the constant skip b (unit skip: b = 1)."""
+    return lib().pho_cskip_message(n, m0, b, k)
+
+
+def generate_cskip(n, e, b, m, count, want_c=True, want_r=True):
+    """Constant-skip draws from message m.  Returns (c, R, m)."""
+    mm = _u64(m)
+    c = np.zeros(count, dtype=np.uint64) if want_c else None
+    r = np.zeros(count, dtype=np.float64) if want_r else None
+    lib().pho_generate_cskip(n, e, b, ctypes.byref(mm), count, _p64(c) if want_c else None,
+                             _pd(r) if want_r else None)
+    return c, r, mm.value
 
 
 def jump_forward(p, a, n, m, s, delta):

@@ -413,6 +413,27 @@ void pho_generate_many(int nthreads, uint64_t ninst, const uint64_t *p, const ui
   free(jobs);
 }
 
+/* Constant-skip schedule of Sec. II (unit skip when b = 1): the message at
+ * position k is m_k = (m_0 + k b) mod n. */
+uint64_t pho_cskip_message(uint64_t n, uint64_t m0, uint64_t b, uint64_t k) {
+  return (uint64_t)(((u128)m0 + (u128)(k % n) * (u128)(b % n)) % n);
+}
+
+/* Draws under the constant skip, from message *m: m := (m + b) mod n,
+ * c := m^e mod n, R := (c+1)/(n+1), `count` times. */
+void pho_generate_cskip(uint64_t n, uint64_t e, uint64_t b, uint64_t *m, uint64_t count, uint64_t *c_out,
+                        double *r_out) {
+  uint64_t mm = *m;
+  double denom = (double)(n + 1);
+  for (uint64_t t = 0; t < count; t++) {
+    mm = (uint64_t)(((u128)mm + b % n) % n);
+    uint64_t c = pho_powmod(mm, e, n);
+    if (c_out) c_out[t] = c;
+    if (r_out) r_out[t] = (double)(c + 1) / denom;
+  }
+  *m = mm;
+}
+
 /* Forward jump by stepping (9a)-(9b) delta times (no encryption). */
 void pho_jump_forward(uint64_t p, uint64_t a, uint64_t n, uint64_t *m, uint64_t *s, uint64_t delta) {
   uint64_t mm = *m, ss = *s;

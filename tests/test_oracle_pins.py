@@ -534,3 +534,49 @@ def test_seeded_instances_are_admissible_and_distinct(orc, width):
     assert np.array_equal(n, n2) and np.array_equal(e, e2) and np.array_equal(k, k2)
     # both exponents are used; e = 9 only where 3 does not divide n - 1
     assert set(int(x) for x in np.unique(e)) == {9, 17}
+
+
+# --------------------------------------------------------------------------
+# Unit and constant skips (Sec. II)
+# --------------------------------------------------------------------------
+
+def test_unit_skip_stream_reproduces_fig2(orc, paper):
+    fx = paper["unit_skip_fig2"]
+    n, e = fx["n"], fx["e"]
+    # position 0 holds m_0 = 0 (c_0 = 0); draws return c_1, c_2, ...
+    assert orc.encrypt(orc.cskip_message(n, 0, 1, 0), e, n) == fx["ciphertexts"][0]
+    c, r, m = orc.generate_cskip(n, e, 1, 0, 4)
+    assert [int(x) for x in c] == fx["ciphertexts"][1:]
+    assert m == 4
+
+
+def test_constant_skip_is_a_scaled_unit_skip(orc):
+    """Eq. (4): (k b)^e = (b^e mod n)(k^e mod n) mod n, and the symmetry
+    ((n-k) b)^e = n - (k b)^e mod n (Sec. II)."""
+    rng = random.Random(31)
+    n, e = 4294967087, 9
+    for _ in range(5):
+        b = rng.randrange(2, n - 1)
+        cb, _, _ = orc.generate_cskip(n, e, b, 0, 3000, want_r=False)
+        cu, _, _ = orc.generate_cskip(n, e, 1, 0, 3000, want_r=False)
+        be = orc.encrypt(b, e, n)
+        assert all(int(x) == be * int(y) % n for x, y in zip(cb, cu))
+        for k in rng.sample(range(1, 3000), 50):
+            ck = orc.encrypt(orc.cskip_message(n, 0, b, k), e, n)
+            cnk = orc.encrypt(orc.cskip_message(n, 0, b, n - k), e, n)
+            assert cnk == n - ck
+
+
+def test_constant_skip_closed_form_and_full_period(orc):
+    rng = random.Random(32)
+    for n in (101, 1009, 4099):
+        for e in [x for x in (3, 5, 7, 9, 11, 17) if math.gcd(x, n - 1) == 1][:2]:
+            b, m0 = rng.randrange(1, n), rng.randrange(n)
+            c, r, m = orc.generate_cskip(n, e, b, m0, n, want_r=True)
+            # every ciphertext exactly once over the period n
+            assert np.array_equal(np.sort(c), np.arange(n, dtype=np.uint64))
+            assert m == m0
+            for k in (1, 2, n // 2, n - 1):
+                assert orc.encrypt(orc.cskip_message(n, m0, b, k), e, n) == int(c[k - 1])
+            for ci, ri in zip(c[:50], r[:50]):
+                assert float(ri) == (int(ci) + 1) / (n + 1)
