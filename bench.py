@@ -34,6 +34,33 @@ HBM_PEAK_GBS = 8000.0         # MI355X published HBM3E bandwidth
 ALU_PEAK_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz, one VALU op per lane per clock
 
 
+KERNEL_SOURCES = ["paper_1411_2484_amd/csrc/kernels.hip", "paper_1411_2484_amd/csrc/arith.hpp",
+                  "paper_1411_2484_amd/csrc/layout.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gen_persistent_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
 def algorithmic_ops_32(e):
     """VALU operations per width-32 draw in the minimal instruction model of
     algorithm (9): skip 6, message 4, Montgomery products 6 each (e = 9: 5,
@@ -218,6 +245,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-ciphertexts", action="store_true", help="skip the u32 + f64 output variant")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph replay variant")
+    ap.add_argument("--no-unit-skip", action="store_true", help="skip the unit-skip schedule variant")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
     ap.add_argument("--workload", default="B", choices=["A", "B", "C", "D", "E"],
                     help="B (default): the headline batch; A, C, D, E: the other workload shapes")
@@ -293,6 +322,28 @@ def main():
                  "kernel_ms": pk, "launches_per_step": N_INST, "speedup_of_batched": pms / ms_per_step}
         log("plain: %s" % plain)
 
+    graph = None
+    if not args.no_graph:
+        g = ctx.graph(reqs, None, None, r, capacity=total)
+        gms, gk = timed_steps(ctx, torch, g.launch, args.steps, 3)
+        g.close()
+        graph = {"value": total / (gms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": gms, "kernel_ms": gk,
+                 "note": "captured plan + persistent kernel + position advance, replayed each step"}
+        log("graph replay: %s" % graph)
+
+    unit = None
+    if not args.no_unit_skip:
+        # the same moduli and exponents on the unit-skip schedule (counter mode):
+        # the encryption path alone, without the skip generator and prefix
+        uctx = ph.Context(0, max_instances=N_INST)
+        uids = uctx.add_instances_skip(32, n_arr, e_arr, np.ones(N_INST, dtype=np.uint64))
+        ureqs = ph.make_requests(uids, [PER] * N_INST, np.arange(N_INST, dtype=np.uint64) * PER)
+        ums, uk = timed_steps(uctx, torch, lambda: uctx.generate(ureqs, None, None, r, capacity=total), args.steps, 3)
+        unit = {"value": total / (ums * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": ums, "kernel_ms": uk,
+                "note": "same 4096 (n, e), unit-skip schedule m_k = m_0 + k"}
+        log("unit skip: %s" % unit)
+        uctx.close()
+
     with_c = None
     if not args.no_ciphertexts:
         c32 = torch.empty(total, dtype=torch.int32, device=dev)
@@ -309,11 +360,12 @@ def main():
     achieved_gbs = total * bytes_per_draw / (kernel_ms * 1e-3) / 1e9
     achieved_ops = total * ops_per_draw / (kernel_ms * 1e-3)
     hbm = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None, "bytes_per_draw": bytes_per_draw}
+           "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(), "bytes_per_draw": bytes_per_draw}
     alu = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Top/s",
            "frac": achieved_ops / ALU_PEAK_OPS, "ops_per_draw": ops_per_draw}
     roof, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
     roof = dict(roof)
+    roof["traffic"] = measured_traffic()
     roof["kernel"] = "gen_persistent"
     roof["kernel_ms"] = kernel_ms
     roof["units_per_launch"] = total
@@ -344,6 +396,8 @@ def main():
         },
         "plain": plain,
         "with_ciphertexts": with_c,
+        "graph_replay": graph,
+        "unit_skip": unit,
         "roofline": roof,
         "roofline_other": other,
         "cpu_baseline": cpu,

@@ -77,7 +77,8 @@ typedef struct {
 typedef struct {
   int32_t block_threads;   /* 64, 128, 256 or 512 */
   int32_t blocks_per_cu;   /* resident blocks per compute unit for the persistent grid */
-  int32_t tiles_per_chunk; /* consecutive 2048-draw tiles a wave takes per work grab (1..64) */
+  int32_t tiles_per_chunk; /* consecutive 2048-draw tiles a wave takes per work grab (1..64);
+                              halved for batches too small to give every wave 4 grabs */
   int32_t unroll;          /* encryption-loop unroll: 1, 2 or 4 */
 } phprng_tuning;
 
@@ -131,6 +132,20 @@ const char *phprng_last_error(const phprng_ctx *ctx);
 phprng_status phprng_add_instances(phprng_ctx *ctx, uint64_t count, int width, const uint64_t *n, const uint64_t *e,
                                    const uint64_t *m0, const uint64_t *s0, const uint64_t *k0, uint32_t *ids);
 
+/* Add `count` instances that use the constant-skip schedule of Sec. II
+ * instead of the pseudorandom skip: m_k = (m_0 + k b) mod n, so the t-th draw
+ * from position k encrypts m_0 + (k + 1 + t) b (b = 1 is the unit skip, the
+ * counter mode of the cipher).  b[i] must lie in [1, n[i] - 1]; m0, k0 may be
+ * NULL (then 0).  Positions of these instances use the whole uint64 range
+ * for both widths; their skip s is b at every position. */
+phprng_status phprng_add_instances_skip(phprng_ctx *ctx, uint64_t count, int width, const uint64_t *n,
+                                        const uint64_t *e, const uint64_t *b, const uint64_t *m0, const uint64_t *k0,
+                                        uint32_t *ids);
+
+/* Schedule of instance `id`: *sched = 0 (pseudorandom skip) or 1 (constant
+ * skip), *b = its constant skip (0 for the pseudorandom skip). */
+phprng_status phprng_get_schedule(phprng_ctx *ctx, uint32_t id, int *sched, uint64_t *b);
+
 /* phprng_draw_instances followed by phprng_add_instances with m0 = 0, s0 = 1. */
 phprng_status phprng_seed_instances(phprng_ctx *ctx, uint64_t count, int width, uint64_t seed,
                                     const uint64_t *e_set, int e_len, uint64_t k_lo, uint64_t k_hi, uint32_t *ids);
@@ -164,7 +179,8 @@ phprng_status phprng_get_state(phprng_ctx *ctx, uint32_t id, phprng_state *out);
 phprng_status phprng_get_position(phprng_ctx *ctx, uint32_t id, uint64_t *k);
 
 /* Restore instance `id` to the state (st->m, st->s) reported at position
- * st->k (st->c is ignored).  Any s in [1, p-1] is accepted: the library finds
+ * st->k (st->c is ignored; for a constant-skip instance st->s must equal
+ * its b).  Any s in [1, p-1] is accepted: the library finds
  * t with a^t = s mod p by a Pohlig-Hellman discrete logarithm (p - 1 is
  * smooth for both skip moduli).  PHPRNG_E_RANGE for width 64 if t lies beyond
  * the supported position range. */

@@ -84,6 +84,9 @@ SIGNATURES = {
     "phprng_seed_instances": (ctypes.c_int, [_vp, _u64, ctypes.c_int, _u64, _pu64, ctypes.c_int, _u64, _u64,
                                              _pu32]),
     "phprng_instance_count": (_u64, [_vp]),
+    "phprng_add_instances_skip": (ctypes.c_int, [_vp, _u64, ctypes.c_int, _pu64, _pu64, _pu64, _pu64, _pu64,
+                                                 _pu32]),
+    "phprng_get_schedule": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int), _pu64]),
     "phprng_generate": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp, ctypes.c_int]),
     "phprng_jump": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_int64]),
     "phprng_get_state": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(phprng_state)]),
@@ -241,6 +244,29 @@ class Context:
         self._chk(lib().phprng_add_instances(self._h, count, width, pn, pe, args[0], args[1], args[2],
                                              ids.ctypes.data_as(_pu32)))
         return ids
+
+    def add_instances_skip(self, width, n, e, b, m0=None, k0=None):
+        """Instances with the constant skip b (b = 1: unit skip)."""
+        n, pn = _u64arr(n)
+        e, pe = _u64arr(e)
+        bb, pb = _u64arr(b)
+        keep, args = [], []
+        for v in (m0, k0):
+            if v is None:
+                args.append(None)
+            else:
+                a, pa = _u64arr(v)
+                keep.append(a)
+                args.append(pa)
+        ids = np.zeros(n.size, dtype=np.uint32)
+        self._chk(lib().phprng_add_instances_skip(self._h, n.size, width, pn, pe, pb, args[0], args[1],
+                                                  ids.ctypes.data_as(_pu32)))
+        return ids
+
+    def get_schedule(self, inst):
+        s, b = ctypes.c_int(), _u64()
+        self._chk(lib().phprng_get_schedule(self._h, int(inst), ctypes.byref(s), ctypes.byref(b)))
+        return s.value, b.value
 
     def seed_instances(self, width, seed, count, e_set=(9, 17), k_lo=0, k_hi=0):
         es, pes = _u64arr(e_set)

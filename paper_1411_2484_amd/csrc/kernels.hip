@@ -91,7 +91,8 @@ __global__ void __launch_bounds__(1024) plan_kernel(const InstRec *inst, ReqRec 
   uint64_t local = 0;
   for (uint64_t r = lo; r < hi; ++r) {
     ReqRec q = req[r];
-    bool w64 = inst[q.inst].width == 64;
+    const InstRec &I = inst[q.inst];
+    bool w64 = I.width == 64 || I.sched == kSchedConstant;  // no skip period to respect
     uint64_t g1 = 0, nt = 0;
     if (q.count > 0) {
       g1 = tile_of(q.k, w64);
@@ -365,6 +366,136 @@ __device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R,
   }
 }
 
+// ---------------------------------------------------------------------------
+// constant / unit skip (Sec. II): m at state index x is mbase + x b mod n, so
+// lane l of a tile starts at state x0 + 1 + l and steps by 64 b mod n; no
+// skip generator, no prefix, no LDS.
+// ---------------------------------------------------------------------------
+
+template <int UNROLL, int EK, int OUT, bool MASKED>
+__device__ __forceinline__ void passCS32(uint32_t m, uint32_t step, uint32_t lane, const Enc32 &K, uint32_t *c32,
+                                         double *rr, uint32_t t_lo, uint32_t t_hi) {
+  const uint32_t span = t_hi - t_lo;
+#pragma unroll UNROLL
+  for (int i = 0; i < kRun; ++i) {
+    if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
+      const uint32_t c = dev::encrypt32<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
+      if (OUT & kOutC) c32[i * 64] = c;
+      if (OUT & kOutR) rr[i * 64] = dev::uniform32(c, K.den, K.rcp);
+    }
+    m = dev::addmod32(m, step, K.n);
+  }
+}
+
+template <int UNROLL, int EK, bool MASKED>
+__device__ __forceinline__ void passCS32_out(uint32_t m, uint32_t step, uint32_t lane, const Enc32 &K,
+                                             uint32_t *c32, double *rr, uint32_t t_lo, uint32_t t_hi) {
+  if (c32 && rr) passCS32<UNROLL, EK, kOutC | kOutR, MASKED>(m, step, lane, K, c32, rr, t_lo, t_hi);
+  else if (rr) passCS32<UNROLL, EK, kOutR, MASKED>(m, step, lane, K, c32, rr, t_lo, t_hi);
+  else if (c32) passCS32<UNROLL, EK, kOutC, MASKED>(m, step, lane, K, c32, rr, t_lo, t_hi);
+}
+
+template <int UNROLL, bool MASKED>
+__device__ __forceinline__ void passCS32_e(int ekind, uint32_t m, uint32_t step, uint32_t lane, const Enc32 &K,
+                                           uint32_t *c32, double *rr, uint32_t t_lo, uint32_t t_hi) {
+  switch (ekind) {
+    case 9: passCS32_out<UNROLL, 9, MASKED>(m, step, lane, K, c32, rr, t_lo, t_hi); break;
+    case 17: passCS32_out<UNROLL, 17, MASKED>(m, step, lane, K, c32, rr, t_lo, t_hi); break;
+    case 3: passCS32_out<UNROLL, 3, MASKED>(m, step, lane, K, c32, rr, t_lo, t_hi); break;
+    case 5: passCS32_out<UNROLL, 5, MASKED>(m, step, lane, K, c32, rr, t_lo, t_hi); break;
+    default: passCS32_out<UNROLL, 0, MASKED>(m, step, lane, K, c32, rr, t_lo, t_hi); break;
+  }
+}
+
+template <int UNROLL>
+__device__ void run_chunk32_cs(const GenArgs &A, const InstRec &I, const ReqRec &R, uint64_t chunk, uint32_t lane) {
+  const uint32_t n = (uint32_t)I.n, ninv = (uint32_t)I.ninv;
+  const Enc32 K{n, ninv, (uint32_t)I.kcorr, I.e, (int)I.ebits, I.den, I.rcp};
+  const uint32_t bR2 = (uint32_t)I.bR2, step = (uint32_t)I.b64, mbase = (uint32_t)I.mbase;
+  const uint64_t g_begin = R.g1 + chunk * A.tiles_per_chunk;
+  const uint64_t g_end = min(g_begin + A.tiles_per_chunk, R.g1 + R.ntiles);
+  for (uint64_t g = g_begin; g < g_end; ++g) {
+    const uint64_t x0 = g * kTile;
+    // lane's first state index v = x0 + 1 + lane; v b mod n by Montgomery:
+    // bring hi(v) below n, then REDC(v) times b R^2
+    const uint64_t v = x0 + 1 + lane;
+    uint32_t vh = (uint32_t)(v >> 32);
+    vh = vh >= n ? vh - n : vh;
+    const uint64_t vr = ((uint64_t)vh << 32) | (uint32_t)v;
+    const uint32_t m = dev::addmod32(mbase, dev::mont32(dev::redc32(vr, n, ninv), bR2, n, ninv), n);
+    const uint64_t req_end = R.k + R.count;
+    const uint32_t t_lo = R.k > x0 ? (uint32_t)(R.k - x0) : 0u;
+    const uint32_t t_hi = (uint32_t)min(req_end - x0, (uint64_t)kTile);
+    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.k) + (int64_t)lane;
+    uint32_t *c32 = A.out_c32 ? A.out_c32 + base : nullptr;
+    double *rr = A.out_r ? A.out_r + base : nullptr;
+    if (t_lo == 0 && t_hi == (uint32_t)kTile)
+      passCS32_e<UNROLL, false>((int)I.ekind, m, step, lane, K, c32, rr, t_lo, t_hi);
+    else
+      passCS32_e<1, true>((int)I.ekind, m, step, lane, K, c32, rr, t_lo, t_hi);
+  }
+}
+
+template <int UNROLL, int EK, int OUT, bool MASKED>
+__device__ __forceinline__ void passCS64(uint64_t m, uint64_t step, uint32_t lane, const Enc64 &K, uint64_t *c64,
+                                         double *rr, uint32_t t_lo, uint32_t t_hi) {
+  const uint32_t span = t_hi - t_lo;
+#pragma unroll UNROLL
+  for (int i = 0; i < kRun; ++i) {
+    if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
+      const uint64_t c = dev::encrypt64<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
+      if (OUT & kOutC) c64[i * 64] = c;
+      if (OUT & kOutR) rr[i * 64] = dev::uniform64(c, K.den);
+    }
+    m = dev::addmod64(m, step, K.n);
+  }
+}
+
+template <int UNROLL, int EK, bool MASKED>
+__device__ __forceinline__ void passCS64_out(uint64_t m, uint64_t step, uint32_t lane, const Enc64 &K,
+                                             uint64_t *c64, double *rr, uint32_t t_lo, uint32_t t_hi) {
+  if (c64 && rr) passCS64<UNROLL, EK, kOutC | kOutR, MASKED>(m, step, lane, K, c64, rr, t_lo, t_hi);
+  else if (rr) passCS64<UNROLL, EK, kOutR, MASKED>(m, step, lane, K, c64, rr, t_lo, t_hi);
+  else if (c64) passCS64<UNROLL, EK, kOutC, MASKED>(m, step, lane, K, c64, rr, t_lo, t_hi);
+}
+
+template <int UNROLL, bool MASKED>
+__device__ __forceinline__ void passCS64_e(int ekind, uint64_t m, uint64_t step, uint32_t lane, const Enc64 &K,
+                                           uint64_t *c64, double *rr, uint32_t t_lo, uint32_t t_hi) {
+  switch (ekind) {
+    case 9: passCS64_out<UNROLL, 9, MASKED>(m, step, lane, K, c64, rr, t_lo, t_hi); break;
+    case 17: passCS64_out<UNROLL, 17, MASKED>(m, step, lane, K, c64, rr, t_lo, t_hi); break;
+    case 3: passCS64_out<UNROLL, 3, MASKED>(m, step, lane, K, c64, rr, t_lo, t_hi); break;
+    case 5: passCS64_out<UNROLL, 5, MASKED>(m, step, lane, K, c64, rr, t_lo, t_hi); break;
+    default: passCS64_out<UNROLL, 0, MASKED>(m, step, lane, K, c64, rr, t_lo, t_hi); break;
+  }
+}
+
+template <int UNROLL>
+__device__ void run_chunk64_cs(const GenArgs &A, const InstRec &I, const ReqRec &R, uint64_t chunk, uint32_t lane) {
+  const uint64_t n = I.n, ninv = I.ninv;
+  const Enc64 K{n, ninv, I.kcorr, I.e, (int)I.ebits, I.den};
+  const uint64_t g_begin = R.g1 + chunk * A.tiles_per_chunk;
+  const uint64_t g_end = min(g_begin + A.tiles_per_chunk, R.g1 + R.ntiles);
+  for (uint64_t g = g_begin; g < g_end; ++g) {
+    const uint64_t x0 = g * kTile;
+    dev::W128 v;
+    v.lo = x0 + 1 + lane;  // hi word 0 < n, so REDC applies
+    v.hi = 0;
+    const uint64_t m = dev::addmod64(I.mbase, dev::mont64(dev::redc64(v, n, ninv), I.bR2, n, ninv), n);
+    const uint64_t req_end = R.k + R.count;
+    const uint32_t t_lo = R.k > x0 ? (uint32_t)(R.k - x0) : 0u;
+    const uint32_t t_hi = (uint32_t)min(req_end - x0, (uint64_t)kTile);
+    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.k) + (int64_t)lane;
+    uint64_t *c64 = A.out_c64 ? A.out_c64 + base : nullptr;
+    double *rr = A.out_r ? A.out_r + base : nullptr;
+    if (t_lo == 0 && t_hi == (uint32_t)kTile)
+      passCS64_e<UNROLL, false>((int)I.ekind, m, I.b64, lane, K, c64, rr, t_lo, t_hi);
+    else
+      passCS64_e<1, true>((int)I.ekind, m, I.b64, lane, K, c64, rr, t_lo, t_hi);
+  }
+}
+
 // Wave-cooperative search: the request r with chunk_base[r] <= c < chunk_base[r+1]
 // (the last such r when empty requests share a base).
 __device__ __forceinline__ uint64_t find_request(const ReqRec *req, uint64_t nreq, uint64_t c, uint32_t lane) {
@@ -395,20 +526,28 @@ __global__ void __launch_bounds__(BLOCK) gen_persistent(GenArgs A) {
   const uint32_t wave = threadIdx.x / 64;
   LT *L = lds[wave];
   const uint64_t total = dev::uniform_u64(A.hdr->total_chunks);
+  // The first chunk of every wave is its global wave index; later chunks come
+  // from the shared counter, offset by the number of waves.  Small batches
+  // therefore need no atomics, and large ones avoid the start-up burst.
+  const uint32_t nwaves = gridDim.x * (BLOCK / 64);
+  uint64_t c = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
   for (;;) {
-    uint32_t c = 0;
-    if (lane == 0) c = atomicAdd(&A.hdr->counter, 1u);
-    c = dev::uniform_u32((uint32_t)__shfl((int)c, 0, 64));
     if (c >= total) break;
     const uint64_t r = dev::uniform_u64(find_request(A.req, A.nreq, c, lane));
     const ReqRec R = A.req[r];
     const InstRec &I = A.inst[R.inst];
     const uint64_t chunk = c - R.chunk_base;
-    if (HAS64 && I.width == 64) {
+    if (I.sched == kSchedConstant) {
+      if (HAS64 && I.width == 64) run_chunk64_cs<UNROLL>(A, I, R, chunk, lane);
+      else run_chunk32_cs<UNROLL>(A, I, R, chunk, lane);
+    } else if (HAS64 && I.width == 64) {
       run_chunk64<UNROLL>(A, I, R, chunk, reinterpret_cast<uint64_t *>(L), lane);
     } else {
       run_chunk32<UNROLL>(A, I, R, chunk, reinterpret_cast<uint32_t *>(L), lane);
     }
+    uint32_t next = 0;
+    if (lane == 0) next = atomicAdd(&A.hdr->counter, 1u);
+    c = (uint64_t)nwaves + dev::uniform_u32((uint32_t)__shfl((int)next, 0, 64));
   }
 }
 
@@ -421,7 +560,10 @@ __global__ void __launch_bounds__(64) gen_plain(GenArgs A, uint64_t r) {
   const ReqRec R = A.req[r];
   if ((uint64_t)blockIdx.x >= R.nchunks) return;
   const InstRec &I = A.inst[R.inst];
-  if (HAS64 && I.width == 64) {
+  if (I.sched == kSchedConstant) {
+    if (HAS64 && I.width == 64) run_chunk64_cs<UNROLL>(A, I, R, blockIdx.x, lane);
+    else run_chunk32_cs<UNROLL>(A, I, R, blockIdx.x, lane);
+  } else if (HAS64 && I.width == 64) {
     run_chunk64<UNROLL>(A, I, R, blockIdx.x, reinterpret_cast<uint64_t *>(lds), lane);
   } else {
     run_chunk32<UNROLL>(A, I, R, blockIdx.x, reinterpret_cast<uint32_t *>(lds), lane);

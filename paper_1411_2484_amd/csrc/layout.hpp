@@ -37,9 +37,17 @@ struct alignas(128) InstRec {
   uint32_t width;  // 32 or 64
   uint32_t ekind;  // 3, 5, 9, 17, or 0 for the generic chain
   uint32_t ebits;  // bit length of e
-  uint32_t pad0;
-  uint64_t pad1[4];
+  uint32_t sched;  // kSchedSkipLcg or kSchedConstant
+  uint64_t bskip;  // constant skip b mod n
+  uint64_t bR2;    // b R^2 mod n
+  uint64_t b64;    // 64 b mod n (one lane-interleaved step)
+  uint64_t pad1;
 };
+
+// Message schedules (Sec. II): the pseudorandom skip of eq. (5)-(7), or a
+// constant skip b (the unit skip is b = 1) with m_k = m_0 + k b mod n.
+constexpr uint32_t kSchedSkipLcg = 0;
+constexpr uint32_t kSchedConstant = 1;
 static_assert(sizeof(InstRec) == 128, "InstRec must be one 128-byte line");
 
 // Device request record.  The host fills inst, k, count, out_off; the plan

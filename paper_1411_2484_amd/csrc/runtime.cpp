@@ -26,9 +26,11 @@ namespace {
 struct HostInst {
   uint64_t n, e;
   int width;
-  uint64_t mbase;  // m at internal index x = mbase + q p(p-1)/2 + U(r) mod n
+  uint64_t mbase;  // m at internal index x = mbase + q p(p-1)/2 + U(r) mod n (constant skip: mbase + x b)
   uint64_t x;      // internal index of the current state
   int64_t kofs;    // reported position k = x - kofs
+  uint32_t sched = kSchedSkipLcg;
+  uint64_t b = 0;  // constant skip
 };
 
 const SkipGroup &group(int width) {
@@ -105,7 +107,7 @@ struct phprng_ctx {
   double acc_ms = 0;        // cumulative kernel time of recycled slots
   uint64_t acc_calls = 0;
   ReqRec *h_req = nullptr;  // staging array of the slot being prepared
-  phprng_tuning tuning{256, 4, 4, 2};
+  phprng_tuning tuning{256, 4, 8, 4};
   std::string err;
 
   phprng_status fail(phprng_status st, const char *fmt, ...) {
@@ -136,8 +138,15 @@ struct phprng_ctx {
     *S = s;
   }
 
-  // State (m, s) at internal index x of instance h (eq. (7)).
+  // State (m, s) at internal index x of instance h (eq. (7); constant skip:
+  // m = m_0 + x b, s = b).
   void state_at(const HostInst &h, uint64_t x, uint64_t *m, uint64_t *s) const {
+    if (h.sched == kSchedConstant) {
+      Mont64 M(h.n);
+      *m = M.add(h.mbase % h.n, M.mulmod(x % h.n, h.b));
+      *s = h.b;
+      return;
+    }
     const SkipGroup &G = group(h.width);
     const uint64_t pm1 = G.p - 1;
     const uint64_t q = x / pm1, r = x % pm1;
@@ -150,7 +159,9 @@ struct phprng_ctx {
     *m = M.add(M.add(h.mbase % h.n, M.reduce128(U)), qb);
   }
 
-  uint64_t max_index(int width) const { return width == 32 ? ~0ull : kMaxPos64; }
+  uint64_t max_index(const HostInst &h) const {
+    return (h.width == 32 || h.sched == kSchedConstant) ? ~0ull : kMaxPos64;
+  }
 
   InstRec make_record(const HostInst &h) const {
     InstRec rec;
@@ -165,6 +176,14 @@ struct phprng_ctx {
     const u128 full = ((u128)G.p * (G.p - 1)) / 2;
     const uint64_t b = M.reduce128(full);
     rec.mbase = h.mbase;
+    rec.sched = h.sched;
+    if (h.sched == kSchedConstant) {
+      const uint64_t R = h.width == 32 ? (1ull << 32) % h.n : M.r1;
+      const uint64_t R2 = M.mulmod(R, R);
+      rec.bskip = h.b;
+      rec.bR2 = M.mulmod(h.b, R2);
+      rec.b64 = M.mulmod(64 % h.n, h.b);
+    }
     if (h.width == 32) {
       const uint32_t n32 = (uint32_t)h.n;
       uint32_t inv = n32;
@@ -510,6 +529,46 @@ extern "C" phprng_status phprng_seed_instances(phprng_ctx *c, uint64_t count, in
   return phprng_add_instances(c, count, width, n.data(), e.data(), nullptr, nullptr, k.data(), ids);
 }
 
+extern "C" phprng_status phprng_add_instances_skip(phprng_ctx *c, uint64_t count, int width, const uint64_t *n,
+                                                   const uint64_t *e, const uint64_t *b, const uint64_t *m0,
+                                                   const uint64_t *k0, uint32_t *ids) {
+  if (!c || !width_ok(width)) return PHPRNG_E_INVALID;
+  if (count == 0) return PHPRNG_OK;
+  if (!n || !e || !b || !ids) return c->fail(PHPRNG_E_INVALID, "null array");
+  if (c->inst.size() + count > c->max_instances) return c->fail(PHPRNG_E_RANGE, "instance table full");
+  hipSetDevice(c->device);
+  std::vector<HostInst> add(count);
+  std::vector<InstRec> recs(count);
+  for (uint64_t i = 0; i < count; ++i) {
+    phprng_status st = check_instance_impl(width, n[i], e[i]);
+    if (st != PHPRNG_OK) return c->fail(st, "instance %llu rejected", (unsigned long long)i);
+    const uint64_t mm0 = m0 ? m0[i] : 0;
+    if (b[i] == 0 || b[i] >= n[i] || mm0 >= n[i])
+      return c->fail(PHPRNG_E_INVALID, "bad skip or m0 at %llu", (unsigned long long)i);
+    HostInst h{n[i], e[i], width, mm0, k0 ? k0[i] : 0, 0};
+    h.sched = kSchedConstant;
+    h.b = b[i];
+    add[i] = h;
+    recs[i] = c->make_record(h);
+  }
+  const uint64_t base = c->inst.size();
+  hipError_t he = hipMemcpy(c->d_inst + base, recs.data(), count * sizeof(InstRec), hipMemcpyHostToDevice);
+  if (he != hipSuccess) return c->hip_fail(he, "instance upload");
+  for (uint64_t i = 0; i < count; ++i) {
+    c->inst.push_back(add[i]);
+    ids[i] = (uint32_t)(base + i);
+  }
+  return PHPRNG_OK;
+}
+
+extern "C" phprng_status phprng_get_schedule(phprng_ctx *c, uint32_t id, int *sched, uint64_t *b) {
+  if (!c || id >= c->inst.size()) return PHPRNG_E_INVALID;
+  const HostInst &h = c->inst[id];
+  if (sched) *sched = (int)h.sched;
+  if (b) *b = h.b;
+  return PHPRNG_OK;
+}
+
 namespace {
 
 // Validate a request list and reserve positions.  Fills the slot's staging
@@ -543,7 +602,7 @@ phprng_status prepare_requests(phprng_ctx *c, const phprng_request *reqs, uint64
       cur.push_back(h.x);
     }
     uint64_t &x = cur[(size_t)where[r.instance]];
-    if (r.count > c->max_index(h.width) - x)
+    if (r.count > c->max_index(h) - x)
       return c->fail(PHPRNG_E_RANGE, "request %llu: position beyond range", (unsigned long long)i);
     x += r.count;
   }
@@ -601,7 +660,15 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
   if (st != PHPRNG_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const phprng_tuning &T = c->tuning;
-  const uint32_t tpc = mode == PHPRNG_MODE_PLAIN ? 1u : (uint32_t)T.tiles_per_chunk;
+  uint32_t tpc = mode == PHPRNG_MODE_PLAIN ? 1u : (uint32_t)T.tiles_per_chunk;
+  // Upper bound on the tiles of the batch (a request touches at most
+  // count / 2048 + 2 tiles, one more at a skip-period boundary).
+  uint64_t tiles = 0;
+  for (uint64_t i = 0; i < nreq; ++i)
+    tiles += slot->h_req[i].count ? slot->h_req[i].count / kTile + 3 : 0;
+  const uint64_t waves = (uint64_t)c->num_cus * T.blocks_per_cu * (T.block_threads / 64);
+  // Small batches: shrink the chunk so that every resident wave gets work.
+  while (tpc > 1 && tiles < 4 * waves * tpc) tpc >>= 1;
   hipError_t e = hipMemcpyAsync(slot->d_req, slot->h_req, nreq * sizeof(ReqRec), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return c->hip_fail(e, "request upload");
   if ((e = launch_plan(c->d_inst, slot->d_req, nreq, slot->d_hdr, tpc, s)) != hipSuccess)
@@ -609,7 +676,11 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
   GenArgs A = make_args(c, slot->d_req, slot->d_hdr, nreq, out_c32, out_c64, out_r, tpc);
   if ((e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
   if (mode == PHPRNG_MODE_PERSISTENT) {
-    const unsigned grid = (unsigned)(c->num_cus * T.blocks_per_cu);
+    // no more blocks than the batch can keep busy
+    const uint64_t wpb = (uint64_t)T.block_threads / 64;
+    const uint64_t need = (tiles + tpc - 1) / tpc;
+    const unsigned grid = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)c->num_cus * T.blocks_per_cu, (need + wpb - 1) / wpb));
     e = launch_persistent(A, grid, T.block_threads, T.unroll, has64, s);
     if (e != hipSuccess) return c->hip_fail(e, "persistent launch");
   } else {
@@ -708,7 +779,7 @@ extern "C" phprng_status phprng_jump(phprng_ctx *c, uint32_t id, int64_t delta) 
     h.x -= d;
   } else {
     const uint64_t d = (uint64_t)delta;
-    if (d > c->max_index(h.width) - h.x) return c->fail(PHPRNG_E_RANGE, "jump beyond range");
+    if (d > c->max_index(h) - h.x) return c->fail(PHPRNG_E_RANGE, "jump beyond range");
     h.x += d;
   }
   return PHPRNG_OK;
@@ -717,6 +788,20 @@ extern "C" phprng_status phprng_jump(phprng_ctx *c, uint32_t id, int64_t delta) 
 extern "C" phprng_status phprng_set_state(phprng_ctx *c, uint32_t id, const phprng_state *st) {
   if (!c || !st || id >= c->inst.size()) return PHPRNG_E_INVALID;
   HostInst &h = c->inst[id];
+  if (h.sched == kSchedConstant) {
+    if (st->m >= h.n || st->s != h.b) return c->fail(PHPRNG_E_INVALID, "bad state for a constant skip");
+    Mont64 M(h.n);
+    HostInst tmp = h;
+    tmp.mbase = M.sub(st->m, M.mulmod(st->k % h.n, h.b));
+    InstRec rec = c->make_record(tmp);
+    hipSetDevice(c->device);
+    hipError_t e = hipMemcpy(c->d_inst + id, &rec, sizeof rec, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return c->hip_fail(e, "instance upload");
+    h.mbase = tmp.mbase;
+    h.x = st->k;
+    h.kofs = 0;
+    return PHPRNG_OK;
+  }
   const SkipGroup &G = group(h.width);
   if (st->m >= h.n || st->s == 0 || st->s >= G.p) return c->fail(PHPRNG_E_INVALID, "bad state");
   const uint64_t pm1 = G.p - 1;
@@ -901,7 +986,7 @@ extern "C" phprng_status phprng_graph_launch(phprng_graph *g, void *stream) {
   // range check before launching: each instance advances by its count
   for (size_t i = 0; i < g->inst.size(); ++i) {
     const HostInst &h = c->inst[g->inst[i]];
-    if (g->count[i] > c->max_index(h.width) - h.x) return c->fail(PHPRNG_E_RANGE, "graph launch beyond range");
+    if (g->count[i] > c->max_index(h) - h.x) return c->fail(PHPRNG_E_RANGE, "graph launch beyond range");
   }
   hipStream_t s = (hipStream_t)stream;
   phprng_ctx::Slot *slot = nullptr;

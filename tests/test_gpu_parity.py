@@ -417,3 +417,53 @@ def test_mixed_full_size_sampled(ph, orc, tabs):
         got = int(x32) if w == 32 else int(x64)
         assert got == int(wc[0]) and float(y) == float(wr[0]), (i, t, w)
     ctx.close()
+
+
+def _cskip_expected(orc, n, e, b, m0, k, count):
+    m = orc.cskip_message(n, m0, b, k)
+    c, r, _ = orc.generate_cskip(n, e, b, m, count)
+    return c, r
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_constant_and_unit_skip_instances(ph, ctx, orc, tabs, mode):
+    """Instances on the constant-skip schedule (unit skip b = 1 included),
+    both widths, mixed with pseudorandom-skip instances in one batch."""
+    rng = random.Random(800 + mode)
+    n32, e32, _ = orc.seed(32, SEED0 + 120 + mode, 6, (9, 17, 3, 5))
+    n64, e64, _ = orc.seed(64, SEED0 + 122 + mode, 4, (9, 17, 3))
+    b32 = [1, 2] + [rng.randrange(1, int(n)) for n in n32[2:]]
+    b64 = [1] + [rng.randrange(1, int(n)) for n in n64[1:]]
+    m32 = [0, 5] + [rng.randrange(int(n)) for n in n32[2:]]
+    m64 = [rng.randrange(int(n)) for n in n64]
+    k32 = [0, 1, (1 << 63) + 12345, rng.randrange(1 << 62), 2 ** 32 - 1, rng.randrange(1 << 40)]
+    k64 = [0, (1 << 63) - 7, rng.randrange(1 << 50), 123]
+    i32 = ctx.add_instances_skip(32, n32, e32, b32, m0=m32, k0=k32)
+    i64 = ctx.add_instances_skip(64, n64, e64, b64, m0=m64, k0=k64)
+    nl, el, kl = orc.seed(32, SEED0 + 124 + mode, 3, (9, 17), 0, 1 << 40)
+    il = ctx.add_instances(32, nl, el, k0=kl)
+    ids = [int(i) for i in i32] + [int(i) for i in i64] + [int(i) for i in il]
+    counts = [rng.choice([1, 2047, 2048, 2049, 7000, rng.randrange(1, 9000)]) for _ in ids]
+    specs = list(zip(ids, counts))
+    (hc32, hc64, hr), offs = _run(ph, ctx, specs, mode=mode, gap=2, shuffle_seed=mode)
+    allp = ([(32, int(n), int(e), b, m, k) for n, e, b, m, k in zip(n32, e32, b32, m32, k32)] +
+            [(64, int(n), int(e), b, m, k) for n, e, b, m, k in zip(n64, e64, b64, m64, k64)])
+    for (iid, count), off, (w, n, e, b, m0, k) in zip(specs, offs, allp):
+        assert ctx.get_schedule(iid) == (1, b)
+        wc, wr = _cskip_expected(orc, n, e, b, m0, k, count)
+        compare_request(hc32 if w == 32 else hc64, hr, off, count, wc, wr, "cskip w%d b=%d" % (w, b))
+        # state after the draws
+        m, s, c, kk = ctx.get_state(iid)
+        assert (m, s, kk) == (orc.cskip_message(n, m0, b, k + count), b, k + count)
+        assert c == orc.encrypt(m, e, n)
+    _check(orc, tabs, ctx, specs[len(allp):], [int(k) for k in kl], (hc32, hc64, hr), offs[len(allp):], "lcg-mix")
+    # restore and jump on a constant-skip instance
+    iid, (w, n, e, b, m0, k) = ids[3], allp[3]
+    ctx.set_state(iid, 77, b, 10 ** 12)
+    ctx.jump(iid, -1000)
+    (hc32, _, hr), _ = _run(ph, ctx, [(iid, 5000)])
+    m_start = (77 - 1000 * b) % n
+    wc, wr = _cskip_expected(orc, n, e, b, m_start, 0, 5000)
+    compare_request(hc32, hr, 0, 5000, wc, wr, "cskip restored")
+    with pytest.raises(ph.PhprngError):
+        ctx.set_state(iid, 1, b + 1 if b + 1 < n else 1, 0)
