@@ -146,7 +146,10 @@ phprng_status phprng_add_instances_skip(phprng_ctx *ctx, uint64_t count, int wid
  * skip), *b = its constant skip (0 for the pseudorandom skip). */
 phprng_status phprng_get_schedule(phprng_ctx *ctx, uint32_t id, int *sched, uint64_t *b);
 
-/* phprng_draw_instances followed by phprng_add_instances with m0 = 0, s0 = 1. */
+/* Same result as phprng_draw_instances followed by phprng_add_instances with
+ * m0 = 0, s0 = 1.  For count >= 1024 the primality of the stream outputs is
+ * decided on the device (one deterministic Rabin-Miller per output) and the
+ * instance records are built there; the draw order is unchanged. */
 phprng_status phprng_seed_instances(phprng_ctx *ctx, uint64_t count, int width, uint64_t seed,
                                     const uint64_t *e_set, int e_len, uint64_t k_lo, uint64_t k_hi, uint32_t *ids);
 

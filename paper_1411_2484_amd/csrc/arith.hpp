@@ -212,6 +212,113 @@ __device__ __forceinline__ uint64_t powmod_p61(uint64_t b, uint64_t e) {
 // with one rounding).
 __device__ __forceinline__ double uniform64(uint64_t c, double den) { return (double)(c + 1) / den; }
 
+// ---- instance set-up on the device (seeding) --------------------------------
+
+__device__ __forceinline__ uint32_t inv32(uint32_t n) {  // n^{-1} mod 2^32, n odd (Newton)
+  uint32_t x = n;
+  for (int i = 0; i < 5; ++i) x *= 2u - n * x;
+  return x;
+}
+
+__device__ __forceinline__ uint64_t inv64(uint64_t n) {  // n^{-1} mod 2^64, n odd (Newton)
+  uint64_t x = n;
+  for (int i = 0; i < 6; ++i) x *= 2ull - n * x;
+  return x;
+}
+
+// Montgomery power: base and result in Montgomery form, one = R mod n.
+__device__ __forceinline__ uint32_t mpow32(uint32_t b, uint64_t e, uint32_t one, uint32_t n, uint32_t ninv) {
+  uint32_t r = one;
+  while (e) {
+    if (e & 1) r = mont32(r, b, n, ninv);
+    b = mont32(b, b, n, ninv);
+    e >>= 1;
+  }
+  return r;
+}
+
+__device__ __forceinline__ uint64_t mpow64(uint64_t b, uint64_t e, uint64_t one, uint64_t n, uint64_t ninv) {
+  uint64_t r = one;
+  while (e) {
+    if (e & 1) r = mont64(r, b, n, ninv);
+    b = mont64(b, b, n, ninv);
+    e >>= 1;
+  }
+  return r;
+}
+
+// Deterministic Rabin-Miller for odd n in [2^31, 2^32): prime bases 2..11
+// decide primality below 2^32 (Sec. IV).  No base is a multiple of n.
+__device__ inline bool is_prime32_dev(uint32_t n) {
+  const uint32_t ninv = inv32(n);
+  const uint32_t one = 0u - n;  // 2^32 mod n (n > 2^31)
+  uint32_t r2 = one;            // R^2 mod n: double R mod n 32 times
+  for (int i = 0; i < 32; ++i) r2 = addmod32(r2, r2, n);
+  const uint32_t mone = n - one;  // Montgomery form of n - 1
+  uint32_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++s;
+  }
+  const uint32_t bases[5] = {2, 3, 5, 7, 11};
+  for (int i = 0; i < 5; ++i) {
+    uint32_t x = mpow32(mont32(bases[i], r2, n, ninv), d, one, n, ninv);
+    if (x == one || x == mone) continue;
+    bool witness = true;
+    for (int j = 1; j < s; ++j) {
+      x = mont32(x, x, n, ninv);
+      if (x == mone) {
+        witness = false;
+        break;
+      }
+    }
+    if (witness) return false;
+  }
+  return true;
+}
+
+// Deterministic Rabin-Miller for odd n in [2^62, 2^63): the twelve prime
+// bases 2..37 decide primality below 2^64 (Sec. IV).
+__device__ inline bool is_prime64_dev(uint64_t n) {
+  const uint64_t ninv = inv64(n);
+  uint64_t one = 0ull - n;  // 2^64 - n, then reduce: 2^64 mod n
+  while (one >= n) one -= n;
+  uint64_t r2 = one;
+  for (int i = 0; i < 64; ++i) r2 = addmod64(r2, r2, n);
+  const uint64_t mone = n - one;
+  uint64_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++s;
+  }
+  const uint32_t bases[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (int i = 0; i < 12; ++i) {
+    uint64_t x = mpow64(mont64(bases[i], r2, n, ninv), d, one, n, ninv);
+    if (x == one || x == mone) continue;
+    bool witness = true;
+    for (int j = 1; j < s; ++j) {
+      x = mont64(x, x, n, ninv);
+      if (x == mone) {
+        witness = false;
+        break;
+      }
+    }
+    if (witness) return false;
+  }
+  return true;
+}
+
+// j-th output (j = 0, 1, ...) of the SplitMix64 stream started at `seed`
+// (Steele, Lea and Flood, 2014): the state after j+1 steps, finalised.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
+  uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // ---- wave helpers ---------------------------------------------------------
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }

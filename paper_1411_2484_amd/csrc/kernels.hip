@@ -68,6 +68,78 @@ __global__ void __launch_bounds__(256) table_segments64(uint64_t nseg, uint64_t 
 }
 
 // ---------------------------------------------------------------------------
+// instance seeding on the device
+// ---------------------------------------------------------------------------
+
+// flags[i] = 1 when output j0 + i of the seeding stream, read as a candidate
+// modulus (lo + x mod 2^w) | 1 of the width's range, is prime.
+__global__ void __launch_bounds__(256) seed_prime_flags(uint64_t seed, uint64_t j0, uint64_t count, int width,
+                                                        uint8_t *flags) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t x = dev::splitmix64_at(seed, j0 + i);
+  bool p;
+  if (width == 32) {
+    const uint32_t n = (uint32_t)((1ull << 31) + (x & ((1ull << 31) - 1))) | 1u;
+    p = dev::is_prime32_dev(n);
+  } else {
+    const uint64_t n = ((1ull << 62) + (x & ((1ull << 62) - 1))) | 1ull;
+    p = dev::is_prime64_dev(n);
+  }
+  flags[i] = p ? 1 : 0;
+}
+
+// Instance records for base-state instances (m_0 = 0, s_0 = 1) of one width:
+// the same constants the host computes (Montgomery inverse, R^2, R^e, the
+// full-period skip sum times R^2, binary64 n + 1 and its reciprocal).
+__global__ void __launch_bounds__(256) build_records(const uint64_t *n_arr, const uint64_t *e_arr, uint64_t count,
+                                                     int width, InstRec *out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t n = n_arr[i], e = e_arr[i];
+  InstRec rec;
+  memset(&rec, 0, sizeof rec);
+  rec.n = n;
+  rec.e = e;
+  rec.width = (uint32_t)width;
+  int eb = 0;
+  for (uint64_t v = e; v; v >>= 1) ++eb;
+  rec.ebits = (uint32_t)eb;
+  rec.ekind = (e == 3 || e == 5 || e == 9 || e == 17) ? (uint32_t)e : 0u;
+  rec.sched = kSchedSkipLcg;
+  rec.den = (double)(n + 1);
+  if (width == 32) {
+    const uint32_t n32 = (uint32_t)n, ninv = dev::inv32(n32);
+    const uint32_t one = 0u - n32;
+    uint32_t r2 = one;
+    for (int k = 0; k < 32; ++k) r2 = dev::addmod32(r2, r2, n32);
+    // R^e: the Montgomery power of R (Montgomery form R^2) is R^{e+1}; one more REDC
+    const uint32_t re1 = dev::mpow32(r2, e, one, n32, ninv);
+    rec.ninv = ninv;
+    rec.r2 = r2;
+    rec.kcorr = dev::mont32(re1, 1u, n32, ninv);
+    // p(p-1)/2 mod n, then times R^2: mont(b, R^3) with R^3 = mont(R^2, R^2)
+    const uint64_t full = ((uint64_t)kP32 * ((uint64_t)kP32 - 1)) / 2;
+    const uint32_t b = dev::mont32(dev::redc32(full, n32, ninv), r2, n32, ninv);
+    rec.br2 = dev::mont32(b, dev::mont32(r2, r2, n32, ninv), n32, ninv);
+    rec.rcp = 1.0 / (double)(n + 1);
+  } else {
+    const uint64_t ninv = dev::inv64(n);
+    uint64_t one = 0ull - n;
+    while (one >= n) one -= n;
+    uint64_t r2 = one;
+    for (int k = 0; k < 64; ++k) r2 = dev::addmod64(r2, r2, n);
+    const uint64_t re1 = dev::mpow64(r2, e, one, n, ninv);
+    rec.ninv = ninv;
+    rec.r2 = r2;
+    rec.kcorr = dev::mont64(re1, 1ull, n, ninv);
+    rec.br2 = 0;
+    rec.rcp = 1.0 / rec.den;
+  }
+  out[i] = rec;
+}
+
+// ---------------------------------------------------------------------------
 // planner
 // ---------------------------------------------------------------------------
 
@@ -584,6 +656,20 @@ hipError_t launch_table_segments64(uint64_t nseg, uint64_t *seg_lo, uint64_t *se
                                    hipStream_t st) {
   unsigned blocks = (unsigned)((nseg + 255) / 256);
   hipLaunchKernelGGL(table_segments64, dim3(blocks), dim3(256), 0, st, nseg, seg_lo, seg_hi, seg_start);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_prime_flags(uint64_t seed, uint64_t j0, uint64_t count, int width, uint8_t *flags,
+                                   hipStream_t st) {
+  unsigned blocks = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(seed_prime_flags, dim3(blocks), dim3(256), 0, st, seed, j0, count, width, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_records(const uint64_t *n, const uint64_t *e, uint64_t count, int width, InstRec *out,
+                                hipStream_t st) {
+  unsigned blocks = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(build_records, dim3(blocks), dim3(256), 0, st, n, e, count, width, out);
   return hipGetLastError();
 }
 

@@ -10,6 +10,10 @@ namespace phprng {
 hipError_t launch_table_segments32(uint64_t nseg, uint64_t *seg_sum, uint32_t *seg_start, hipStream_t st);
 hipError_t launch_table_segments64(uint64_t nseg, uint64_t *seg_lo, uint64_t *seg_hi, uint64_t *seg_start,
                                    hipStream_t st);
+hipError_t launch_seed_prime_flags(uint64_t seed, uint64_t j0, uint64_t count, int width, uint8_t *flags,
+                                   hipStream_t st);
+hipError_t launch_build_records(const uint64_t *n, const uint64_t *e, uint64_t count, int width, InstRec *out,
+                                hipStream_t st);
 hipError_t launch_plan(const InstRec *inst, ReqRec *req, uint64_t nreq, PlanHdr *hdr, uint32_t tiles_per_chunk,
                        hipStream_t st);
 hipError_t launch_advance(ReqRec *req, uint64_t nreq, hipStream_t st);

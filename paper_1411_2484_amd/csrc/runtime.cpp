@@ -519,14 +519,124 @@ extern "C" phprng_status phprng_add_instances(phprng_ctx *c, uint64_t count, int
   return PHPRNG_OK;
 }
 
+namespace {
+
+bool exponent_ok(uint64_t n, uint64_t e) { return e >= 3 && gcd64(e, n - 1) == 1 && e % (n - 1) != 1; }
+
+// The seeding draw of phprng_draw_instances with the primality of every
+// stream output decided on the device (one deterministic Rabin-Miller per
+// output, in batches); the walk over the stream stays on the host and
+// consumes outputs in exactly the same order.
+phprng_status draw_on_device(phprng_ctx *c, int width, uint64_t seed, uint64_t count, const uint64_t *e_set,
+                             int e_len, uint64_t k_lo, uint64_t k_hi, uint64_t *n_out, uint64_t *e_out,
+                             uint64_t *k_out) {
+  const uint64_t lo = width == 32 ? (1ull << 31) : (1ull << 62);
+  const uint64_t span = lo;
+  std::vector<uint8_t> flags;
+  uint8_t *d_flags = nullptr;
+  uint64_t d_cap = 0;
+  auto extend = [&](uint64_t want) -> phprng_status {
+    const uint64_t j0 = flags.size();
+    const uint64_t nb = std::max<uint64_t>(want, 1ull << 20);
+    if (nb > d_cap) {
+      if (d_flags) hipFree(d_flags);
+      d_flags = nullptr;
+      hipError_t e = hipMalloc(&d_flags, nb);
+      if (e != hipSuccess) return c->hip_fail(e, "seed flags");
+      d_cap = nb;
+    }
+    hipError_t e = launch_seed_prime_flags(seed, j0, nb, width, d_flags, nullptr);
+    if (e != hipSuccess) return c->hip_fail(e, "seed launch");
+    flags.resize(j0 + nb);
+    e = hipMemcpy(flags.data() + j0, d_flags, nb, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return c->hip_fail(e, "seed copy");
+    return PHPRNG_OK;
+  };
+  const uint64_t per = width == 32 ? 14 : 26;  // expected stream outputs per instance, with margin
+  phprng_status st = extend(count * per + count / 4 + 1024);
+  std::unordered_set<uint64_t> seen;
+  seen.reserve(count * 2 + 16);
+  uint64_t sm = seed, j = 0;
+  for (uint64_t i = 0; i < count && st == PHPRNG_OK; ++i) {
+    for (;;) {
+      if (j + 3 > flags.size()) {
+        st = extend(flags.size() / 4 + 1024);
+        if (st != PHPRNG_OK) break;
+      }
+      const uint64_t x = splitmix64(sm);
+      const bool prime = flags[j++] != 0;
+      const uint64_t n = (lo + x % span) | 1ull;
+      if (!prime || seen.count(n)) continue;
+      const uint64_t y = splitmix64(sm);
+      ++j;
+      uint64_t chosen = 0;
+      for (int t = 0; t < e_len; ++t) {
+        const uint64_t cand = e_set[(y % (uint64_t)e_len + (uint64_t)t) % (uint64_t)e_len];
+        if (exponent_ok(n, cand)) {
+          chosen = cand;
+          break;
+        }
+      }
+      if (chosen == 0) continue;
+      seen.insert(n);
+      n_out[i] = n;
+      e_out[i] = chosen;
+      break;
+    }
+    if (k_hi > k_lo) {
+      k_out[i] = k_lo + splitmix64(sm) % (k_hi - k_lo);
+      ++j;
+    } else {
+      k_out[i] = k_lo;
+    }
+  }
+  if (d_flags) hipFree(d_flags);
+  return st;
+}
+
+}  // namespace
+
 extern "C" phprng_status phprng_seed_instances(phprng_ctx *c, uint64_t count, int width, uint64_t seed,
                                                const uint64_t *e_set, int e_len, uint64_t k_lo, uint64_t k_hi,
                                                uint32_t *ids) {
   if (!c) return PHPRNG_E_INVALID;
+  if (count < 1024) {
+    std::vector<uint64_t> n(count), e(count), k(count);
+    phprng_status st =
+        phprng_draw_instances(width, seed, count, e_set, e_len, k_lo, k_hi, n.data(), e.data(), k.data());
+    if (st != PHPRNG_OK) return c->fail(st, "instance draw failed");
+    return phprng_add_instances(c, count, width, n.data(), e.data(), nullptr, nullptr, k.data(), ids);
+  }
+  // Large draws: primality on the device, records built on the device.
+  if (!width_ok(width) || !e_set || e_len <= 0 || k_hi < k_lo || !ids) return c->fail(PHPRNG_E_INVALID, "seed args");
+  bool any = false;
+  for (int i = 0; i < e_len; ++i) any = any || e_set[i] >= 3;
+  if (!any) return c->fail(PHPRNG_E_EXPONENT, "no admissible exponent in the set");
+  if (c->inst.size() + count > c->max_instances) return c->fail(PHPRNG_E_RANGE, "instance table full");
+  if (width == 64 && k_hi > kMaxPos64) return c->fail(PHPRNG_E_RANGE, "width-64 start beyond the supported range");
+  hipSetDevice(c->device);
   std::vector<uint64_t> n(count), e(count), k(count);
-  phprng_status st = phprng_draw_instances(width, seed, count, e_set, e_len, k_lo, k_hi, n.data(), e.data(), k.data());
-  if (st != PHPRNG_OK) return c->fail(st, "instance draw failed");
-  return phprng_add_instances(c, count, width, n.data(), e.data(), nullptr, nullptr, k.data(), ids);
+  phprng_status st = draw_on_device(c, width, seed, count, e_set, e_len, k_lo, k_hi, n.data(), e.data(), k.data());
+  if (st != PHPRNG_OK) return st;
+  if (width == 64 && !c->have64) {
+    st = c->build_table64();
+    if (st != PHPRNG_OK) return st;
+  }
+  uint64_t *d_ne = nullptr;
+  hipError_t he = hipMalloc(&d_ne, 2 * count * sizeof(uint64_t));
+  if (he != hipSuccess) return c->hip_fail(he, "seed records");
+  const uint64_t base = c->inst.size();
+  he = hipMemcpy(d_ne, n.data(), count * 8, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(d_ne + count, e.data(), count * 8, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = launch_build_records(d_ne, d_ne + count, count, width, c->d_inst + base, nullptr);
+  if (he == hipSuccess) he = hipDeviceSynchronize();
+  hipFree(d_ne);
+  if (he != hipSuccess) return c->hip_fail(he, "seed records");
+  for (uint64_t i = 0; i < count; ++i) {
+    c->inst.push_back(HostInst{n[i], e[i], width, 0, k[i], 0});
+    ids[i] = (uint32_t)(base + i);
+  }
+  return PHPRNG_OK;
 }
 
 extern "C" phprng_status phprng_add_instances_skip(phprng_ctx *c, uint64_t count, int width, const uint64_t *n,

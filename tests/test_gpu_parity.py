@@ -467,3 +467,26 @@ def test_constant_and_unit_skip_instances(ph, ctx, orc, tabs, mode):
     compare_request(hc32, hr, 0, 5000, wc, wr, "cskip restored")
     with pytest.raises(ph.PhprngError):
         ctx.set_state(iid, 1, b + 1 if b + 1 < n else 1, 0)
+
+
+@pytest.mark.parametrize("width,count,es,klo,khi", [(32, 5000, (9, 17), 0, 1 << 40), (64, 1500, (9, 17, 3), 0, 1 << 30),
+                                                     (32, 2048, (3, 5, 7), 5, 6), (64, 1024, (17,), 0, 0)])
+def test_device_seeding_matches_oracle_draw(ph, orc, tabs, width, count, es, klo, khi):
+    """Large seeding calls decide primality and build records on the device;
+    the drawn (n, e, k) must equal the oracle's SplitMix64 draw, and the
+    records must generate the oracle's streams."""
+    seed = SEED0 + 900 + width + count
+    c = ph.Context(0, max_instances=count)
+    ids = c.seed_instances(width, seed, count, es, klo, khi)
+    n_o, e_o, k_o = orc.seed(width, seed, count, es, klo, khi)
+    got = np.array([c.get_params(int(i))[:2] for i in ids], dtype=np.uint64)
+    assert np.array_equal(got[:, 0], n_o) and np.array_equal(got[:, 1], e_o)
+    assert [c.get_position(int(i)) for i in ids] == [int(x) for x in k_o]
+    rng = random.Random(count)
+    pick = rng.sample(range(count), 12)
+    specs = [(int(ids[i]), 3000) for i in pick]
+    (hc32, hc64, hr), offs = _run(ph, c, specs)
+    for (iid, cnt), i, off in zip(specs, pick, offs):
+        wc, wr, _ = oracle_draws(orc, tabs, width, int(n_o[i]), int(e_o[i]), int(k_o[i]), cnt)
+        compare_request(hc32 if width == 32 else hc64, hr, off, cnt, wc, wr, "device-seeded")
+    c.close()
