@@ -247,6 +247,7 @@ def main():
     ap.add_argument("--no-ciphertexts", action="store_true", help="skip the u32 + f64 output variant")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph replay variant")
     ap.add_argument("--no-unit-skip", action="store_true", help="skip the unit-skip schedule variant")
+    ap.add_argument("--no-w64", action="store_true", help="skip the 64-bit-moduli variant")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
     ap.add_argument("--workload", default="B", choices=["A", "B", "C", "D", "E"],
                     help="B (default): the headline batch; A, C, D, E: the other workload shapes")
@@ -344,6 +345,19 @@ def main():
         log("unit skip: %s" % unit)
         uctx.close()
 
+    w64 = None
+    if not args.no_w64:
+        # 64-bit moduli (n in [2^62, 2^63)), 1024 seeded instances x 2^20 draws, FP64 only
+        wctx = ph.Context(0, max_instances=1024)
+        wids = wctx.seed_instances(64, 0x14112484 + 3, 1024, (9, 17), 0, 0)
+        wreqs = ph.make_requests(wids, [1 << 20] * 1024, np.arange(1024, dtype=np.uint64) << 20)
+        wms, wk = timed_steps(wctx, torch, lambda: wctx.generate(wreqs, None, None, r, capacity=total),
+                              max(args.steps // 2, 2), 3)
+        w64 = {"value": total / (wms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": wms, "kernel_ms": wk,
+               "workload": "1024 seeded 64-bit instances x 2^20 draws, FP64 uniforms"}
+        log("width 64: %s" % w64)
+        wctx.close()
+
     with_c = None
     if not args.no_ciphertexts:
         c32 = torch.empty(total, dtype=torch.int32, device=dev)
@@ -398,6 +412,7 @@ def main():
         "with_ciphertexts": with_c,
         "graph_replay": graph,
         "unit_skip": unit,
+        "width64": w64,
         "roofline": roof,
         "roofline_other": other,
         "cpu_baseline": cpu,

@@ -208,9 +208,18 @@ __device__ __forceinline__ uint64_t powmod_p61(uint64_t b, uint64_t e) {
   return r;
 }
 
-// binary64(c + 1) / binary64(n + 1), IEEE division (c + 1 < 2^63 converts
-// with one rounding).
-__device__ __forceinline__ double uniform64(uint64_t c, double den) { return (double)(c + 1) / den; }
+// binary64(c + 1) / binary64(n + 1) correctly rounded, with den = RN(n + 1)
+// and rcp = RN(1/den); c + 1 < 2^63 converts with one rounding.  The first
+// correction makes the quotient faithful (within 1 ulp); from a faithful
+// quotient and a correctly rounded reciprocal, one more remainder-and-
+// correct step gives the correctly rounded quotient (Markstein), with five
+// FP64 operations instead of the IEEE divide sequence.
+__device__ __forceinline__ double uniform64(uint64_t c, double den, double rcp) {
+  const double a = (double)(c + 1);
+  const double q0 = a * rcp;
+  const double q1 = __builtin_fma(__builtin_fma(-q0, den, a), rcp, q0);
+  return __builtin_fma(__builtin_fma(-q1, den, a), rcp, q1);
+}
 
 // ---- instance set-up on the device (seeding) --------------------------------
 

@@ -333,7 +333,7 @@ __device__ void run_chunk32(const GenArgs &A, const InstRec &I, const ReqRec &R,
 struct Enc64 {
   uint64_t n, ninv, kc, e;
   int ebits;
-  double den;
+  double den, rcp;
 };
 
 template <int UNROLL, int EK, int OUT, bool MASKED>
@@ -347,7 +347,7 @@ __device__ __forceinline__ void passC64(const uint64_t *L, uint32_t lane, const 
     if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
       const uint64_t c = dev::encrypt64<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
       if (OUT & kOutC) c64[i * 64] = c;
-      if (OUT & kOutR) rr[i * 64] = dev::uniform64(c, K.den);
+      if (OUT & kOutR) rr[i * 64] = dev::uniform64(c, K.den, K.rcp);
     }
   }
 }
@@ -429,7 +429,7 @@ __device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R,
     const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.k) + (int64_t)lane;
     uint64_t *c64 = A.out_c64 ? A.out_c64 + base : nullptr;
     double *rr = A.out_r ? A.out_r + base : nullptr;
-    const Enc64 K{n, ninv, kc, e, ebits, den};
+    const Enc64 K{n, ninv, kc, e, ebits, den, I.rcp};
     if (t_lo == 0 && t_hi == (uint32_t)kTile)
       passC64_e<UNROLL, false>(ekind, L, lane, K, c64, rr, t_lo, t_hi);
     else
@@ -517,7 +517,7 @@ __device__ __forceinline__ void passCS64(uint64_t m, uint64_t step, uint32_t lan
     if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
       const uint64_t c = dev::encrypt64<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
       if (OUT & kOutC) c64[i * 64] = c;
-      if (OUT & kOutR) rr[i * 64] = dev::uniform64(c, K.den);
+      if (OUT & kOutR) rr[i * 64] = dev::uniform64(c, K.den, K.rcp);
     }
     m = dev::addmod64(m, step, K.n);
   }
@@ -546,7 +546,7 @@ __device__ __forceinline__ void passCS64_e(int ekind, uint64_t m, uint64_t step,
 template <int UNROLL>
 __device__ void run_chunk64_cs(const GenArgs &A, const InstRec &I, const ReqRec &R, uint64_t chunk, uint32_t lane) {
   const uint64_t n = I.n, ninv = I.ninv;
-  const Enc64 K{n, ninv, I.kcorr, I.e, (int)I.ebits, I.den};
+  const Enc64 K{n, ninv, I.kcorr, I.e, (int)I.ebits, I.den, I.rcp};
   const uint64_t g_begin = R.g1 + chunk * A.tiles_per_chunk;
   const uint64_t g_end = min(g_begin + A.tiles_per_chunk, R.g1 + R.ntiles);
   for (uint64_t g = g_begin; g < g_end; ++g) {

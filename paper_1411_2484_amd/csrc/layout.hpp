@@ -33,7 +33,7 @@ struct alignas(128) InstRec {
   uint64_t mbase;  // message offset: m at internal index x is mbase + q b + U(r) mod n
   uint64_t e;      // exponent
   double den;      // binary64(n + 1)
-  double rcp;      // RN(1 / (n + 1)) (width 32)
+  double rcp;      // RN(1 / den)
   uint32_t width;  // 32 or 64
   uint32_t ekind;  // 3, 5, 9, 17, or 0 for the generic chain
   uint32_t ebits;  // bit length of e

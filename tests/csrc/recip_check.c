@@ -20,6 +20,14 @@ static inline uint64_t sm64(uint64_t *s) {
   return z ^ (z >> 31);
 }
 
+/* Width-64 form: a = RN(c+1), b = RN(n+1) are doubles; one correction makes
+ * the quotient faithful, the second rounds it correctly. */
+static inline double form2(double a, double b, double y) {
+  double q0 = a * y;
+  double q1 = fma(fma(-q0, b, a), y, q0);
+  return fma(fma(-q1, b, a), y, q1);
+}
+
 typedef struct {
   uint64_t seed, count, mode, mismatches, checked;
 } job_t;
@@ -31,6 +39,64 @@ static void *worker(void *arg) {
   job_t *j = (job_t *)arg;
   uint64_t s = j->seed, bad = 0, done = 0;
   for (uint64_t i = 0; i < j->count; i++) {
+    if (j->mode >= 2) {
+      /* width 64: n in [2^62, 2^63), c in [0, n) */
+      uint64_t n = ((uint64_t)1 << 62) + (sm64(&s) & (((uint64_t)1 << 62) - 1));
+      double bd = (double)(n + 1), y = 1.0 / bd;
+      if (j->mode == 4) {
+        /* hardest cases: a/b within ~2^-107 (relative) of a rounding midpoint.
+         * B = odd 53-bit significand of b; for odd d, L = d B^{-1} mod 2^54 is
+         * odd, and if L has 54 bits then A = (L B - d) / 2^54 is an integer
+         * significand with A/B = L/2^54 - d/(2^54 B). */
+        uint64_t B = ((uint64_t)1 << 52) | (sm64(&s) & (((uint64_t)1 << 52) - 1)) | 1;
+        uint64_t inv = B; /* B^{-1} mod 2^64 by Newton */
+        for (int it = 0; it < 6; it++) inv *= 2 - B * inv;
+        const uint64_t mask54 = ((uint64_t)1 << 54) - 1;
+        for (int64_t d = -7; d <= 7; d += 2) {
+          uint64_t L = ((uint64_t)d * inv) & mask54;
+          if (L < ((uint64_t)1 << 53)) continue;
+          unsigned __int128 LB = (unsigned __int128)L * B;
+          unsigned __int128 num = LB - (unsigned __int128)(__int128)d;
+          uint64_t A = (uint64_t)(num >> 54);
+          if ((num & mask54) != 0 || A < ((uint64_t)1 << 52) || A >= ((uint64_t)1 << 53)) continue;
+          double bd2 = ldexp((double)B, 10);             /* b in [2^62, 2^63) */
+          for (int sh = 10; sh >= -30; sh -= 8) {        /* a/b in (2^-41, 1) */
+            double ad = ldexp((double)A, sh);
+            if (ad > bd2 || ad < 1.0) continue;
+            double yy = 1.0 / bd2;
+            bad += form2(ad, bd2, yy) != ad / bd2;
+            done++;
+          }
+        }
+        continue;
+      }
+      if (j->mode == 2) {
+        uint64_t cc = sm64(&s) % n;
+        double ad = (double)(cc + 1);
+        bad += form2(ad, bd, y) != ad / bd;
+        done++;
+      } else {
+        /* near-midpoint: a/b close to (2M+1) 2^(-k-53); a = the doubles around mid*b */
+        int k = 1 + (int)(sm64(&s) % 40);
+        uint64_t M = ((uint64_t)1 << 52) | (sm64(&s) & (((uint64_t)1 << 52) - 1));
+        long double mid = ldexpl((long double)(2 * M + 1), -k - 53);
+        double t = (double)(mid * (long double)bd);
+        double ad = t;
+        for (int u = 0; u < 3; u++) {
+          if (ad >= 1.0 && ad <= bd) {
+            bad += form2(ad, bd, y) != ad / bd;
+            done++;
+          }
+          ad = nextafter(ad, 0.0);
+        }
+        ad = nextafter(t, 1e300);
+        if (ad >= 1.0 && ad <= bd) {
+          bad += form2(ad, bd, y) != ad / bd;
+          done++;
+        }
+      }
+      continue;
+    }
     uint64_t b = ((uint64_t)1 << 31) + 1 + (sm64(&s) % ((uint64_t)1 << 31));
     double bd = (double)b, y = 1.0 / bd;
     if (j->mode == 0) {

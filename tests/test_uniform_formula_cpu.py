@@ -67,3 +67,31 @@ def test_plain_reciprocal_multiply_is_not_exact():
     y = 1.0 / (n + 1)
     diff = sum(1 for _ in range(20000) if (lambda c: (c + 1) * y != (c + 1) / (n + 1))(rng.randrange(n)))
     assert diff > 1000
+
+
+@pytest.mark.slow
+def test_width64_double_correction_random_pairs(rc):
+    """Width-64 form (two corrections from a = RN(c+1), b = RN(n+1))."""
+    nt = _threads()
+    done = ctypes.c_uint64()
+    bad = rc.recip_sampled(0x64, (10 ** 9 + nt - 1) // nt, 2, nt, ctypes.byref(done))
+    assert done.value >= 10 ** 9
+    assert bad == 0
+
+
+def test_width64_double_correction_near_midpoints(rc):
+    nt = _threads()
+    done = ctypes.c_uint64()
+    bad = rc.recip_sampled(0x65, 2 * 10 ** 7 // nt, 3, nt, ctypes.byref(done))
+    assert done.value > 10 ** 7
+    assert bad == 0
+
+
+def test_width64_double_correction_hardest_cases(rc):
+    """Quotients within ~2^-107 (relative) of a binary64 rounding midpoint,
+    built from the significand of b by a modular inverse."""
+    nt = _threads()
+    done = ctypes.c_uint64()
+    bad = rc.recip_sampled(0x66, 2 * 10 ** 6 // nt, 4, nt, ctypes.byref(done))
+    assert done.value > 10 ** 6
+    assert bad == 0
