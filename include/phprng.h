@@ -300,6 +300,107 @@ typedef struct {
 phprng_status phprng_server_replay(phprng_server *server, const phprng_arrival *arrivals, uint64_t n,
                                    int64_t *latency_ns, double *wall_s);
 
+
+/* ---- statistical battery: the chi-square tests of the Tests section ---------*/
+
+/* The battery histograms a sequence of uniforms on the device and reports
+ * chi^2 and P for nine of the paper's tests.  The sequence is consumed in
+ * blocks of PHPRNG_BATTERY_BLOCK = 2^20 uniforms (the Fourier length); every
+ * test works inside a block, so the result does not depend on how the blocks
+ * are split over calls.  A uniform R falls in bin min(floor(R B), B - 1) of B
+ * equal bins (the clamp only acts on R = 1.0).  Per block:
+ *   FREQUENCY  all uniforms, 2^20 bins;
+ *   SERIAL2..5 non-overlapping D-tuples (the last 2^20 mod D uniforms are
+ *              unused), first element most significant, 1024 / 100 / 32 / 16
+ *              bins per axis (2^20, 10^6, 2^20, 2^20 cells);
+ *   POKER      non-overlapping hands of five digits min(floor(10 R), 9):
+ *              all different, one pair, two pairs, three of a kind, full
+ *              house, four of a kind, five of a kind;
+ *   COLLISION  64 trials of 2^14 consecutive uniforms into 2^20 urns,
+ *              collisions = 2^14 - occupied urns, categories <= 100, 101 ..
+ *              154, >= 155;
+ *   RUNS       bits R > 1/2, maximal runs with a differing bit on both sides
+ *              inside the block, lengths 1 .. 20 and >= 21, expected counts
+ *              = observed runs x the exact length law;
+ *   FOURIER    x_j = R_j - 1/2, coefficients M^-1/2 sum_j x_j exp(+2 pi i j k / M)
+ *              for k < M/2; real and imaginary parts in 64 bins of width
+ *              sigma / 8 over [-4 sigma, 4 sigma) and two tails, sigma^2 =
+ *              1/24, the bin of v being floor(v RN(8 sqrt 24)).
+ * chi^2 = sum (O - E)^2 / E over the categories, dof = categories - 1, and P
+ * is the one-sided probability about the median of the chi^2 law:
+ * min(Q, 1 - Q) with Q its upper tail.  The paper's pass criterion is no
+ * P < 1e-8. */
+#define PHPRNG_BATTERY_BLOCK 1048576u
+
+enum {
+  PHPRNG_TEST_FREQUENCY = 0,
+  PHPRNG_TEST_SERIAL2,
+  PHPRNG_TEST_SERIAL3,
+  PHPRNG_TEST_SERIAL4,
+  PHPRNG_TEST_SERIAL5,
+  PHPRNG_TEST_POKER,
+  PHPRNG_TEST_COLLISION,
+  PHPRNG_TEST_RUNS,
+  PHPRNG_TEST_FOURIER,
+  PHPRNG_TEST_COUNT
+};
+
+typedef struct {
+  double chi2;
+  double p_value;
+  uint64_t dof;
+  uint64_t samples; /* histogram entries: uniforms, tuples, hands, trials, runs or coefficient parts */
+} phprng_test_result;
+
+typedef struct phprng_battery phprng_battery;
+
+/* Create a battery on HIP device `device`: 42 MB of histograms and 258 MB of
+ * transform scratch.  The caller owns it (phprng_battery_destroy). */
+phprng_status phprng_battery_create(phprng_battery **battery, int device);
+phprng_status phprng_battery_destroy(phprng_battery *battery);
+const char *phprng_battery_last_error(const phprng_battery *battery);
+
+/* Zero the histograms and the kernel timing (asynchronous on `stream`). */
+phprng_status phprng_battery_reset(phprng_battery *battery, void *stream);
+
+/* Add `count` uniforms (a multiple of 2^20; device array, 16-byte aligned)
+ * to the histograms; asynchronous on `stream`.  `r` must stay valid until the
+ * stream completes.  Calls on one battery must be ordered on one stream. */
+phprng_status phprng_battery_accumulate(phprng_battery *battery, const double *r, uint64_t count, void *stream);
+
+/* Reduce the histograms to chi^2 on the device and fill out[PHPRNG_TEST_COUNT]
+ * (host array); waits for `stream`. */
+phprng_status phprng_battery_report(phprng_battery *battery, phprng_test_result *out, void *stream);
+
+/* Copy the histogram of `test` (host array of `capacity` counts) and/or its
+ * number of categories (*ncat; either pointer may be NULL); waits for `stream`. */
+phprng_status phprng_battery_counts(phprng_battery *battery, int test, uint64_t *out, uint64_t capacity,
+                                    uint64_t *ncat, void *stream);
+
+/* The category probabilities of `test` used for the expected counts (host;
+ * equal for the frequency and serial tests). */
+phprng_status phprng_battery_probabilities(int test, double *out, uint64_t capacity, uint64_t *ncat);
+
+/* The Fourier coefficients alone: for each block of `count` uniforms (device),
+ * coef receives 2^20 doubles (device), the real and imaginary parts of
+ * coefficients k = 0 .. 2^19 - 1 interleaved.  The histograms are unchanged. */
+phprng_status phprng_battery_fourier(phprng_battery *battery, const double *r, uint64_t count, double *coef,
+                                     void *stream);
+
+/* Kernel time (ms) and launches since the last reset for the five kernel
+ * classes: histograms, collision, runs, transform pass 1, transform pass 2
+ * (HIP events on the launch stream; waits for them). */
+phprng_status phprng_battery_timing(phprng_battery *battery, double *ms, uint64_t *launches);
+
+/* One-sided P-value min(Q, 1 - Q) of chi^2 with `dof` degrees of freedom (host). */
+phprng_status phprng_chi2_pvalue(double chi2, double dof, double *p);
+
+/* Interstream order of the Tests section (device arrays, asynchronous on
+ * `stream`): out[t * nstreams + i] = in[i * length + t], i.e. the t-th
+ * uniform of every stream, then the (t+1)-th.  in and out must not overlap;
+ * nstreams <= 4,194,240. */
+phprng_status phprng_interleave(const double *in, double *out, uint64_t nstreams, uint64_t length, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

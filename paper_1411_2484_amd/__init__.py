@@ -57,6 +57,11 @@ class phprng_server_config(ctypes.Structure):
                 ("max_batch_draws", ctypes.c_uint64)]
 
 
+class phprng_test_result(ctypes.Structure):
+    _fields_ = [("chi2", ctypes.c_double), ("p_value", ctypes.c_double), ("dof", ctypes.c_uint64),
+                ("samples", ctypes.c_uint64)]
+
+
 class phprng_completion(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("instance", ctypes.c_uint32),
                 ("status", ctypes.c_int32), ("count", ctypes.c_uint64), ("k", ctypes.c_uint64),
@@ -111,7 +116,23 @@ SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_double)]),
     "phprng_timing_reset": (ctypes.c_int, [_vp]),
     "phprng_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
+    "phprng_battery_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int]),
+    "phprng_battery_destroy": (ctypes.c_int, [_vp]),
+    "phprng_battery_last_error": (ctypes.c_char_p, [_vp]),
+    "phprng_battery_reset": (ctypes.c_int, [_vp, _vp]),
+    "phprng_battery_accumulate": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
+    "phprng_battery_report": (ctypes.c_int, [_vp, ctypes.POINTER(phprng_test_result), _vp]),
+    "phprng_battery_counts": (ctypes.c_int, [_vp, ctypes.c_int, _pu64, _u64, _pu64, _vp]),
+    "phprng_battery_probabilities": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), _u64, _pu64]),
+    "phprng_battery_fourier": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp]),
+    "phprng_battery_timing": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), _pu64]),
+    "phprng_chi2_pvalue": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "phprng_interleave": (ctypes.c_int, [_vp, _vp, _u64, _u64, _vp]),
 }
+
+BATTERY_BLOCK = 1 << 20
+BATTERY_TESTS = ("frequency", "serial2", "serial3", "serial4", "serial5", "poker", "collision", "runs", "fourier")
+BATTERY_KERNELS = ("hist", "collision", "runs", "fft_pass1", "fft_pass2")
 
 _lib = None
 
@@ -421,6 +442,88 @@ class Server:
     def close(self):
         if getattr(self, "_h", None):
             lib().phprng_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- statistical battery (Tests section) ---------------------------------------
+
+def chi2_pvalue(chi2, dof):
+    """One-sided P-value min(Q, 1 - Q) of chi^2 with `dof` degrees of freedom."""
+    p = ctypes.c_double()
+    _check(lib().phprng_chi2_pvalue(float(chi2), float(dof), ctypes.byref(p)))
+    return p.value
+
+
+def battery_probabilities(test):
+    """Category probabilities of a battery test (index into BATTERY_TESTS)."""
+    n = _u64()
+    _check(lib().phprng_battery_probabilities(int(test), None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value, dtype=np.float64)
+    _check(lib().phprng_battery_probabilities(int(test), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              out.size, ctypes.byref(n)))
+    return out
+
+
+def interleave(src, dst, nstreams, length, stream=None):
+    """dst[t * nstreams + i] = src[i * length + t] (device float64 tensors)."""
+    _check(lib().phprng_interleave(_dptr(src), _dptr(dst), int(nstreams), int(length), _stream_handle(stream)))
+
+
+class Battery:
+    """phprng_battery_*: device histograms of the nine chi-square tests."""
+
+    def __init__(self, device=0):
+        h = _vp()
+        _check(lib().phprng_battery_create(ctypes.byref(h), int(device)))
+        self._h = h
+
+    def _chk(self, st):
+        if st != PHPRNG_OK:
+            raise PhprngError(st, lib().phprng_battery_last_error(self._h).decode())
+
+    def reset(self, stream=None):
+        self._chk(lib().phprng_battery_reset(self._h, _stream_handle(stream)))
+
+    def accumulate(self, r, count=None, stream=None):
+        """Add the uniforms of device tensor `r` (float64; count a multiple of 2^20)."""
+        n = r.numel() if count is None else int(count)
+        self._chk(lib().phprng_battery_accumulate(self._h, _dptr(r), n, _stream_handle(stream)))
+
+    def report(self, stream=None):
+        """{test name: (chi2, dof, p_value, samples)}."""
+        out = (phprng_test_result * len(BATTERY_TESTS))()
+        self._chk(lib().phprng_battery_report(self._h, out, _stream_handle(stream)))
+        return {name: (out[i].chi2, out[i].dof, out[i].p_value, out[i].samples)
+                for i, name in enumerate(BATTERY_TESTS)}
+
+    def counts(self, test, stream=None):
+        n = _u64()
+        self._chk(lib().phprng_battery_counts(self._h, int(test), None, 0, ctypes.byref(n), _stream_handle(stream)))
+        out = np.zeros(n.value, dtype=np.uint64)
+        self._chk(lib().phprng_battery_counts(self._h, int(test), out.ctypes.data_as(_pu64), out.size,
+                                              ctypes.byref(n), _stream_handle(stream)))
+        return out
+
+    def fourier(self, r, coef, count=None, stream=None):
+        n = r.numel() if count is None else int(count)
+        self._chk(lib().phprng_battery_fourier(self._h, _dptr(r), n, _dptr(coef), _stream_handle(stream)))
+
+    def timing(self):
+        """{kernel class: (ms, launches)} since the last reset."""
+        ms = (ctypes.c_double * len(BATTERY_KERNELS))()
+        ln = (ctypes.c_uint64 * len(BATTERY_KERNELS))()
+        self._chk(lib().phprng_battery_timing(self._h, ms, ln))
+        return {k: (ms[i], ln[i]) for i, k in enumerate(BATTERY_KERNELS)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().phprng_battery_destroy(self._h)
             self._h = None
 
     def __del__(self):
