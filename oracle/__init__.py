@@ -78,6 +78,7 @@ def lib():
             "pho_seed": (ctypes.c_int, [ctypes.c_int, _u64, _u64, _pu64, ctypes.c_int, _u64, _u64, _pu64, _pu64,
                                         _pu64]),
             "pho_count_many": (_u64, [ctypes.c_int, _pu64, _u64, ctypes.c_int, _u64]),
+            "pho_pattern_hist": (None, [_u64, _u64, _u64, _u64, _u64, _u64, ctypes.c_int, _u64, _u64, _u64, _pu64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -279,3 +280,12 @@ def count_many(values, mode, e=0, nthreads=0):
     """mode 0: #prime; 1: #safe prime; 2: #(gcd(e, v-1) = 1)."""
     v = np.ascontiguousarray(values, dtype=np.uint64)
     return int(lib().pho_count_many(nthreads, _p64(v), v.size, mode, e))
+
+
+def pattern_hist(n, e, p, a, x0, l0, dim, bins, s_lo, s_hi):
+    """Full-period local pattern histogram (Sec. III): counts of the D-1
+    points that follow every first point c in [x0, x0 + l0), over skips
+    s in [s_lo, s_hi), in bins^(dim-1) cells."""
+    hist = np.zeros(int(bins) ** (int(dim) - 1), dtype=np.uint64)
+    lib().pho_pattern_hist(n, e, p, a, x0, l0, int(dim), bins, s_lo, s_hi, _p64(hist))
+    return hist

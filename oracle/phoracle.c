@@ -597,3 +597,42 @@ uint64_t pho_count_many(int nthreads, const uint64_t *v, uint64_t len, int mode,
   free(jobs);
   return total;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Full-period local pattern (Sec. III: the D-dimensional pattern of         */
+/* consecutive ciphertexts over the whole period, in O(p L0) steps)          */
+/* ------------------------------------------------------------------------ */
+
+/* Over the full period every pair (m_k, s_k) occurs exactly once, so the
+ * tuples (c_k, c_{k+1}, ..., c_{k+D-1}) whose first point lies in a window
+ * are enumerated by the window's ciphertexts c and all skips s: with
+ * m = c^d mod n (d = e^{-1} mod (n-1)), the following points are
+ *   c_{k+1} = (m + s)^e,  c_{k+2} = (m + s + (a s mod p))^e, ...
+ * (all mod n), the skip advancing by one multiplication by a mod p per point.
+ * Each tuple with c in [x0, x0 + l0) and s in [s_lo, s_hi) (the full period
+ * takes s = 1 .. p-1) adds one to the cell of its D-1 following points:
+ * bins floor(c_j B / n) per axis, the first following point the most
+ * significant digit of the cell index.  hist has B^(D-1) entries and is
+ * accumulated, not cleared. */
+void pho_pattern_hist(uint64_t n, uint64_t e, uint64_t p, uint64_t a, uint64_t x0, uint64_t l0, int dim,
+                      uint64_t bins, uint64_t s_lo, uint64_t s_hi, uint64_t *hist) {
+  uint64_t d = pho_inverse(e, n - 1);
+  for (uint64_t c = x0; c < x0 + l0; c++) {
+    uint64_t m = pho_powmod(c, d, n);
+    for (uint64_t s = s_lo; s < s_hi; s++) {
+      uint64_t sk = s;
+      uint64_t mk = (uint64_t)(((u128)m + sk) % n);
+      uint64_t cell = 0;
+      for (int j = 1; j < dim; j++) {
+        if (j > 1) {
+          sk = pho_mulmod(a, sk, p);
+          mk = (uint64_t)(((u128)mk + sk) % n);
+        }
+        uint64_t cj = pho_powmod(mk, e, n);
+        uint64_t b = (uint64_t)(((u128)cj * bins) / n);
+        cell = cell * bins + b;
+      }
+      hist[cell]++;
+    }
+  }
+}
