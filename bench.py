@@ -236,6 +236,163 @@ def workload_e(args, torch, ph):
                        serve=points)
 
 
+BATTERY_BYTES_PER_DRAW = {  # algorithmic HBM bytes per tested uniform, per battery kernel
+    "hist": 8.0 + 1.0 / 8,      # read R, write one bit
+    "collision": 8.0,           # read R
+    "runs": 1.0 / 8,            # read the bits
+    "fft_pass1": 16.0,          # read R, write 8 B of complex rows per uniform
+    "fft_pass2": 8.0,           # read the rows
+}
+
+
+def battery_cpu_baseline(r_host, target_s=12.0):
+    """The oracle battery on host copies of whole blocks of the tested
+    sequence, repeated until about target_s seconds."""
+    from oracle import battery as OB
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        OB.run_battery(r_host)
+        done += r_host.size
+        el = time.perf_counter() - t0
+        if el >= target_s:
+            break
+    return {"value": done / el / 1e9, "unit": "Guniforms/s", "cores": 1, "kind": "oracle",
+            "sample": "the nine tests on %d generator uniforms (%d blocks of 2^20), %d passes in %.1f s"
+                      % (r_host.size, r_host.size >> 20, done // r_host.size, el)}
+
+
+def workload_f(args, torch, ph):
+    """The statistical battery of the Tests section on the generator's output:
+    1024 seeded 32-bit instances x 2^20 draws per step (each block of the
+    tested sequence is one stream: intrastream), generation plus the nine
+    tests; the interstream variant interleaves the 1024 streams first."""
+    dev = torch.device("cuda:0")
+    nst, per = 1024, 1 << 20
+    total = nst * per
+    ctx = ph.Context(0, max_instances=nst)
+    ids = ctx.seed_instances(32, 0x14112484 + 8, nst, (9, 17), 0, 0)
+    r = torch.empty(total, dtype=torch.float64, device=dev)
+    inter = torch.empty(total, dtype=torch.float64, device=dev)
+    reqs = ph.make_requests(ids, [per] * nst, np.arange(nst, dtype=np.uint64) * per)
+    steps = max(2, args.steps // 4)
+    res = {}
+    for order in ("intrastream", "interstream"):
+        bat = ph.Battery(0)
+
+        def step():
+            ctx.generate(reqs, None, None, r, capacity=total)
+            if order == "interstream":
+                ph.interleave(r, inter, nst, per)
+                bat.accumulate(inter)
+            else:
+                bat.accumulate(r)
+
+        step()
+        torch.cuda.synchronize()
+        bat.reset()
+        ctx.timing_reset()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kt = bat.timing()
+        gen_ms, gen_calls = ctx.timing_read()
+        rep = bat.report()
+        draws = total * steps
+        kernels = {}
+        for k, (ms, n) in kt.items():
+            gbs = draws * BATTERY_BYTES_PER_DRAW[k] / (ms * 1e-3) / 1e9
+            kernels[k] = {"ms_per_step": ms / steps, "launches": n, "achieved_gbs": gbs,
+                          "bytes_per_draw": BATTERY_BYTES_PER_DRAW[k]}
+        bat_ms = sum(v[0] for v in kt.values()) / steps
+        res[order] = {"value": draws / wall / 1e9, "ms_per_step": wall * 1e3 / steps,
+                      "generation_ms_per_step": gen_ms / max(gen_calls, 1), "battery_kernel_ms_per_step": bat_ms,
+                      "battery_only_guniforms_s": total / (bat_ms * 1e-3) / 1e9, "kernels": kernels,
+                      "tests": {name: {"chi2": v[0], "dof": v[1], "p": v[2], "samples": v[3]}
+                                for name, v in rep.items()},
+                      "min_p": min(v[2] for v in rep.values())}
+        log("battery %s: %.1f Guniforms/s tested (battery kernels %.2f ms/step), min P %.3g"
+            % (order, res[order]["value"], bat_ms, res[order]["min_p"]))
+        bat.close()
+    intra = res["intrastream"]
+    dom = max(intra["kernels"], key=lambda k: intra["kernels"][k]["ms_per_step"])
+    dk = intra["kernels"][dom]
+    roof = {"bound": "hbm", "achieved": dk["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dk["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+            "bytes_per_draw": dk["bytes_per_draw"], "units_per_launch": 32 << 20}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = battery_cpu_baseline(r[: 8 << 20].cpu().numpy())
+        log("battery cpu baseline: %s" % cpu)
+    ctx.close()
+    line = common_line(intra["value"], "Guniforms/s", steps, 1, intra["ms_per_step"],
+                       {"workload": "statistical battery (nine chi-square tests, blocks of 2^20) on 1024 seeded "
+                                    "32-bit streams x 2^20 draws per step, generation included"},
+                       roofline=roof, cpu_baseline=cpu, **res)
+    line["metric"] = "uniforms tested per second by the nine-test battery (generation + tests)"
+    line["dtype"] = "f64"
+    return line
+
+
+def pattern_ops_per_tuple(dim, e=9):
+    """VALU operations per tuple of the pattern kernel in the minimal model:
+    per following point one modular add (3), the encryption chain (6 per
+    Montgomery product) and the bin (8); one skip step (6) per point after
+    the first."""
+    chain = {3: 3, 5: 4, 9: 5, 17: 6}[int(e)]
+    return (dim - 1) * (3 + 6 * chain + 8) + (dim - 2) * 6
+
+
+def workload_g(args, torch, ph):
+    """Full-period local pattern of Sec. III with the Tests section's sizes:
+    the paper's safe prime n = 4294967087, e = 9, the 128 first points
+    [0, 128), every skip of the period [1, p), D = 3, 4, 5 in 2^24 cells."""
+    import oracle
+    n, e, l0 = 4294967087, 9, 128
+    p31 = (1 << 31) - 1
+    res = {}
+    for dim, bins in ((3, 4096), (4, 256), (5, 64)):
+        spec = ph.pattern_spec(n, e, 0, l0, dim, bins, 1, p31)
+        hist = torch.zeros(bins ** (dim - 1), dtype=torch.int64, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ph.pattern_histogram(spec, hist)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        chi2, pv, total = ph.pattern_chi2(spec, hist)
+        tuples = l0 * (p31 - 1)
+        ops = pattern_ops_per_tuple(dim, e)
+        res["D%d" % dim] = {"seconds": wall, "tuples": tuples, "gtuples_s": tuples / wall / 1e9,
+                            "chi2": chi2, "dof": bins ** (dim - 1) - 1, "p": pv, "total": total,
+                            "alu_frac": tuples * ops / wall / ALU_PEAK_OPS, "ops_per_tuple": ops}
+        log("pattern D=%d: %.2f s, %.1f Gtuples/s, chi2 %.1f, P %.3g" % (dim, wall, tuples / wall / 1e9, chi2, pv))
+        del hist
+    # the oracle on a bounded sample: one first point, 2^22 skips, D = 3
+    p, a = oracle.lcg_params(32)
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < 10.0:
+        oracle.pattern_hist(n, e, p, a, reps, 1, 3, 4096, 1, 1 + (1 << 22))
+        reps += 1
+    el = time.perf_counter() - t0
+    cpu = {"value": reps * (1 << 22) / el / 1e9, "unit": "Gtuples/s", "cores": 1, "kind": "oracle",
+           "sample": "%d first points x 2^22 skips, D = 3, 4096^2 cells, in %.1f s" % (reps, el)}
+    d3 = res["D3"]
+    roof = {"bound": "alu", "achieved": d3["tuples"] * d3["ops_per_tuple"] / d3["seconds"] / 1e12,
+            "peak": ALU_PEAK_OPS / 1e12, "unit": "Top/s", "frac": d3["alu_frac"], "traffic": None,
+            "kernel": "pattern_kernel<9, 3>", "ops_per_tuple": d3["ops_per_tuple"]}
+    total_s = sum(v["seconds"] for v in res.values())
+    line = common_line(d3["gtuples_s"], "Gtuples/s", 1, 0, d3["seconds"] * 1e3,
+                       {"workload": "full-period local pattern: n = 4294967087, e = 9, first points [0, 128), "
+                                    "skips [1, 2^31 - 1), 2^24 cells, D = 3 (value), 4, 5"},
+                       roofline=roof, cpu_baseline=cpu, all_dims_seconds=total_s, **res)
+    line["metric"] = "full-period pattern tuples per second (D = 3)"
+    line["dtype"] = "u32"
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,8 +406,9 @@ def main():
     ap.add_argument("--no-unit-skip", action="store_true", help="skip the unit-skip schedule variant")
     ap.add_argument("--no-w64", action="store_true", help="skip the 64-bit-moduli variant")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
-    ap.add_argument("--workload", default="B", choices=["A", "B", "C", "D", "E"],
-                    help="B (default): the headline batch; A, C, D, E: the other workload shapes")
+    ap.add_argument("--workload", default="B", choices=["A", "B", "C", "D", "E", "F", "G"],
+                    help="B (default): the headline batch; A, C, D, E: the other workload shapes; "
+                         "F: the statistical battery on the generator's output; G: the full-period pattern")
     ap.add_argument("--serve-instances", type=int, default=1000000)
     ap.add_argument("--serve-arena", type=int, default=1 << 31, help="serving arena, FP64 uniforms")
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[1e3, 1e4, 1e5, 1e6])
@@ -273,7 +431,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     if args.workload != "B":
-        fn = {"A": workload_a, "C": workload_c, "D": workload_d, "E": workload_e}[args.workload]
+        fn = {"A": workload_a, "C": workload_c, "D": workload_d, "E": workload_e, "F": workload_f,
+              "G": workload_g}[args.workload]
         print(json.dumps(fn(args, torch, ph)), flush=True)
         return
     dev = torch.device("cuda:0")

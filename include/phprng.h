@@ -401,6 +401,41 @@ phprng_status phprng_chi2_pvalue(double chi2, double dof, double *p);
  * nstreams <= 4,194,240. */
 phprng_status phprng_interleave(const double *in, double *out, uint64_t nstreams, uint64_t length, void *stream);
 
+
+/* ---- full-period local pattern (Sec. III) -----------------------------------*/
+
+/* Over one period n(p-1) of a width-32 instance every state (m_k, s_k)
+ * occurs once, so the windows (c_k, c_{k+1}, ..., c_{k+D-1}) whose first
+ * point lies in [x0, x0 + l0) are enumerated by that first point c and the
+ * skip s = s_{k+1} of the next step, in O(p l0) steps:
+ *   m = c^d mod n (d = e^{-1} mod (n-1)),
+ *   c_{k+1} = (m + s)^e,  c_{k+2} = (m + s + (a s mod p))^e,  ...  (mod n).
+ * The D-1 following points are binned by floor(c_j bins / n) per axis (the
+ * first following point is the most significant digit of the cell index).
+ * The full period takes s over [1, p); any sub-range [s_lo, s_hi) may be
+ * given, and histograms of disjoint ranges add up.  The Tests section uses
+ * l0 = 2^7 and 2^24 cells (bins = 2^(24/(D-1))) for D = 3, 4, 5. */
+typedef struct {
+  uint64_t n, e;       /* a width-32 instance (phprng_check_instance rules) */
+  uint64_t x0, l0;     /* first points c in [x0, x0 + l0), x0 + l0 <= n */
+  uint64_t s_lo, s_hi; /* skips in [s_lo, s_hi), 1 <= s_lo < s_hi <= p = 2^31 - 1 */
+  uint32_t dim;        /* D, 2..5 */
+  uint32_t bins;       /* cells per following axis; bins^(D-1) <= 2^28 */
+} phprng_pattern;
+
+/* Add the counts of `pat` to hist, a caller-owned device array of
+ * bins^(D-1) uint64 counts (not cleared); asynchronous on `stream`. */
+phprng_status phprng_pattern_histogram(const phprng_pattern *pat, uint64_t *hist, void *stream);
+
+/* chi^2 of a histogram of `pat` (device) against the uniform model: each
+ * following point uniform over [0, n), so a cell expects
+ * T prod_j (w_{b_j} / n) with T = l0 (s_hi - s_lo) and w_b the number of
+ * c in [0, n) with bin b; dof = cells - 1; P one-sided about the median as
+ * for the battery.  *total receives the histogram's sum.  Any output pointer
+ * may be NULL; waits for `stream` (uses 16 KB of stream-ordered scratch). */
+phprng_status phprng_pattern_chi2(const phprng_pattern *pat, const uint64_t *hist, double *chi2, double *p_value,
+                                  uint64_t *total, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

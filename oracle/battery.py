@@ -4,8 +4,7 @@ uniforms (the chi-square tests listed in the paper's Tests section).
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark are the only callers.  Plain numpy in binary64, written
 from the definitions; library routines serve as single steps (``bincount``,
-an FFT, the normal distribution function of scipy, mpmath's regularised
-incomplete gamma function).
+an FFT, the normal distribution and incomplete gamma functions of scipy).
 
 Readings of the paper that fix what is computed (the paper names the tests
 and their bin counts but not every convention):
@@ -41,7 +40,6 @@ from __future__ import annotations
 
 import math
 
-import mpmath
 import numpy as np
 from scipy import special
 
@@ -251,21 +249,14 @@ def chi_square(observed, expected):
 
 
 def p_value(chi2, dof):
-    """One-sided probability about the median: min(Q, 1 - Q), Q = P(X >= chi2)."""
-    # both tails in 40-digit arithmetic: binary64 library routines lose several
-    # digits at the 10^6 degrees of freedom of the serial tests
-    # (the tail on the near side of the mean is evaluated, the other one is its
-    # complement, which 40 digits carry without loss)
-    rough = min(float(special.gammaincc(dof / 2.0, chi2 / 2.0)), float(special.gammainc(dof / 2.0, chi2 / 2.0)))
-    if rough < 1e-250:      # far tails: binary64 already tells the (vanishing) answer
-        return rough
-    with mpmath.workdps(40):
-        a, x = mpmath.mpf(dof) / 2, mpmath.mpf(chi2) / 2
-        if x < a:
-            t = mpmath.gammainc(a, 0, x, regularized=True)
-        else:
-            t = mpmath.gammainc(a, x, mpmath.inf, regularized=True)
-        return float(min(t, 1 - t))
+    """One-sided probability about the median: min(Q, 1 - Q), Q = P(X >= chi2).
+    Both tails come straight from scipy's regularised incomplete gamma
+    functions (no complement is formed, so neither tail loses digits to
+    cancellation); their relative accuracy is about 1e-8 at 10^6 degrees of
+    freedom and better below."""
+    q = float(special.gammaincc(dof / 2.0, chi2 / 2.0))
+    p = float(special.gammainc(dof / 2.0, chi2 / 2.0))
+    return min(q, p)
 
 
 def run_battery(r):

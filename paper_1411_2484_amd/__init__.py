@@ -62,6 +62,12 @@ class phprng_test_result(ctypes.Structure):
                 ("samples", ctypes.c_uint64)]
 
 
+class phprng_pattern(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("e", ctypes.c_uint64), ("x0", ctypes.c_uint64), ("l0", ctypes.c_uint64),
+                ("s_lo", ctypes.c_uint64), ("s_hi", ctypes.c_uint64), ("dim", ctypes.c_uint32),
+                ("bins", ctypes.c_uint32)]
+
+
 class phprng_completion(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("instance", ctypes.c_uint32),
                 ("status", ctypes.c_int32), ("count", ctypes.c_uint64), ("k", ctypes.c_uint64),
@@ -128,6 +134,9 @@ SIGNATURES = {
     "phprng_battery_timing": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), _pu64]),
     "phprng_chi2_pvalue": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "phprng_interleave": (ctypes.c_int, [_vp, _vp, _u64, _u64, _vp]),
+    "phprng_pattern_histogram": (ctypes.c_int, [ctypes.POINTER(phprng_pattern), _vp, _vp]),
+    "phprng_pattern_chi2": (ctypes.c_int, [ctypes.POINTER(phprng_pattern), _vp, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), _pu64, _vp]),
 }
 
 BATTERY_BLOCK = 1 << 20
@@ -531,3 +540,25 @@ class Battery:
             self.close()
         except Exception:
             pass
+
+
+# ---- full-period local pattern (Sec. III) ---------------------------------------
+
+def pattern_spec(n, e, x0, l0, dim, bins, s_lo=1, s_hi=None):
+    """phprng_pattern for a width-32 instance; s_hi defaults to p (the full period)."""
+    if s_hi is None:
+        s_hi = (1 << 31) - 1
+    return phprng_pattern(int(n), int(e), int(x0), int(l0), int(s_lo), int(s_hi), int(dim), int(bins))
+
+
+def pattern_histogram(spec, hist, stream=None):
+    """Add the counts of `spec` to `hist` (device int64 tensor of bins^(dim-1))."""
+    _check(lib().phprng_pattern_histogram(ctypes.byref(spec), _dptr(hist), _stream_handle(stream)))
+
+
+def pattern_chi2(spec, hist, stream=None):
+    """(chi2, p_value, total) of a pattern histogram."""
+    c, p, t = ctypes.c_double(), ctypes.c_double(), _u64()
+    _check(lib().phprng_pattern_chi2(ctypes.byref(spec), _dptr(hist), ctypes.byref(c), ctypes.byref(p),
+                                     ctypes.byref(t), _stream_handle(stream)))
+    return c.value, p.value, t.value
