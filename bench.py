@@ -236,12 +236,17 @@ def workload_e(args, torch, ph):
                        serve=points)
 
 
+BATTERY_KEYS_PER_DRAW = 1 + 1 / 2 + 1 / 3 + 1 / 4 + 1 / 5   # frequency + serial 2..5 histogram keys
+# per 32-block chunk, the counting stage writes and reads 2 slices of 159
+# partitions x 2^15 u32 counts and updates 159 x 2^15 u64 histogram cells
+BATTERY_COUNT_FIXED_BYTES = 2 * (159 * 2 * (1 << 15) * 4) + 2 * (159 * (1 << 15) * 8)
 BATTERY_BYTES_PER_DRAW = {  # algorithmic HBM bytes per tested uniform, per battery kernel
-    "hist": 8.0 + 1.0 / 8,      # read R, write one bit
+    "hist": 8.0 + 1.0 / 8 + 2 * BATTERY_KEYS_PER_DRAW,  # read R, write one bit and 2-byte bucket keys
     "collision": 8.0,           # read R
     "runs": 1.0 / 8,            # read the bits
     "fft_pass1": 16.0,          # read R, write 8 B of complex rows per uniform
     "fft_pass2": 8.0,           # read the rows
+    "hist_count": 2 * BATTERY_KEYS_PER_DRAW + BATTERY_COUNT_FIXED_BYTES / float(32 << 20),
 }
 
 

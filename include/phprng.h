@@ -354,8 +354,8 @@ typedef struct {
 
 typedef struct phprng_battery phprng_battery;
 
-/* Create a battery on HIP device `device`: 42 MB of histograms and 258 MB of
- * transform scratch.  The caller owns it (phprng_battery_destroy). */
+/* Create a battery on HIP device `device`: 42 MB of histograms and about
+ * 720 MB of transform and histogram scratch.  The caller owns it (phprng_battery_destroy). */
 phprng_status phprng_battery_create(phprng_battery **battery, int device);
 phprng_status phprng_battery_destroy(phprng_battery *battery);
 const char *phprng_battery_last_error(const phprng_battery *battery);
@@ -387,9 +387,10 @@ phprng_status phprng_battery_probabilities(int test, double *out, uint64_t capac
 phprng_status phprng_battery_fourier(phprng_battery *battery, const double *r, uint64_t count, double *coef,
                                      void *stream);
 
-/* Kernel time (ms) and launches since the last reset for the five kernel
- * classes: histograms, collision, runs, transform pass 1, transform pass 2
- * (HIP events on the launch stream; waits for them). */
+/* Kernel time (ms) and launches since the last reset for the six kernel
+ * classes (ms and launches are host arrays of 6): histogram keys, collision,
+ * runs, transform pass 1, transform pass 2, histogram counting (HIP events
+ * on the launch stream; waits for them). */
 phprng_status phprng_battery_timing(phprng_battery *battery, double *ms, uint64_t *launches);
 
 /* One-sided P-value min(Q, 1 - Q) of chi^2 with `dof` degrees of freedom (host). */
@@ -420,11 +421,13 @@ typedef struct {
   uint64_t x0, l0;     /* first points c in [x0, x0 + l0), x0 + l0 <= n */
   uint64_t s_lo, s_hi; /* skips in [s_lo, s_hi), 1 <= s_lo < s_hi <= p = 2^31 - 1 */
   uint32_t dim;        /* D, 2..5 */
-  uint32_t bins;       /* cells per following axis; bins^(D-1) <= 2^28 */
+  uint32_t bins;       /* cells per following axis; bins^(D-1) <= 2^24 */
 } phprng_pattern;
 
 /* Add the counts of `pat` to hist, a caller-owned device array of
- * bins^(D-1) uint64 counts (not cleared); asynchronous on `stream`. */
+ * bins^(D-1) uint64 counts (not cleared).  Runs on `stream` and waits for
+ * it; uses stream-ordered scratch of about 2.5 bytes per key of a round of
+ * up to 2^28 keys (at most about 0.75 GB). */
 phprng_status phprng_pattern_histogram(const phprng_pattern *pat, uint64_t *hist, void *stream);
 
 /* chi^2 of a histogram of `pat` (device) against the uniform model: each

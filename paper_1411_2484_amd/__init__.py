@@ -141,7 +141,7 @@ SIGNATURES = {
 
 BATTERY_BLOCK = 1 << 20
 BATTERY_TESTS = ("frequency", "serial2", "serial3", "serial4", "serial5", "poker", "collision", "runs", "fourier")
-BATTERY_KERNELS = ("hist", "collision", "runs", "fft_pass1", "fft_pass2")
+BATTERY_KERNELS = ("hist", "collision", "runs", "fft_pass1", "fft_pass2", "hist_count")
 
 _lib = None
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphprng.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "hostmath.cpp", "server.cpp", "battery.hip", "battery.cpp", "pattern.hip"]
+SOURCES = ["kernels.hip", "runtime.cpp", "hostmath.cpp", "server.cpp", "battery.hip", "battery.cpp", "pattern.hip", "phist.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

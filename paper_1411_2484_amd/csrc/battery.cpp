@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -15,10 +16,11 @@
 #include "phprng.h"
 
 using namespace phprng::bat;
+namespace ph = phprng::ph;
 
 namespace {
 
-constexpr int kKernelClasses = 5;    // hist, collision, runs, fft pass 1, fft pass 2
+constexpr int kKernelClasses = 6;    // hist, collision, runs, fft pass 1, fft pass 2, hist count + add
 constexpr uint64_t kChunkBlocks = 32;  // blocks per inner pass (scratch: 256 MB of transform rows)
 
 const uint32_t kCats[PHPRNG_TEST_COUNT] = {kFreqBins, kCells2, kCells3, kCells4, kCells5,
@@ -98,7 +100,12 @@ struct Pending {
 struct phprng_battery {
   int device = 0;
   unsigned long long *d_hist = nullptr;  // all histograms, one allocation
-  Hists h{};
+  // partitioned histograms of the frequency and serial tests
+  ph::PartSet parts{};
+  BatteryParts bparts{};
+  uint16_t *d_pdata = nullptr;
+  uint32_t *d_pfill = nullptr, *d_pncell = nullptr, *d_pslices = nullptr;
+  unsigned long long **d_phist = nullptr;
   unsigned long long *d_cat[PHPRNG_TEST_COUNT] = {};
   uint64_t *d_bits = nullptr;
   double2 *d_y = nullptr;
@@ -170,7 +177,7 @@ void resolve(phprng_battery *b, bool wait) {
 template <class F>
 phprng_status timed(phprng_battery *b, int cls, hipStream_t st, const char *what, F launch) {
   hipEvent_t a = take_event(b), c = take_event(b);
-  if (a) hipEventRecord(a, st);
+  if (a) (void)hipEventRecord(a, st);
   hipError_t e = launch();
   if (e != hipSuccess) return hip_fail(b, e, what);
   if (a && c && hipEventRecord(c, st) == hipSuccess) {
@@ -223,8 +230,37 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
     b->d_cat[t] = b->d_hist + off;
     off += kCats[t];
   }
-  b->h = Hists{b->d_cat[0], b->d_cat[1], b->d_cat[2], b->d_cat[3], b->d_cat[4],
-               b->d_cat[5], b->d_cat[6], b->d_cat[7], b->d_cat[8]};
+  // partition space: the frequency and serial tests, 2^15 cells per partition
+  std::vector<unsigned long long *> phist;
+  std::vector<uint32_t> pncell;
+  uint32_t npart = 0;
+  for (int t = 0; t < kPartTests; ++t) {
+    const uint32_t cells = kCats[PHPRNG_TEST_FREQUENCY + t];
+    const uint32_t np = (cells + ph::kPartCells - 1) / ph::kPartCells;
+    b->bparts.p0[t] = npart;
+    b->bparts.np[t] = np;
+    for (uint32_t q = 0; q < np; ++q) {
+      phist.push_back(b->d_cat[PHPRNG_TEST_FREQUENCY + t] + (uint64_t)q * ph::kPartCells);
+      pncell.push_back(std::min<uint32_t>(ph::kPartCells, cells - q * ph::kPartCells));
+    }
+    npart += np;
+  }
+  // bucket room per partition and chunk: the frequency test's share (2^20 keys
+  // per partition for 32 blocks) with a margin; any surplus goes to atomics
+  const uint32_t cap = (uint32_t)(kChunkBlocks * kBlock / 32 * 5 / 4 + 4096);
+  const uint32_t nslice = 2;
+  ok = hipMalloc(&b->d_pdata, (uint64_t)npart * cap * sizeof(uint16_t)) == hipSuccess &&
+       hipMalloc(&b->d_pfill, npart * sizeof(uint32_t)) == hipSuccess &&
+       hipMalloc(&b->d_pncell, npart * sizeof(uint32_t)) == hipSuccess &&
+       hipMalloc(&b->d_pslices, (uint64_t)npart * nslice * ph::kPartCells * sizeof(uint32_t)) == hipSuccess &&
+       hipMalloc(&b->d_phist, npart * sizeof(unsigned long long *)) == hipSuccess;
+  if (!ok || hipMemcpy(b->d_phist, phist.data(), npart * sizeof(void *), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_pncell, pncell.data(), npart * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(b->d_pfill, 0, npart * sizeof(uint32_t)) != hipSuccess) {
+    phprng_battery_destroy(b);
+    return PHPRNG_E_NOMEM;
+  }
+  b->parts = ph::PartSet{b->d_pdata, b->d_pfill, b->d_phist, b->d_pncell, b->d_pslices, npart, cap, nslice, 0};
   // roots of unity in extended precision, then rounded
   std::vector<double2> tw(3 * 1024);
   const long double two_pi = 6.283185307179586476925286766559005768L;
@@ -260,12 +296,13 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
 
 phprng_status phprng_battery_destroy(phprng_battery *b) {
   if (!b) return PHPRNG_E_INVALID;
-  hipSetDevice(b->device);
+  (void)hipSetDevice(b->device);
   resolve(b, true);
-  for (hipEvent_t e : b->free_events) hipEventDestroy(e);
-  void *bufs[] = {b->d_hist, b->d_bits, b->d_y, b->d_tw, b->d_probs, b->d_jobs, b->d_chi2, b->d_total, b->d_discard};
+  for (hipEvent_t e : b->free_events) (void)hipEventDestroy(e);
+  void *bufs[] = {b->d_hist,  b->d_bits,  b->d_y,      b->d_tw,     b->d_probs,   b->d_jobs,   b->d_chi2,
+                  b->d_total, b->d_discard, b->d_pdata, b->d_pfill, b->d_pncell, b->d_pslices, b->d_phist};
   for (void *p : bufs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   delete b;
   return PHPRNG_OK;
 }
@@ -274,7 +311,7 @@ const char *phprng_battery_last_error(const phprng_battery *b) { return b ? b->e
 
 phprng_status phprng_battery_reset(phprng_battery *b, void *stream) {
   if (!b) return PHPRNG_E_INVALID;
-  hipSetDevice(b->device);
+  (void)hipSetDevice(b->device);
   uint64_t total = 0;
   for (int t = 0; t < PHPRNG_TEST_COUNT; ++t) total += kCats[t];
   hipError_t e = hipMemsetAsync(b->d_hist, 0, total * sizeof(unsigned long long), (hipStream_t)stream);
@@ -290,13 +327,16 @@ phprng_status phprng_battery_reset(phprng_battery *b, void *stream) {
 phprng_status phprng_battery_accumulate(phprng_battery *b, const double *r, uint64_t count, void *stream) {
   phprng_status s = check_blocks(b, r, count);
   if (s != PHPRNG_OK) return s;
-  hipSetDevice(b->device);
+  (void)hipSetDevice(b->device);
   hipStream_t st = (hipStream_t)stream;
   const uint64_t nblocks = count / kBlock;
   for (uint64_t b0 = 0; b0 < nblocks; b0 += kChunkBlocks) {
     const uint64_t nb = nblocks - b0 < kChunkBlocks ? nblocks - b0 : kChunkBlocks;
     const double *src = r + b0 * kBlock;
-    if ((s = timed(b, 0, st, "hist kernel", [&] { return launch_hist(src, nb, b->h, b->d_bits, st); })) != PHPRNG_OK ||
+    if ((s = timed(b, 0, st, "hist kernel",
+                   [&] {
+                     return launch_hist(src, nb, b->parts, b->bparts, b->d_cat[PHPRNG_TEST_POKER], b->d_bits, st);
+                   })) != PHPRNG_OK ||
         (s = timed(b, 1, st, "collision kernel",
                    [&] { return launch_collision(src, nb, b->d_cat[PHPRNG_TEST_COLLISION], st); })) != PHPRNG_OK ||
         (s = timed(b, 2, st, "runs kernel",
@@ -304,6 +344,10 @@ phprng_status phprng_battery_accumulate(phprng_battery *b, const double *r, uint
         (s = timed(b, 3, st, "fft pass 1", [&] { return launch_fft_pass1(src, nb, b->d_y, b->tw, st); })) != PHPRNG_OK ||
         (s = timed(b, 4, st, "fft pass 2", [&] {
            return launch_fft_pass2(b->d_y, nb, b->d_cat[PHPRNG_TEST_FOURIER], nullptr, b->tw, b->fourier_scale, st);
+         })) != PHPRNG_OK ||
+        (s = timed(b, 5, st, "histogram count", [&] {
+           hipError_t e = ph::launch_count(b->parts, st);
+           return e == hipSuccess ? ph::launch_add(b->parts, st) : e;
          })) != PHPRNG_OK)
       return s;
   }
@@ -314,7 +358,7 @@ phprng_status phprng_battery_fourier(phprng_battery *b, const double *r, uint64_
   phprng_status s = check_blocks(b, r, count);
   if (s != PHPRNG_OK) return s;
   if (count && !coef) return fail(b, PHPRNG_E_INVALID, "null coefficient array");
-  hipSetDevice(b->device);
+  (void)hipSetDevice(b->device);
   hipStream_t st = (hipStream_t)stream;
   const uint64_t nblocks = count / kBlock;
   for (uint64_t b0 = 0; b0 < nblocks; b0 += kChunkBlocks) {
@@ -329,7 +373,7 @@ phprng_status phprng_battery_fourier(phprng_battery *b, const double *r, uint64_
 
 phprng_status phprng_battery_report(phprng_battery *b, phprng_test_result *out, void *stream) {
   if (!b || !out) return PHPRNG_E_INVALID;
-  hipSetDevice(b->device);
+  (void)hipSetDevice(b->device);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_chi2(b->d_jobs, PHPRNG_TEST_COUNT, b->d_chi2, b->d_total, st);
   double chi2[PHPRNG_TEST_COUNT];
@@ -360,7 +404,7 @@ phprng_status phprng_battery_counts(phprng_battery *b, int test, uint64_t *out, 
   if (ncat) *ncat = kCats[test];
   if (!out) return PHPRNG_OK;
   if (capacity < kCats[test]) return fail(b, PHPRNG_E_RANGE, "capacity below %u", kCats[test]);
-  hipSetDevice(b->device);
+  (void)hipSetDevice(b->device);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(out, b->d_cat[test], kCats[test] * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -385,7 +429,7 @@ phprng_status phprng_battery_probabilities(int test, double *out, uint64_t capac
 
 phprng_status phprng_battery_timing(phprng_battery *b, double *ms, uint64_t *launches) {
   if (!b) return PHPRNG_E_INVALID;
-  hipSetDevice(b->device);
+  (void)hipSetDevice(b->device);
   resolve(b, true);
   for (int i = 0; i < kKernelClasses; ++i) {
     if (ms) ms[i] = b->ms[i];

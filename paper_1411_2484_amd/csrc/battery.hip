@@ -16,17 +16,6 @@ __device__ __forceinline__ uint32_t bin_of(double x, uint32_t b) {
   return u < b ? u : b - 1;
 }
 
-template <int D, uint32_t B>
-__device__ __forceinline__ void serial_tile(const double *t, uint32_t len, unsigned long long *cells) {
-  const uint32_t ntup = len / D;
-  for (uint32_t j = threadIdx.x; j < ntup; j += blockDim.x) {
-    uint32_t cell = 0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) cell = cell * B + bin_of(t[j * D + i], B);
-    atomicAdd(&cells[cell], 1ull);
-  }
-}
-
 // Poker hand category from the number of equal pairs among the five digits:
 // 0 all different, 1 one pair, 2 two pairs, 3 three of a kind, 4 full house,
 // 6 four of a kind, 10 five of a kind.
@@ -39,31 +28,60 @@ __device__ __forceinline__ uint32_t poker_cat(const uint32_t d[5]) {
   return pairs <= 4 ? pairs : (pairs == 6 ? 5u : 6u);
 }
 
-// One tile of one block: frequency, serial D = 2..5 and poker histograms, and
-// the bits R > 1/2 packed one 64-bit word per 64 uniforms (for the runs test).
-__global__ __launch_bounds__(256) void hist_kernel(const double *__restrict__ r, Hists h,
-                                                   uint64_t *__restrict__ bits) {
+// Keys of one test for one tile, held in registers for the partitioned
+// histogram: item j = threadIdx.x + it * 256 is the j-th D-tuple of the tile
+// (D = 1: the j-th uniform), its key the partition-space offset of the test
+// plus its cell (first element most significant).
+template <int D, uint32_t B, int K>
+__device__ __forceinline__ void tuple_keys(const double *t, uint32_t len, uint32_t key0, uint32_t (&key)[K]) {
+  const uint32_t ntup = len / D;
+#pragma unroll
+  for (int it = 0; it < K; ++it) {
+    const uint32_t j = threadIdx.x + it * 256;
+    uint32_t cell = 0;
+    if (j < ntup) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) cell = cell * B + bin_of(t[j * D + i], B);
+    }
+    key[it] = j < ntup ? key0 + cell : ph::kNoKey;
+  }
+}
+
+template <int D, uint32_t B, int K>
+__device__ __forceinline__ void tuple_test(const double *t, uint32_t len, const ph::PartSet &P, uint32_t p0,
+                                           uint32_t np, uint32_t *cnt, uint32_t *base) {
+  uint32_t key[K];
+  tuple_keys<D, B, K>(t, len, p0 << ph::kPartBits, key);
+  ph::scatter_regs<256, K>(key, P, p0, np, cnt, base);
+}
+
+// One tile of one block: frequency and serial D = 2..5 keys into the
+// partitioned histograms, the poker histogram, and the bits R > 1/2 packed
+// one 64-bit word per 64 uniforms (for the runs test).
+__global__ __launch_bounds__(256) void hist_kernel(const double *__restrict__ r, ph::PartSet P, BatteryParts bp,
+                                                   unsigned long long *poker_hist, uint64_t *__restrict__ bits) {
   __shared__ double t[kHistTile];
   __shared__ uint32_t poker[kPokerCats];
+  __shared__ uint32_t cnt[kMaxTestParts], base[kMaxTestParts];
   const uint32_t tile = blockIdx.x % kHistTilesPerBlock;
   const uint64_t blk = blockIdx.x / kHistTilesPerBlock;
   const uint32_t off = tile * kHistTile;
   const uint32_t len = (kBlock - off) < kHistTile ? (kBlock - off) : kHistTile;  // 3840 or 256
-  const uint64_t base = blk * kBlock + off;
+  const uint64_t base_i = blk * kBlock + off;
   if (threadIdx.x < kPokerCats) poker[threadIdx.x] = 0;
   // len is a multiple of 256, so every wave covers 64 consecutive uniforms per step
   for (uint32_t i = threadIdx.x; i < len; i += 256) {
-    const double x = r[base + i];
+    const double x = r[base_i + i];
     t[i] = x;
-    atomicAdd(&h.freq[bin_of(x, kFreqBins)], 1ull);
     const uint64_t word = __ballot(x > 0.5);
-    if ((threadIdx.x & 63) == 0) bits[(base + i) >> 6] = word;
+    if ((threadIdx.x & 63) == 0) bits[(base_i + i) >> 6] = word;
   }
   __syncthreads();
-  serial_tile<2, kAxis2>(t, len, h.s2);
-  serial_tile<3, kAxis3>(t, len, h.s3);
-  serial_tile<4, kAxis4>(t, len, h.s4);
-  serial_tile<5, kAxis5>(t, len, h.s5);
+  tuple_test<1, kFreqBins, kHistTile / 256>(t, len, P, bp.p0[0], bp.np[0], cnt, base);
+  tuple_test<2, kAxis2, (kHistTile / 2 + 255) / 256>(t, len, P, bp.p0[1], bp.np[1], cnt, base);
+  tuple_test<3, kAxis3, (kHistTile / 3 + 255) / 256>(t, len, P, bp.p0[2], bp.np[2], cnt, base);
+  tuple_test<4, kAxis4, (kHistTile / 4 + 255) / 256>(t, len, P, bp.p0[3], bp.np[3], cnt, base);
+  tuple_test<5, kAxis5, (kHistTile / 5 + 255) / 256>(t, len, P, bp.p0[4], bp.np[4], cnt, base);
   const uint32_t nhand = len / 5;
   for (uint32_t j = threadIdx.x; j < nhand; j += 256) {
     uint32_t d[5];
@@ -72,7 +90,8 @@ __global__ __launch_bounds__(256) void hist_kernel(const double *__restrict__ r,
     atomicAdd(&poker[poker_cat(d)], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < kPokerCats && poker[threadIdx.x]) atomicAdd(&h.poker[threadIdx.x], (unsigned long long)poker[threadIdx.x]);
+  if (threadIdx.x < kPokerCats && poker[threadIdx.x])
+    atomicAdd(&poker_hist[threadIdx.x], (unsigned long long)poker[threadIdx.x]);
 }
 
 // One collision trial per workgroup: 2^14 uniforms into 2^20 urns held as a
@@ -382,8 +401,9 @@ __global__ __launch_bounds__(256) void interleave_kernel(const double *__restric
 
 }  // namespace
 
-hipError_t launch_hist(const double *r, uint64_t nblocks, Hists h, uint64_t *bits, hipStream_t st) {
-  hist_kernel<<<dim3((unsigned)(nblocks * kHistTilesPerBlock)), dim3(256), 0, st>>>(r, h, bits);
+hipError_t launch_hist(const double *r, uint64_t nblocks, const ph::PartSet &P, const BatteryParts &bp,
+                       unsigned long long *poker, uint64_t *bits, hipStream_t st) {
+  hist_kernel<<<dim3((unsigned)(nblocks * kHistTilesPerBlock)), dim3(256), 0, st>>>(r, P, bp, poker, bits);
   return hipGetLastError();
 }
 

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "phist.hpp"
+
 namespace phprng {
 namespace bat {
 
@@ -37,8 +39,12 @@ constexpr uint32_t kFftCols = 8;                           // pass-1 columns per
 constexpr uint32_t kFftPass1Groups = kFftN2 / kFftCols;   // workgroups per block, pass 1
 constexpr uint32_t kFftPass2Groups = kFftN1 / 2 + 1;      // row pairs per block, pass 2
 
-struct Hists {
-  unsigned long long *freq, *s2, *s3, *s4, *s5, *poker, *coll, *runs, *fourier;
+// The frequency and serial tests go through partitioned histograms: test t
+// owns partitions [p0[t], p0[t] + np[t]) of one partition space.
+constexpr int kPartTests = 5;
+constexpr uint32_t kMaxTestParts = 32;
+struct BatteryParts {
+  uint32_t p0[kPartTests], np[kPartTests];
 };
 
 // Roots of unity with the positive exponent of the paper's Fourier sum:
@@ -55,7 +61,8 @@ struct Chi2Job {
   uint32_t pad;
 };
 
-hipError_t launch_hist(const double *r, uint64_t nblocks, Hists h, uint64_t *bits, hipStream_t st);
+hipError_t launch_hist(const double *r, uint64_t nblocks, const ph::PartSet &P, const BatteryParts &bp,
+                       unsigned long long *poker, uint64_t *bits, hipStream_t st);
 hipError_t launch_collision(const double *r, uint64_t nblocks, unsigned long long *coll, hipStream_t st);
 hipError_t launch_runs(const uint64_t *bits, uint64_t nblocks, unsigned long long *runs, hipStream_t st);
 hipError_t launch_fft_pass1(const double *r, uint64_t nblocks, double2 *y, Twiddles tw, hipStream_t st);

@@ -7,22 +7,29 @@
 // the next step: m = c^d mod n, then (m + s)^e, (m + s + (a s mod p))^e, ...
 // One workgroup takes one first point and 16384 consecutive skips; each
 // thread decrypts its first point once (a 32-bit exponent chain) and then
-// runs the cheap forward chain per skip.
+// runs the cheap forward chain per skip.  The cells go through partitioned
+// histograms (phist.hpp): a global atomic per tuple would cap the rate at the
+// device's atomic throughput.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "arith.hpp"
 #include "hostmath.hpp"
 #include "phprng.h"
+#include "phist.hpp"
 #include "stats.hpp"
 
 namespace phprng {
 namespace pat {
 
 constexpr uint32_t kChunk = 256 * 64;  // skips per workgroup
-constexpr uint64_t kMaxCells = 1ull << 28;
+constexpr uint32_t kHalf = 256 * 32;   // skips whose keys a workgroup holds in registers at once
+constexpr uint32_t kMaxParts = 512;
+constexpr uint64_t kMaxCells = (uint64_t)kMaxParts << ph::kPartBits;  // 2^24
+constexpr uint64_t kRoundKeys = 1ull << 28;  // keys per bucket round
 constexpr unsigned kChiBlocks = 1024;
 constexpr uint64_t kMaxGroups = 1ull << 22;  // workgroups per pattern launch
 
@@ -50,24 +57,29 @@ __device__ __forceinline__ uint32_t cell_bin(uint32_t c, const PatArgs &A) {
 }
 
 template <int EK, int D>
-__global__ __launch_bounds__(256) void pattern_kernel(PatArgs A) {
+__global__ __launch_bounds__(256) void pattern_kernel(PatArgs A, ph::PartSet P) {
+  __shared__ uint32_t cnt[kMaxParts], base[kMaxParts];
   const uint64_t i = blockIdx.x / A.nchunks;
   const uint64_t ch = blockIdx.x - i * A.nchunks;
   const uint32_t m = dev::encrypt32<0>(A.x0 + (uint32_t)i, A.n, A.ninv, A.kd, A.d, A.dbits);
-  const uint64_t s0 = A.s_lo + ch * kChunk + threadIdx.x;
-  for (uint32_t it = 0; it < kChunk / 256; ++it) {
-    const uint64_t s = s0 + (uint64_t)it * 256;
-    if (s >= A.s_hi) break;
-    uint32_t sk = (uint32_t)s;
-    uint32_t mk = dev::addmod32(m, sk, A.n);
-    uint32_t cell = cell_bin(dev::encrypt32<EK>(mk, A.n, A.ninv, A.kc, A.e, A.ebits), A);
+  for (uint32_t half = 0; half < kChunk / kHalf; ++half) {
+    const uint64_t s0 = A.s_lo + ch * kChunk + half * kHalf + threadIdx.x;
+    uint32_t key[kHalf / 256];
 #pragma unroll
-    for (int j = 2; j < D; ++j) {
-      sk = dev::mulmod_p31(sk, kA32);
-      mk = dev::addmod32(mk, sk, A.n);
-      cell = cell * A.bins + cell_bin(dev::encrypt32<EK>(mk, A.n, A.ninv, A.kc, A.e, A.ebits), A);
+    for (uint32_t it = 0; it < kHalf / 256; ++it) {
+      const uint64_t s = s0 + (uint64_t)it * 256;
+      uint32_t sk = (uint32_t)(s < A.s_hi ? s : A.s_lo);  // lanes past the range compute a valid dummy
+      uint32_t mk = dev::addmod32(m, sk, A.n);
+      uint32_t cell = cell_bin(dev::encrypt32<EK>(mk, A.n, A.ninv, A.kc, A.e, A.ebits), A);
+#pragma unroll
+      for (int j = 2; j < D; ++j) {
+        sk = dev::mulmod_p31(sk, kA32);
+        mk = dev::addmod32(mk, sk, A.n);
+        cell = cell * A.bins + cell_bin(dev::encrypt32<EK>(mk, A.n, A.ninv, A.kc, A.e, A.ebits), A);
+      }
+      key[it] = s < A.s_hi ? cell : ph::kNoKey;
     }
-    atomicAdd(&A.hist[cell], 1ull);
+    ph::scatter_regs<256, kHalf / 256>(key, P, 0, P.npart, cnt, base);
   }
 }
 
@@ -138,15 +150,27 @@ __global__ __launch_bounds__(256) void pattern_sum_kernel(double *part, unsigned
 }
 
 template <int EK>
-hipError_t launch_dim(const PatArgs &A, unsigned grid, int dim, hipStream_t st) {
+hipError_t launch_dim(const PatArgs &A, const ph::PartSet &P, unsigned grid, int dim, hipStream_t st) {
   switch (dim) {
-    case 2: pattern_kernel<EK, 2><<<grid, 256, 0, st>>>(A); break;
-    case 3: pattern_kernel<EK, 3><<<grid, 256, 0, st>>>(A); break;
-    case 4: pattern_kernel<EK, 4><<<grid, 256, 0, st>>>(A); break;
-    default: pattern_kernel<EK, 5><<<grid, 256, 0, st>>>(A); break;
+    case 2: pattern_kernel<EK, 2><<<grid, 256, 0, st>>>(A, P); break;
+    case 3: pattern_kernel<EK, 3><<<grid, 256, 0, st>>>(A, P); break;
+    case 4: pattern_kernel<EK, 4><<<grid, 256, 0, st>>>(A, P); break;
+    default: pattern_kernel<EK, 5><<<grid, 256, 0, st>>>(A, P); break;
   }
   return hipGetLastError();
 }
+
+hipError_t launch_ek(const PatArgs &A, const ph::PartSet &P, unsigned grid, int dim, uint64_t e, hipStream_t st) {
+  switch (e) {
+    case 3: return launch_dim<3>(A, P, grid, dim, st);
+    case 5: return launch_dim<5>(A, P, grid, dim, st);
+    case 9: return launch_dim<9>(A, P, grid, dim, st);
+    case 17: return launch_dim<17>(A, P, grid, dim, st);
+    default: return launch_dim<0>(A, P, grid, dim, st);
+  }
+}
+
+
 
 int bit_length(uint64_t x) {
   int b = 0;
@@ -206,26 +230,69 @@ phprng_status phprng_pattern_histogram(const phprng_pattern *P, uint64_t *hist, 
   A.nchunks = (P->s_hi - P->s_lo + pat::kChunk - 1) / pat::kChunk;
   A.binscale = (double)P->bins / (double)P->n;
   A.hist = reinterpret_cast<unsigned long long *>(hist);
-  // one launch per batch of first points, each within 2^22 workgroups (a
-  // dispatch counts its work-items in 32 bits)
-  const uint64_t per_launch = std::max<uint64_t>(1, pat::kMaxGroups / A.nchunks);
+  // Rounds of at most 2^28 keys (and 2^22 workgroups): a round is a batch of
+  // first points over the whole skip range, or one first point over a slice
+  // of it.  Each round scatters its keys into the partition buckets, then
+  // the buckets are counted into the histogram.
+  const uint64_t srange = P->s_hi - P->s_lo;
+  const uint64_t s_step = srange > pat::kRoundKeys ? pat::kRoundKeys : srange;
+  const uint64_t fp_per_round = std::max<uint64_t>(
+      1, std::min({P->l0, pat::kRoundKeys / s_step, pat::kMaxGroups / ((s_step + pat::kChunk - 1) / pat::kChunk)}));
+  const uint64_t round_keys = fp_per_round * s_step;
+  const uint32_t npart = (uint32_t)((ncell + ph::kPartCells - 1) / ph::kPartCells);
+  const uint32_t nslice = std::max<uint32_t>(1, 512 / npart);
+  // bucket room: the expected share of a full partition plus a margin (any
+  // surplus is added with atomics)
+  const uint64_t share = (round_keys * std::min<uint64_t>(ph::kPartCells, ncell) + ncell - 1) / ncell;
+  const uint32_t cap = (uint32_t)std::min<uint64_t>(share + share / 4 + 4096, 0xffffffffull);
+  const uint64_t bytes_data = ((uint64_t)npart * cap * 2 + 255) / 256 * 256;
+  const uint64_t bytes_slices = (uint64_t)npart * nslice * ph::kPartCells * 4;
+  const uint64_t bytes = bytes_data + bytes_slices + npart * 16;
   hipStream_t s = (hipStream_t)stream;
-  for (uint64_t i0 = 0; i0 < P->l0; i0 += per_launch) {
-    const uint64_t cnt = std::min<uint64_t>(per_launch, P->l0 - i0);
-    pat::PatArgs B = A;
-    B.x0 = (uint32_t)(P->x0 + i0);
-    const unsigned grid = (unsigned)(cnt * A.nchunks);
-    hipError_t e;
-    switch (P->e) {
-      case 3: e = pat::launch_dim<3>(B, grid, P->dim, s); break;
-      case 5: e = pat::launch_dim<5>(B, grid, P->dim, s); break;
-      case 9: e = pat::launch_dim<9>(B, grid, P->dim, s); break;
-      case 17: e = pat::launch_dim<17>(B, grid, P->dim, s); break;
-      default: e = pat::launch_dim<0>(B, grid, P->dim, s); break;
-    }
-    if (e != hipSuccess) return PHPRNG_E_DEVICE;
+  void *mem = nullptr;
+  if (hipMallocAsync(&mem, bytes, s) != hipSuccess) return PHPRNG_E_NOMEM;
+  char *cm = (char *)mem;
+  ph::PartSet PS;
+  PS.data = (uint16_t *)cm;
+  PS.slices = (uint32_t *)(cm + bytes_data);
+  PS.fill = (uint32_t *)(cm + bytes_data + bytes_slices);
+  uint32_t *ncell_d = PS.fill + npart;
+  // pointer table after fill[npart] and ncell[npart]: 8 npart bytes past a
+  // 256-byte aligned base, so 8-byte aligned
+  unsigned long long **hist_d = (unsigned long long **)(PS.fill + 2 * npart);
+  PS.ncell = ncell_d;
+  PS.hist = hist_d;
+  PS.npart = npart;
+  PS.cap = cap;
+  PS.nslice = nslice;
+  PS.pad = 0;
+  std::vector<uint32_t> tab32(2 * npart, 0);  // fill = 0 | ncell
+  std::vector<unsigned long long *> tabp(npart);
+  for (uint32_t q = 0; q < npart; ++q) {
+    tab32[npart + q] = (uint32_t)std::min<uint64_t>(ph::kPartCells, ncell - (uint64_t)q * ph::kPartCells);
+    tabp[q] = reinterpret_cast<unsigned long long *>(hist) + (uint64_t)q * ph::kPartCells;
   }
-  return PHPRNG_OK;
+  hipError_t e = hipMemcpyAsync(PS.fill, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hist_d, tabp.data(), npart * sizeof(void *), hipMemcpyHostToDevice, s);
+  for (uint64_t i0 = 0; e == hipSuccess && i0 < P->l0; i0 += fp_per_round) {
+    const uint64_t cnt = std::min<uint64_t>(fp_per_round, P->l0 - i0);
+    for (uint64_t s_lo = P->s_lo; e == hipSuccess && s_lo < P->s_hi; s_lo += s_step) {
+      pat::PatArgs B = A;
+      B.x0 = (uint32_t)(P->x0 + i0);
+      B.s_lo = s_lo;
+      B.s_hi = std::min<uint64_t>(s_lo + s_step, P->s_hi);
+      B.nchunks = (B.s_hi - B.s_lo + pat::kChunk - 1) / pat::kChunk;
+      e = pat::launch_ek(B, PS, (unsigned)(cnt * B.nchunks), P->dim, P->e, s);
+      if (e == hipSuccess) e = ph::launch_count(PS, s);
+      if (e == hipSuccess) e = ph::launch_add(PS, s);
+    }
+  }
+  // the host tables above must outlive their asynchronous copies
+  hipError_t se = hipStreamSynchronize(s);
+  hipError_t fe = hipFreeAsync(mem, s);
+  if (e == hipSuccess) e = se;
+  if (e == hipSuccess) e = fe;
+  return e == hipSuccess ? PHPRNG_OK : PHPRNG_E_DEVICE;
 }
 
 phprng_status phprng_pattern_chi2(const phprng_pattern *P, const uint64_t *hist, double *chi2, double *p_value,

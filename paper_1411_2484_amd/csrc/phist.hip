@@ -1,0 +1,52 @@
+// Stages 2 and 3 of the partitioned histograms (phist.hpp).
+#include "phist.hpp"
+
+namespace phprng {
+namespace ph {
+
+namespace {
+
+// One workgroup per (partition, slice): count this slice of the bucket's
+// offsets in LDS and store the partition's counts for the slice.
+__global__ __launch_bounds__(1024) void count_kernel(PartSet P) {
+  __shared__ uint32_t c[kPartCells];
+  const uint32_t p = blockIdx.x / P.nslice, s = blockIdx.x % P.nslice;
+  for (uint32_t i = threadIdx.x; i < kPartCells; i += 1024) c[i] = 0;
+  __syncthreads();
+  const uint32_t fill = P.fill[p] < P.cap ? P.fill[p] : P.cap;
+  const uint32_t lo = (uint32_t)((uint64_t)fill * s / P.nslice), hi = (uint32_t)((uint64_t)fill * (s + 1) / P.nslice);
+  const uint16_t *d = P.data + (uint64_t)p * P.cap;
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += 1024) atomicAdd(&c[d[i]], 1u);
+  __syncthreads();
+  uint32_t *out = P.slices + ((uint64_t)p * P.nslice + s) * kPartCells;
+  const uint32_t nc = P.ncell[p];
+  for (uint32_t i = threadIdx.x; i < nc; i += 1024) out[i] = c[i];
+}
+
+// hist[p][j] += sum over slices; the first thread of each partition clears
+// its fill counter (stage 2 has finished reading it).
+__global__ __launch_bounds__(256) void add_kernel(PartSet P) {
+  const uint32_t p = blockIdx.x / (kPartCells / 256);
+  const uint32_t j = (blockIdx.x % (kPartCells / 256)) * 256 + threadIdx.x;
+  if (j == 0) P.fill[p] = 0;
+  if (j >= P.ncell[p]) return;
+  const uint32_t *in = P.slices + (uint64_t)p * P.nslice * kPartCells + j;
+  unsigned long long s = 0;
+  for (uint32_t k = 0; k < P.nslice; ++k) s += in[(uint64_t)k * kPartCells];
+  if (s) P.hist[p][j] += s;
+}
+
+}  // namespace
+
+hipError_t launch_count(const PartSet &P, hipStream_t st) {
+  count_kernel<<<dim3(P.npart * P.nslice), dim3(1024), 0, st>>>(P);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(const PartSet &P, hipStream_t st) {
+  add_kernel<<<dim3(P.npart * (kPartCells / 256)), dim3(256), 0, st>>>(P);
+  return hipGetLastError();
+}
+
+}  // namespace ph
+}  // namespace phprng

@@ -1,0 +1,72 @@
+// Partitioned histograms for gfx950.  A global atomic per histogram entry
+// runs at the device's atomic rate (about 2.7e10 per second, whatever the
+// scope or locality), so large histograms are built in three stages:
+//   1. scatter (inside the producing kernel): a workgroup ranks its keys by
+//      partition (2^15 cells each) with LDS atomics, reserves room in every
+//      partition's bucket with one global atomic per partition, and writes
+//      the 15-bit cell offsets (uint16) into the buckets;
+//   2. count: one workgroup per (partition, slice of its bucket) counts the
+//      offsets in a 128 KB LDS histogram and stores the counts;
+//   3. add: the per-slice counts are summed into the uint64 histogram and the
+//      bucket fill counters are cleared for the next round.
+// A bucket that runs full sends its surplus keys straight to the histogram
+// with global atomics, so the result is exact for any key distribution.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace phprng {
+namespace ph {
+
+constexpr int kPartBits = 15;
+constexpr uint32_t kPartCells = 1u << kPartBits;
+constexpr uint32_t kNoKey = 0xffffffffu;
+
+struct PartSet {
+  uint16_t *data;                     // [npart][cap] cell offsets
+  uint32_t *fill;                     // [npart] entries written this round
+  unsigned long long *const *hist;    // [npart] first cell of each partition in its histogram
+  const uint32_t *ncell;              // [npart] cells of each partition (<= 2^15)
+  uint32_t *slices;                   // [npart][nslice][2^15] stage-2 counts
+  uint32_t npart, cap, nslice, pad;
+};
+
+// Stage 1 for keys held in registers: key[it] of thread t is item t + it * NT;
+// keys are (partition << 15) | offset with partition in [p0, p0 + np), or
+// kNoKey.  cnt and base are LDS arrays of np words.  Ends with a barrier.
+template <int NT, int K>
+__device__ __forceinline__ void scatter_regs(const uint32_t (&key)[K], const PartSet &P, uint32_t p0, uint32_t np,
+                                             uint32_t *cnt, uint32_t *base) {
+  for (uint32_t i = threadIdx.x; i < np; i += NT) cnt[i] = 0;
+  __syncthreads();
+  uint32_t rank[K];
+#pragma unroll
+  for (int it = 0; it < K; ++it)
+    rank[it] = key[it] != kNoKey ? atomicAdd(&cnt[(key[it] >> kPartBits) - p0], 1u) : 0u;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < np; i += NT) {
+    const uint32_t c = cnt[i];
+    base[i] = c ? atomicAdd(&P.fill[p0 + i], c) : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < K; ++it) {
+    if (key[it] == kNoKey) continue;
+    const uint32_t p = key[it] >> kPartBits;
+    const uint32_t off = key[it] & (kPartCells - 1);
+    const uint32_t j = base[p - p0] + rank[it];
+    if (j < P.cap)
+      P.data[(uint64_t)p * P.cap + j] = (uint16_t)off;
+    else
+      atomicAdd(&P.hist[p][off], 1ull);
+  }
+  __syncthreads();
+}
+
+hipError_t launch_count(const PartSet &P, hipStream_t st);
+hipError_t launch_add(const PartSet &P, hipStream_t st);
+
+}  // namespace ph
+}  // namespace phprng
