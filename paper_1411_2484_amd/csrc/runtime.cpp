@@ -1026,7 +1026,7 @@ extern "C" phprng_status phprng_autotune(phprng_ctx *c, uint64_t draws, phprng_t
   // confirm the winner against the starting shape with more repetitions
   if (result == PHPRNG_OK && run(bestT, 7) > run(orig, 7)) bestT = orig;
   for (uint64_t i = 0; i < ninst; ++i) c->inst[i].x = saved[i];
-  hipFree(d_r);
+  (void)hipFree(d_r);
   c->tuning = result == PHPRNG_OK ? bestT : orig;
   if (best) *best = c->tuning;
   return result;
@@ -1041,7 +1041,7 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
                                              void *stream, phprng_graph **graph) {
   if (!c || !graph || nreq == 0) return PHPRNG_E_INVALID;
   *graph = nullptr;
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   {
     std::vector<uint8_t> used(c->inst.size(), 0);
     for (uint64_t i = 0; i < nreq; ++i) {
@@ -1080,7 +1080,7 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
     e = launch_persistent(A, (unsigned)(c->num_cus * T.blocks_per_cu), T.block_threads, T.unroll, has64, cap_stream);
   if (e == hipSuccess) e = launch_advance(g->d_req, nreq, cap_stream);
   hipError_t e2 = hipStreamEndCapture(cap_stream, &g->graph);
-  hipStreamDestroy(cap_stream);
+  (void)hipStreamDestroy(cap_stream);
   if (e != hipSuccess || e2 != hipSuccess) return c->hip_fail(e != hipSuccess ? e : e2, "graph capture");
   if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
     return c->hip_fail(e, "graph instantiate");
@@ -1092,7 +1092,7 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
 extern "C" phprng_status phprng_graph_launch(phprng_graph *g, void *stream) {
   if (!g || !g->ctx) return PHPRNG_E_INVALID;
   phprng_ctx *c = g->ctx;
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   // range check before launching: each instance advances by its count
   for (size_t i = 0; i < g->inst.size(); ++i) {
     const HostInst &h = c->inst[g->inst[i]];
@@ -1115,8 +1115,8 @@ extern "C" phprng_status phprng_graph_launch(phprng_graph *g, void *stream) {
 
 extern "C" phprng_status phprng_graph_destroy(phprng_graph *g) {
   if (!g) return PHPRNG_E_INVALID;
-  if (g->ctx) hipSetDevice(g->ctx->device);
-  hipDeviceSynchronize();
+  if (g->ctx) (void)hipSetDevice(g->ctx->device);
+  (void)hipDeviceSynchronize();
   if (g->exec) hipGraphExecDestroy(g->exec);
   if (g->graph) hipGraphDestroy(g->graph);
   hipFree(g->d_req);

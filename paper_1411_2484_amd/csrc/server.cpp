@@ -38,7 +38,7 @@ int64_t now_ns() {
 // First-fit allocator over [0, capacity) elements with coalescing frees.
 class Arena {
  public:
-  explicit Arena(uint64_t cap) : cap_(cap) { free_[0] = cap; }
+  explicit Arena(uint64_t cap) { free_[0] = cap; }
   bool alloc(uint64_t n, uint64_t *off) {
     if (n == 0) {
       *off = 0;
@@ -76,7 +76,7 @@ class Arena {
   uint64_t used() const { return used_; }
 
  private:
-  uint64_t cap_, used_ = 0;
+  uint64_t used_ = 0;
   std::map<uint64_t, uint64_t> free_;
 };
 
@@ -233,7 +233,7 @@ void phprng_server::loop() {
   }
   // drain: wait for every batch still on the device
   for (auto &b : batches)
-    if (b.active) hipEventSynchronize(b.done);
+    if (b.active) (void)hipEventSynchronize(b.done);
   retire_finished();
 }
 
@@ -324,9 +324,9 @@ extern "C" phprng_status phprng_server_destroy(phprng_server *s) {
   s->cv_work.notify_all();
   if (s->thread.joinable()) s->thread.join();
   for (auto &b : s->batches)
-    if (b.done) hipEventDestroy(b.done);
-  for (auto st : s->streams) hipStreamDestroy(st);
-  hipFree(s->arena_ptr);
+    if (b.done) (void)hipEventDestroy(b.done);
+  for (auto st : s->streams) (void)hipStreamDestroy(st);
+  (void)hipFree(s->arena_ptr);
   delete s->arena;
   delete s;
   return PHPRNG_OK;
