@@ -237,8 +237,8 @@ struct phprng_ctx {
     }
     if (nreq > s.cap) {
       uint64_t cap = std::max<uint64_t>(nreq, 2 * s.cap);
-      if (s.d_req) hipFree(s.d_req);
-      if (s.h_req) hipHostFree(s.h_req);
+      if (s.d_req) (void)hipFree(s.d_req);
+      if (s.h_req) (void)hipHostFree(s.h_req);
       s.d_req = nullptr;
       s.h_req = nullptr;
       s.cap = 0;
@@ -265,7 +265,7 @@ phprng_status phprng_ctx::build_table32() {
   hipError_t e;
   if ((e = hipMalloc(&d_sum, ne * sizeof(uint64_t))) != hipSuccess) return hip_fail(e, "table32 alloc");
   if ((e = hipMalloc(&d_start, ne * sizeof(uint32_t))) != hipSuccess) {
-    hipFree(d_sum);
+    (void)hipFree(d_sum);
     return hip_fail(e, "table32 alloc");
   }
   if ((e = launch_table_segments32(ne, d_sum, d_start, nullptr)) != hipSuccess) return hip_fail(e, "table32 launch");
@@ -275,7 +275,7 @@ phprng_status phprng_ctx::build_table32() {
     return hip_fail(e, "table32 copy");
   if ((e = hipMemcpy(s32.data(), d_start, ne * sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess)
     return hip_fail(e, "table32 copy");
-  hipFree(d_sum);
+  (void)hipFree(d_sum);
   u32.resize(ne);
   uint64_t acc = 0;
   for (uint64_t i = 0; i < ne; ++i) {
@@ -287,7 +287,7 @@ phprng_status phprng_ctx::build_table32() {
   uint64_t S;
   prefix(32, pm1, &U, &S);
   if (U != ((u128)kP32 * pm1) / 2 || S != 1) {
-    hipFree(d_start);
+    (void)hipFree(d_start);
     return fail(PHPRNG_E_DEVICE, "32-bit skip-prefix table failed its full-period check");
   }
   d_s32 = d_start;
@@ -444,22 +444,22 @@ extern "C" phprng_status phprng_create(phprng_ctx **out, int device, uint64_t ma
 
 extern "C" phprng_status phprng_destroy(phprng_ctx *c) {
   if (!c) return PHPRNG_E_INVALID;
-  hipSetDevice(c->device);
-  hipDeviceSynchronize();
-  hipFree(c->d_inst);
-  hipFree(c->d_lanemul);
-  hipFree(c->d_u32);
-  hipFree(c->d_s32);
-  hipFree(c->d_u64lo);
-  hipFree(c->d_u64hi);
-  hipFree(c->d_s64);
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(c->d_inst);
+  (void)hipFree(c->d_lanemul);
+  (void)hipFree(c->d_u32);
+  (void)hipFree(c->d_s32);
+  (void)hipFree(c->d_u64lo);
+  (void)hipFree(c->d_u64hi);
+  (void)hipFree(c->d_s64);
   for (auto &s : c->slots) {
-    hipFree(s.d_req);
-    if (s.h_req) hipHostFree(s.h_req);
-    hipFree(s.d_hdr);
-    if (s.ev0) hipEventDestroy(s.ev0);
-    if (s.ev1) hipEventDestroy(s.ev1);
-    if (s.done) hipEventDestroy(s.done);
+    (void)hipFree(s.d_req);
+    if (s.h_req) (void)hipHostFree(s.h_req);
+    (void)hipFree(s.d_hdr);
+    if (s.ev0) (void)hipEventDestroy(s.ev0);
+    if (s.ev1) (void)hipEventDestroy(s.ev1);
+    if (s.done) (void)hipEventDestroy(s.done);
   }
   delete c;
   return PHPRNG_OK;
@@ -476,7 +476,7 @@ extern "C" phprng_status phprng_add_instances(phprng_ctx *c, uint64_t count, int
   if (count == 0) return PHPRNG_OK;
   if (!n || !e || !ids) return c->fail(PHPRNG_E_INVALID, "null array");
   if (c->inst.size() + count > c->max_instances) return c->fail(PHPRNG_E_RANGE, "instance table full");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   for (uint64_t i = 0; i < count; ++i) {
     phprng_status st = check_instance_impl(width, n[i], e[i]);
     if (st != PHPRNG_OK) return c->fail(st, "instance %llu rejected", (unsigned long long)i);
@@ -539,7 +539,7 @@ phprng_status draw_on_device(phprng_ctx *c, int width, uint64_t seed, uint64_t c
     const uint64_t j0 = flags.size();
     const uint64_t nb = std::max<uint64_t>(want, 1ull << 20);
     if (nb > d_cap) {
-      if (d_flags) hipFree(d_flags);
+      if (d_flags) (void)hipFree(d_flags);
       d_flags = nullptr;
       hipError_t e = hipMalloc(&d_flags, nb);
       if (e != hipSuccess) return c->hip_fail(e, "seed flags");
@@ -590,7 +590,7 @@ phprng_status draw_on_device(phprng_ctx *c, int width, uint64_t seed, uint64_t c
       k_out[i] = k_lo;
     }
   }
-  if (d_flags) hipFree(d_flags);
+  if (d_flags) (void)hipFree(d_flags);
   return st;
 }
 
@@ -614,7 +614,7 @@ extern "C" phprng_status phprng_seed_instances(phprng_ctx *c, uint64_t count, in
   if (!any) return c->fail(PHPRNG_E_EXPONENT, "no admissible exponent in the set");
   if (c->inst.size() + count > c->max_instances) return c->fail(PHPRNG_E_RANGE, "instance table full");
   if (width == 64 && k_hi > kMaxPos64) return c->fail(PHPRNG_E_RANGE, "width-64 start beyond the supported range");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   std::vector<uint64_t> n(count), e(count), k(count);
   phprng_status st = draw_on_device(c, width, seed, count, e_set, e_len, k_lo, k_hi, n.data(), e.data(), k.data());
   if (st != PHPRNG_OK) return st;
@@ -630,7 +630,7 @@ extern "C" phprng_status phprng_seed_instances(phprng_ctx *c, uint64_t count, in
   if (he == hipSuccess) he = hipMemcpy(d_ne + count, e.data(), count * 8, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = launch_build_records(d_ne, d_ne + count, count, width, c->d_inst + base, nullptr);
   if (he == hipSuccess) he = hipDeviceSynchronize();
-  hipFree(d_ne);
+  (void)hipFree(d_ne);
   if (he != hipSuccess) return c->hip_fail(he, "seed records");
   for (uint64_t i = 0; i < count; ++i) {
     c->inst.push_back(HostInst{n[i], e[i], width, 0, k[i], 0});
@@ -646,7 +646,7 @@ extern "C" phprng_status phprng_add_instances_skip(phprng_ctx *c, uint64_t count
   if (count == 0) return PHPRNG_OK;
   if (!n || !e || !b || !ids) return c->fail(PHPRNG_E_INVALID, "null array");
   if (c->inst.size() + count > c->max_instances) return c->fail(PHPRNG_E_RANGE, "instance table full");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   std::vector<HostInst> add(count);
   std::vector<InstRec> recs(count);
   for (uint64_t i = 0; i < count; ++i) {
@@ -762,7 +762,7 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
   if (!c) return PHPRNG_E_INVALID;
   if (mode != PHPRNG_MODE_PERSISTENT && mode != PHPRNG_MODE_PLAIN) return c->fail(PHPRNG_E_INVALID, "bad mode");
   if (nreq == 0) return PHPRNG_OK;
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   bool has64 = false;
   std::vector<std::pair<uint32_t, uint64_t>> moves;
   phprng_ctx::Slot *slot = nullptr;
@@ -904,7 +904,7 @@ extern "C" phprng_status phprng_set_state(phprng_ctx *c, uint32_t id, const phpr
     HostInst tmp = h;
     tmp.mbase = M.sub(st->m, M.mulmod(st->k % h.n, h.b));
     InstRec rec = c->make_record(tmp);
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     hipError_t e = hipMemcpy(c->d_inst + id, &rec, sizeof rec, hipMemcpyHostToDevice);
     if (e != hipSuccess) return c->hip_fail(e, "instance upload");
     h.mbase = tmp.mbase;
@@ -932,7 +932,7 @@ extern "C" phprng_status phprng_set_state(phprng_ctx *c, uint32_t id, const phpr
   const uint64_t mbase = M.sub(st->m, mu);
   tmp.mbase = mbase;
   InstRec rec = c->make_record(tmp);
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   hipError_t e = hipMemcpy(c->d_inst + id, &rec, sizeof rec, hipMemcpyHostToDevice);
   if (e != hipSuccess) return c->hip_fail(e, "instance upload");
   h.mbase = mbase;
@@ -966,7 +966,7 @@ extern "C" phprng_status phprng_get_tuning(phprng_ctx *c, phprng_tuning *t) {
 extern "C" phprng_status phprng_autotune(phprng_ctx *c, uint64_t draws, phprng_tuning *best) {
   if (!c || draws == 0) return PHPRNG_E_INVALID;
   if (c->inst.empty()) return c->fail(PHPRNG_E_INVALID, "no instances");
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   const uint64_t ninst = std::min<uint64_t>(c->inst.size(), 4096);
   const uint64_t per = std::max<uint64_t>(draws / ninst, 1);
   std::vector<phprng_request> reqs(ninst);
@@ -1117,10 +1117,10 @@ extern "C" phprng_status phprng_graph_destroy(phprng_graph *g) {
   if (!g) return PHPRNG_E_INVALID;
   if (g->ctx) (void)hipSetDevice(g->ctx->device);
   (void)hipDeviceSynchronize();
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
-  hipFree(g->d_req);
-  hipFree(g->d_hdr);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  (void)hipFree(g->d_req);
+  (void)hipFree(g->d_hdr);
   delete g;
   return PHPRNG_OK;
 }
