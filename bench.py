@@ -321,6 +321,82 @@ def workload_f(args, torch, ph):
         log("battery %s: %.1f Guniforms/s tested (battery kernels %.2f ms/step), min P %.3g"
             % (order, res[order]["value"], bat_ms, res[order]["min_p"]))
         bat.close()
+    # the paper's largest interleaving shape tried here: N_p = 2^20 streams,
+    # 1024 draws each, tested in the interstream order
+    ctx.close()
+    np_streams, np_len = 1 << 20, 1024
+    big = ph.Context(0, max_instances=np_streams)
+    t0 = time.perf_counter()
+    bids = big.seed_instances(32, 0x14112484 + 10, np_streams, (9, 17), 0, 0)
+    seed_s = time.perf_counter() - t0
+    breqs = ph.make_requests(bids, [np_len] * np_streams, np.arange(np_streams, dtype=np.uint64) * np_len)
+    bat = ph.Battery(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    big.generate(breqs, None, None, r, capacity=total)
+    ph.interleave(r, inter, np_streams, np_len)
+    bat.accumulate(inter)
+    rep = bat.report()
+    wall = time.perf_counter() - t0
+    res["interstream_np_2p20"] = {"streams": np_streams, "draws_per_stream": np_len, "seconds": wall,
+                                  "seeding_seconds": seed_s,
+                                  "tests": {k: {"chi2": v[0], "p": v[2]} for k, v in rep.items()},
+                                  "min_p": min(v[2] for v in rep.values())}
+    log("battery interstream N_p = 2^20: %.2f s, min P %.3g" % (wall, res["interstream_np_2p20"]["min_p"]))
+    bat.close()
+    big.close()
+    # constant skip b = p(p-1)/2 mod n over its whole period n (Sec. II): every
+    # ciphertext occurs once, so the one-dimensional test sees a distribution
+    # that is uniform to within one count per bin (far below the chi^2 median)
+    n_ex, e_ex, p31 = 4294967087, 9, (1 << 31) - 1
+    b_ex = (p31 * (p31 - 1) // 2) % n_ex
+    cs = ph.Context(0, max_instances=1)
+    cid = cs.add_instances_skip(32, [n_ex], [e_ex], [b_ex])
+    nblk = n_ex // (1 << 20)
+    bat = ph.Battery(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < nblk:
+        nb = min(1024, nblk - done)
+        cs.generate(ph.make_requests(cid, [nb << 20], [0]), None, None, r, capacity=total)
+        bat.accumulate(r[: nb << 20])
+        done += nb
+    rep = bat.report()
+    wall = time.perf_counter() - t0
+    res["constant_skip_full_period"] = {
+        "n": n_ex, "e": e_ex, "b": b_ex, "uniforms": nblk << 20, "seconds": wall,
+        "tests": {k: {"chi2": v[0], "dof": v[1], "p": v[2]} for k, v in rep.items()}}
+    log("battery constant skip over its period: %.2f s, P = %s" % (wall, {k: "%.3g" % v[2] for k, v in rep.items()}))
+    bat.close()
+    cs.close()
+    ctx = None
+    if args.battery_uniforms > 0:
+        # one long stream of the paper's example instance (Sec. II tested single
+        # streams of 10^11 to 10^13 uniforms), in steps of 2^30
+        lc = ph.Context(0, max_instances=1)
+        lid = lc.add_instances(32, [4294967087], [9])
+        nsteps = max(1, int(args.battery_uniforms) >> 30)
+        lreq = ph.make_requests(lid, [total], [0])
+        bat = ph.Battery(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(nsteps):
+            lc.generate(lreq, None, None, r, capacity=total)
+            bat.accumulate(r)
+            if (i + 1) % 128 == 0:
+                torch.cuda.synchronize()
+                log("battery long stream: %d of %d steps" % (i + 1, nsteps))
+        rep = bat.report()
+        wall = time.perf_counter() - t0
+        res["long_stream"] = {"n": 4294967087, "e": 9, "uniforms": nsteps * total, "seconds": wall,
+                              "guniforms_s": nsteps * total / wall / 1e9,
+                              "tests": {k: {"chi2": v[0], "dof": v[1], "p": v[2]} for k, v in rep.items()},
+                              "min_p": min(v[2] for v in rep.values())}
+        log("battery long stream: %.3g uniforms in %.1f s, P = %s"
+            % (nsteps * total, wall, {k: "%.3g" % v[2] for k, v in rep.items()}))
+        bat.close()
+        lc.close()
     intra = res["intrastream"]
     dom = max(intra["kernels"], key=lambda k: intra["kernels"][k]["ms_per_step"])
     dk = intra["kernels"][dom]
@@ -331,7 +407,6 @@ def workload_f(args, torch, ph):
     if not args.no_cpu_baseline:
         cpu = battery_cpu_baseline(r[: 8 << 20].cpu().numpy())
         log("battery cpu baseline: %s" % cpu)
-    ctx.close()
     line = common_line(intra["value"], "Guniforms/s", steps, 1, intra["ms_per_step"],
                        {"workload": "statistical battery (nine chi-square tests, blocks of 2^20) on 1024 seeded "
                                     "32-bit streams x 2^20 draws per step, generation included"},
@@ -414,6 +489,8 @@ def main():
     ap.add_argument("--workload", default="B", choices=["A", "B", "C", "D", "E", "F", "G"],
                     help="B (default): the headline batch; A, C, D, E: the other workload shapes; "
                          "F: the statistical battery on the generator's output; G: the full-period pattern")
+    ap.add_argument("--battery-uniforms", type=float, default=0,
+                    help="workload F: also test one stream of this many uniforms (multiple of 2^30)")
     ap.add_argument("--serve-instances", type=int, default=1000000)
     ap.add_argument("--serve-arena", type=int, default=1 << 31, help="serving arena, FP64 uniforms")
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[1e3, 1e4, 1e5, 1e6])
