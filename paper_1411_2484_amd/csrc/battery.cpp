@@ -245,9 +245,13 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
     }
     npart += np;
   }
+  if (npart > kMaxParts) {
+    phprng_battery_destroy(b);
+    return PHPRNG_E_INVALID;
+  }
   // bucket room per partition and chunk: the frequency test's share (2^20 keys
   // per partition for 32 blocks) with a margin; any surplus goes to atomics
-  const uint32_t cap = (uint32_t)(kChunkBlocks * kBlock / 32 * 5 / 4 + 4096);
+  const uint32_t cap = (uint32_t)(kChunkBlocks * kBlock / 32 * 5 / 4 + 4096) & ~7u;
   const uint32_t nslice = 2;
   ok = hipMalloc(&b->d_pdata, (uint64_t)npart * cap * sizeof(uint16_t)) == hipSuccess &&
        hipMalloc(&b->d_pfill, npart * sizeof(uint32_t)) == hipSuccess &&

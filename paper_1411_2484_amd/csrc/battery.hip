@@ -33,7 +33,7 @@ __device__ __forceinline__ uint32_t poker_cat(const uint32_t d[5]) {
 // (D = 1: the j-th uniform), its key the partition-space offset of the test
 // plus its cell (first element most significant).
 template <int D, uint32_t B, int K>
-__device__ __forceinline__ void tuple_keys(const double *t, uint32_t len, uint32_t key0, uint32_t (&key)[K]) {
+__device__ __forceinline__ void tuple_keys(const double *t, uint32_t len, uint32_t key0, uint32_t *key) {
   const uint32_t ntup = len / D;
 #pragma unroll
   for (int it = 0; it < K; ++it) {
@@ -47,22 +47,22 @@ __device__ __forceinline__ void tuple_keys(const double *t, uint32_t len, uint32
   }
 }
 
-template <int D, uint32_t B, int K>
-__device__ __forceinline__ void tuple_test(const double *t, uint32_t len, const ph::PartSet &P, uint32_t p0,
-                                           uint32_t np, uint32_t *cnt, uint32_t *base) {
-  uint32_t key[K];
-  tuple_keys<D, B, K>(t, len, p0 << ph::kPartBits, key);
-  ph::scatter_regs<256, K>(key, P, p0, np, cnt, base);
-}
+// Registers per thread for the keys of one tile: 15 + 8 + 5 + 4 + 3.
+constexpr int kK1 = kHistTile / 256, kK2 = (kHistTile / 2 + 255) / 256, kK3 = (kHistTile / 3 + 255) / 256;
+constexpr int kK4 = (kHistTile / 4 + 255) / 256, kK5 = (kHistTile / 5 + 255) / 256;
+constexpr int kKeys = kK1 + kK2 + kK3 + kK4 + kK5;
 
 // One tile of one block: frequency and serial D = 2..5 keys into the
 // partitioned histograms, the poker histogram, and the bits R > 1/2 packed
 // one 64-bit word per 64 uniforms (for the runs test).
 __global__ __launch_bounds__(256) void hist_kernel(const double *__restrict__ r, ph::PartSet P, BatteryParts bp,
                                                    unsigned long long *poker_hist, uint64_t *__restrict__ bits) {
-  __shared__ double t[kHistTile];
+  // the tile of uniforms, later reused as the key staging area of the scatter
+  __shared__ __align__(16) uint32_t buf[kKeys * 256];
+  static_assert(kKeys * 256 * 4 >= kHistTile * 8, "staging area must hold the tile");
   __shared__ uint32_t poker[kPokerCats];
-  __shared__ uint32_t cnt[kMaxTestParts], base[kMaxTestParts];
+  __shared__ uint32_t cnt[kMaxParts], poff[kMaxParts], base[kMaxParts];
+  double *t = reinterpret_cast<double *>(buf);
   const uint32_t tile = blockIdx.x % kHistTilesPerBlock;
   const uint64_t blk = blockIdx.x / kHistTilesPerBlock;
   const uint32_t off = tile * kHistTile;
@@ -77,11 +77,6 @@ __global__ __launch_bounds__(256) void hist_kernel(const double *__restrict__ r,
     if ((threadIdx.x & 63) == 0) bits[(base_i + i) >> 6] = word;
   }
   __syncthreads();
-  tuple_test<1, kFreqBins, kHistTile / 256>(t, len, P, bp.p0[0], bp.np[0], cnt, base);
-  tuple_test<2, kAxis2, (kHistTile / 2 + 255) / 256>(t, len, P, bp.p0[1], bp.np[1], cnt, base);
-  tuple_test<3, kAxis3, (kHistTile / 3 + 255) / 256>(t, len, P, bp.p0[2], bp.np[2], cnt, base);
-  tuple_test<4, kAxis4, (kHistTile / 4 + 255) / 256>(t, len, P, bp.p0[3], bp.np[3], cnt, base);
-  tuple_test<5, kAxis5, (kHistTile / 5 + 255) / 256>(t, len, P, bp.p0[4], bp.np[4], cnt, base);
   const uint32_t nhand = len / 5;
   for (uint32_t j = threadIdx.x; j < nhand; j += 256) {
     uint32_t d[5];
@@ -89,7 +84,16 @@ __global__ __launch_bounds__(256) void hist_kernel(const double *__restrict__ r,
     for (int i = 0; i < 5; ++i) d[i] = bin_of(t[j * 5 + i], 10);
     atomicAdd(&poker[poker_cat(d)], 1u);
   }
-  __syncthreads();
+  // all five tests' keys of the tile in registers, then one scatter over the
+  // partition space (its first barrier orders the last reads of the tile
+  // before the staging area is overwritten)
+  uint32_t key[kKeys];
+  tuple_keys<1, kFreqBins, kK1>(t, len, bp.p0[0] << ph::kPartBits, key);
+  tuple_keys<2, kAxis2, kK2>(t, len, bp.p0[1] << ph::kPartBits, key + kK1);
+  tuple_keys<3, kAxis3, kK3>(t, len, bp.p0[2] << ph::kPartBits, key + kK1 + kK2);
+  tuple_keys<4, kAxis4, kK4>(t, len, bp.p0[3] << ph::kPartBits, key + kK1 + kK2 + kK3);
+  tuple_keys<5, kAxis5, kK5>(t, len, bp.p0[4] << ph::kPartBits, key + kK1 + kK2 + kK3 + kK4);
+  ph::scatter_staged<256, kKeys>(key, P, 0, P.npart, cnt, poff, base, buf);
   if (threadIdx.x < kPokerCats && poker[threadIdx.x])
     atomicAdd(&poker_hist[threadIdx.x], (unsigned long long)poker[threadIdx.x]);
 }

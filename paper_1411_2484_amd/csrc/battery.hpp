@@ -42,7 +42,7 @@ constexpr uint32_t kFftPass2Groups = kFftN1 / 2 + 1;      // row pairs per block
 // The frequency and serial tests go through partitioned histograms: test t
 // owns partitions [p0[t], p0[t] + np[t]) of one partition space.
 constexpr int kPartTests = 5;
-constexpr uint32_t kMaxTestParts = 32;
+constexpr uint32_t kMaxParts = 160;  // 32 + 32 + 31 + 32 + 32 partitions of 2^15 cells
 struct BatteryParts {
   uint32_t p0[kPartTests], np[kPartTests];
 };

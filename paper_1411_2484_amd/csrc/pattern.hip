@@ -58,7 +58,8 @@ __device__ __forceinline__ uint32_t cell_bin(uint32_t c, const PatArgs &A) {
 
 template <int EK, int D>
 __global__ __launch_bounds__(256) void pattern_kernel(PatArgs A, ph::PartSet P) {
-  __shared__ uint32_t cnt[kMaxParts], base[kMaxParts];
+  __shared__ uint32_t cnt[kMaxParts], off[kMaxParts], base[kMaxParts];
+  __shared__ uint32_t stage[kHalf];
   const uint64_t i = blockIdx.x / A.nchunks;
   const uint64_t ch = blockIdx.x - i * A.nchunks;
   const uint32_t m = dev::encrypt32<0>(A.x0 + (uint32_t)i, A.n, A.ninv, A.kd, A.d, A.dbits);
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(256) void pattern_kernel(PatArgs A, ph::PartSet P) 
       }
       key[it] = s < A.s_hi ? cell : ph::kNoKey;
     }
-    ph::scatter_regs<256, kHalf / 256>(key, P, 0, P.npart, cnt, base);
+    ph::scatter_staged<256, kHalf / 256>(key, P, 0, P.npart, cnt, off, base, stage);
   }
 }
 
@@ -244,7 +245,7 @@ phprng_status phprng_pattern_histogram(const phprng_pattern *P, uint64_t *hist, 
   // bucket room: the expected share of a full partition plus a margin (any
   // surplus is added with atomics)
   const uint64_t share = (round_keys * std::min<uint64_t>(ph::kPartCells, ncell) + ncell - 1) / ncell;
-  const uint32_t cap = (uint32_t)std::min<uint64_t>(share + share / 4 + 4096, 0xffffffffull);
+  const uint32_t cap = (uint32_t)std::min<uint64_t>(share + share / 4 + 4096, 0xfffffff0ull) & ~7u;
   const uint64_t bytes_data = ((uint64_t)npart * cap * 2 + 255) / 256 * 256;
   const uint64_t bytes_slices = (uint64_t)npart * nslice * ph::kPartCells * 4;
   const uint64_t bytes = bytes_data + bytes_slices + npart * 16;

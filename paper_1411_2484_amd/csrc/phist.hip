@@ -14,9 +14,22 @@ __global__ __launch_bounds__(1024) void count_kernel(PartSet P) {
   for (uint32_t i = threadIdx.x; i < kPartCells; i += 1024) c[i] = 0;
   __syncthreads();
   const uint32_t fill = P.fill[p] < P.cap ? P.fill[p] : P.cap;
-  const uint32_t lo = (uint32_t)((uint64_t)fill * s / P.nslice), hi = (uint32_t)((uint64_t)fill * (s + 1) / P.nslice);
-  const uint16_t *d = P.data + (uint64_t)p * P.cap;
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += 1024) atomicAdd(&c[d[i]], 1u);
+  // slice bounds on 8-entry (16-byte) boundaries, the last slice takes the tail
+  const uint32_t lo = (uint32_t)((uint64_t)fill * s / P.nslice) & ~7u;
+  const uint32_t hi = s + 1 == P.nslice ? fill : (uint32_t)((uint64_t)fill * (s + 1) / P.nslice) & ~7u;
+  const uint16_t *d = P.data + (uint64_t)p * P.cap;  // cap is a multiple of 8
+  // 16-byte loads keep enough bytes in flight to cover the memory latency
+  const uint4 *dv = reinterpret_cast<const uint4 *>(d);
+  for (uint32_t v = lo / 8 + threadIdx.x; v < hi / 8; v += 1024) {
+    const uint4 w = dv[v];
+    const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      atomicAdd(&c[q[k] & 0xffffu], 1u);
+      atomicAdd(&c[q[k] >> 16], 1u);
+    }
+  }
+  for (uint32_t i = (hi & ~7u) + threadIdx.x; i < hi; i += 1024) atomicAdd(&c[d[i]], 1u);
   __syncthreads();
   uint32_t *out = P.slices + ((uint64_t)p * P.nslice + s) * kPartCells;
   const uint32_t nc = P.ncell[p];

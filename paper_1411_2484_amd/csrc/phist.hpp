@@ -25,7 +25,7 @@ constexpr uint32_t kPartCells = 1u << kPartBits;
 constexpr uint32_t kNoKey = 0xffffffffu;
 
 struct PartSet {
-  uint16_t *data;                     // [npart][cap] cell offsets
+  uint16_t *data;                     // [npart][cap] cell offsets (16-byte aligned, cap a multiple of 8)
   uint32_t *fill;                     // [npart] entries written this round
   unsigned long long *const *hist;    // [npart] first cell of each partition in its histogram
   const uint32_t *ncell;              // [npart] cells of each partition (<= 2^15)
@@ -61,6 +61,70 @@ __device__ __forceinline__ void scatter_regs(const uint32_t (&key)[K], const Par
       P.data[(uint64_t)p * P.cap + j] = (uint16_t)off;
     else
       atomicAdd(&P.hist[p][off], 1ull);
+  }
+  __syncthreads();
+}
+
+// Stage 1 with the keys sorted by partition in LDS before they leave, so
+// that the bucket writes of a wave fall in one or two contiguous runs instead
+// of one narrow store per partition.  cnt, off and base are LDS arrays of np
+// words, stage an LDS array of NT * K words; np <= 8 * 64.  Ends with a barrier.
+template <int NT, int K>
+__device__ __forceinline__ void scatter_staged(const uint32_t (&key)[K], const PartSet &P, uint32_t p0, uint32_t np,
+                                               uint32_t *cnt, uint32_t *off, uint32_t *base, uint32_t *stage) {
+  for (uint32_t i = threadIdx.x; i < np; i += NT) cnt[i] = 0;
+  __syncthreads();
+  uint32_t rank[K];
+#pragma unroll
+  for (int it = 0; it < K; ++it)
+    rank[it] = key[it] != kNoKey ? atomicAdd(&cnt[(key[it] >> kPartBits) - p0], 1u) : 0u;
+  __syncthreads();
+  // bucket reservations by all threads at once (one round trip of returning
+  // global atomics), and the exclusive scan of the counts by the first wave
+  // (up to 8 per lane)
+  __shared__ uint32_t total;
+  for (uint32_t i = threadIdx.x; i < np; i += NT) {
+    const uint32_t c = cnt[i];
+    base[i] = c ? atomicAdd(&P.fill[p0 + i], c) : 0u;
+  }
+  if (threadIdx.x < 64) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t per = (np + 63) / 64;
+    uint32_t local = 0;
+    for (uint32_t k = 0; k < per; ++k) {
+      const uint32_t i = lane * per + k;
+      if (i < np) local += cnt[i];
+    }
+    uint32_t incl = local;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d);
+      if ((int)lane >= d) incl += v;
+    }
+    uint32_t run = incl - local;
+    for (uint32_t k = 0; k < per; ++k) {
+      const uint32_t i = lane * per + k;
+      if (i < np) {
+        off[i] = run;
+        run += cnt[i];
+      }
+    }
+    if (lane == 63) total = incl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < K; ++it)
+    if (key[it] != kNoKey) stage[off[(key[it] >> kPartBits) - p0] + rank[it]] = key[it];
+  __syncthreads();
+  const uint32_t n = total;
+  for (uint32_t i = threadIdx.x; i < n; i += NT) {
+    const uint32_t k = stage[i];
+    const uint32_t q = (k >> kPartBits) - p0;
+    const uint32_t o = k & (kPartCells - 1);
+    const uint32_t j = base[q] + (i - off[q]);
+    if (j < P.cap)
+      P.data[(uint64_t)(p0 + q) * P.cap + j] = (uint16_t)o;
+    else
+      atomicAdd(&P.hist[p0 + q][o], 1ull);
   }
   __syncthreads();
 }
