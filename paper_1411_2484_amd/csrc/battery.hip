@@ -311,21 +311,28 @@ __global__ __launch_bounds__(256) void fft_pass2_kernel(const double2 *__restric
   lds_fft<L, 2, L, 256>(re, im, tw.w1024);
   const double fs = 1.0 / 1024.0;  // 1 / sqrt(M), exact
   double *cb = coef ? coef + blk * (uint64_t)kBlock : nullptr;
-  // k2 range handled by this group: all 1024 for a row pair; 0..512 for row 0; 0..511 for row 256
+  // Work items: all 1024 k2 of a row pair, k2 = 0..512 for row 0, k2 = 0..511
+  // for row 256.  For the rows other than 0 the items walk LDS positions in
+  // order (k2 = out_freq(p)); the partner 1023 - k2 then sits at position
+  // 1023 - p (complementing every base-4 digit commutes with reversing them),
+  // so neither read strides across the banks.  Row 256 takes the positions
+  // whose lowest digit is 0 or 1, i.e. k2 < 512.
   const uint32_t nk2 = ra == 0 ? 513u : (ra == kFftN1 / 2 ? 512u : 1024u);
-  for (uint32_t k2 = threadIdx.x; k2 < nk2; k2 += 256) {
+  for (uint32_t j = threadIdx.x; j < nk2; j += 256) {
     uint32_t k, kp, pa, pb;
     if (ra == 0) {
-      const uint32_t k2p = (1024 - k2) & 1023;
+      const uint32_t k2 = j, k2p = (1024 - k2) & 1023;
       k = kFftN1 * k2;
       kp = (kFftN - k) % kFftN;
       pa = pos_of<L>(k2);
       pb = pos_of<L>(k2p);
     } else {
+      const uint32_t p = ra == kFftN1 / 2 ? ((j >> 1) << 2) | (j & 1) : j;
+      const uint32_t k2 = out_freq<L>(p);
       k = ra + kFftN1 * k2;
       kp = kFftN - k;
-      pa = pos_of<L>(k2);
-      pb = L + pos_of<L>(1023 - k2);  // row rb sits in the second column (for row 256 it is the same row)
+      pa = p;
+      pb = L + (L - 1 - p);  // row rb sits in the second column (for row 256 it is the same row)
     }
     const double ar = re[pa], ai = im[pa], br = re[pb], bi = im[pb];
     const double er = (ar + br) * 0.5, ei = (ai - bi) * 0.5;
