@@ -198,3 +198,17 @@ def test_battery_argument_errors(ph, torch):
     with pytest.raises(ph.PhprngError):
         ph.interleave(r, r, 2, 4)
     bat.close()
+
+
+def test_battery_on_width64_generator_output(ph, torch):
+    """Uniforms of 64-bit moduli (R in (0, 1]) through the battery: histograms
+    equal the oracle's on the same values."""
+    ctx = ph.Context(0, max_instances=4)
+    ids = ctx.seed_instances(64, 0x14112484 + 11, 4, (9, 17), 0, 1 << 30)
+    r = torch.empty(4 * M, dtype=torch.float64, device="cuda:0")
+    ctx.generate(ph.make_requests(ids, [M] * 4, np.arange(4, dtype=np.uint64) * M), None, None, r)
+    bat = ph.Battery(0)
+    bat.accumulate(r)
+    _check_against_oracle(ph, torch, bat, r.cpu().numpy())
+    bat.close()
+    ctx.close()

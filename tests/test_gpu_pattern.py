@@ -58,6 +58,9 @@ CASES = [  # x0, l0, dim, bins, s_lo, s_hi
     (5, 3, 5, 8, 1, 1 + 50000),
     (0, 2, 3, 4096, 1, 1 + 40000),    # the 2^24 cells of the Tests section (D = 3)
     (0, 2, 5, 64, P31 - 30000, P31),  # the last skips of the period, 2^24 cells (D = 5)
+    (7, 5, 3, 100, 1, 1 + 60000),     # bins that are not powers of two
+    (0, 3, 5, 7, 1000, 1000 + 40000),
+    (0, 4, 2, 1000003, 1, 1 + 50000),
 ]
 
 
