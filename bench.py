@@ -237,7 +237,7 @@ def workload_e(args, torch, ph):
 
 
 BATTERY_KEYS_PER_DRAW = 1 + 1 / 2 + 1 / 3 + 1 / 4 + 1 / 5   # frequency + serial 2..5 histogram keys
-# per 32-block chunk, the counting stage writes and reads 2 slices of 159
+# per 128-block chunk, the counting stage writes and reads 2 slices of 159
 # partitions x 2^15 u32 counts and updates 159 x 2^15 u64 histogram cells
 BATTERY_COUNT_FIXED_BYTES = 2 * (159 * 2 * (1 << 15) * 4) + 2 * (159 * (1 << 15) * 8)
 BATTERY_BYTES_PER_DRAW = {  # algorithmic HBM bytes per tested uniform, per battery kernel
@@ -246,7 +246,7 @@ BATTERY_BYTES_PER_DRAW = {  # algorithmic HBM bytes per tested uniform, per batt
     "runs": 1.0 / 8,            # read the bits
     "fft_pass1": 16.0,          # read R, write 8 B of complex rows per uniform
     "fft_pass2": 8.0,           # read the rows
-    "hist_count": 2 * BATTERY_KEYS_PER_DRAW + BATTERY_COUNT_FIXED_BYTES / float(32 << 20),
+    "hist_count": 2 * BATTERY_KEYS_PER_DRAW + BATTERY_COUNT_FIXED_BYTES / float(128 << 20),
 }
 
 
@@ -402,7 +402,7 @@ def workload_f(args, torch, ph):
     dk = intra["kernels"][dom]
     roof = {"bound": "hbm", "achieved": dk["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dk["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
-            "bytes_per_draw": dk["bytes_per_draw"], "units_per_launch": 32 << 20}
+            "bytes_per_draw": dk["bytes_per_draw"], "units_per_launch": 128 << 20}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = battery_cpu_baseline(r[: 8 << 20].cpu().numpy())

@@ -355,7 +355,7 @@ typedef struct {
 typedef struct phprng_battery phprng_battery;
 
 /* Create a battery on HIP device `device`: 42 MB of histograms and about
- * 720 MB of transform and histogram scratch.  The caller owns it (phprng_battery_destroy). */
+ * 2.8 GB of transform and histogram scratch (128 blocks of 2^20 per pass).  The caller owns it (phprng_battery_destroy). */
 phprng_status phprng_battery_create(phprng_battery **battery, int device);
 phprng_status phprng_battery_destroy(phprng_battery *battery);
 const char *phprng_battery_last_error(const phprng_battery *battery);
@@ -427,7 +427,7 @@ typedef struct {
 /* Add the counts of `pat` to hist, a caller-owned device array of
  * bins^(D-1) uint64 counts (not cleared).  Runs on `stream` and waits for
  * it; uses stream-ordered scratch of about 2.5 bytes per key of a round of
- * up to 2^28 keys (at most about 0.75 GB). */
+ * up to 2^30 keys (at most about 2.8 GB). */
 phprng_status phprng_pattern_histogram(const phprng_pattern *pat, uint64_t *hist, void *stream);
 
 /* chi^2 of a histogram of `pat` (device) against the uniform model: each

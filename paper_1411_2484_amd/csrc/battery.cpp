@@ -21,7 +21,7 @@ namespace ph = phprng::ph;
 namespace {
 
 constexpr int kKernelClasses = 6;    // hist, collision, runs, fft pass 1, fft pass 2, hist count + add
-constexpr uint64_t kChunkBlocks = 32;  // blocks per inner pass (scratch: 256 MB of transform rows)
+constexpr uint64_t kChunkBlocks = 128;  // blocks per inner pass (scratch: 1 GB of transform rows)
 
 const uint32_t kCats[PHPRNG_TEST_COUNT] = {kFreqBins, kCells2, kCells3, kCells4, kCells5,
                                            kPokerCats, kCollCats, kRunsCats, kFourierCats};
@@ -250,7 +250,7 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
     return PHPRNG_E_INVALID;
   }
   // bucket room per partition and chunk: the frequency test's share (2^20 keys
-  // per partition for 32 blocks) with a margin; any surplus goes to atomics
+  // per partition for a chunk) with a margin; any surplus goes to atomics
   const uint32_t cap = (uint32_t)(kChunkBlocks * kBlock / 32 * 5 / 4 + 4096) & ~7u;
   const uint32_t nslice = 2;
   ok = hipMalloc(&b->d_pdata, (uint64_t)npart * cap * sizeof(uint16_t)) == hipSuccess &&

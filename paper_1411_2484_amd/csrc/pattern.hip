@@ -29,7 +29,7 @@ constexpr uint32_t kChunk = 256 * 64;  // skips per workgroup
 constexpr uint32_t kHalf = 256 * 32;   // skips whose keys a workgroup holds in registers at once
 constexpr uint32_t kMaxParts = 512;
 constexpr uint64_t kMaxCells = (uint64_t)kMaxParts << ph::kPartBits;  // 2^24
-constexpr uint64_t kRoundKeys = 1ull << 28;  // keys per bucket round
+constexpr uint64_t kRoundKeys = 1ull << 30;  // keys per bucket round
 constexpr unsigned kChiBlocks = 1024;
 constexpr uint64_t kMaxGroups = 1ull << 22;  // workgroups per pattern launch
 
@@ -231,7 +231,7 @@ phprng_status phprng_pattern_histogram(const phprng_pattern *P, uint64_t *hist, 
   A.nchunks = (P->s_hi - P->s_lo + pat::kChunk - 1) / pat::kChunk;
   A.binscale = (double)P->bins / (double)P->n;
   A.hist = reinterpret_cast<unsigned long long *>(hist);
-  // Rounds of at most 2^28 keys (and 2^22 workgroups): a round is a batch of
+  // Rounds of at most 2^30 keys (and 2^22 workgroups): a round is a batch of
   // first points over the whole skip range, or one first point over a slice
   // of it.  Each round scatters its keys into the partition buckets, then
   // the buckets are counted into the histogram.

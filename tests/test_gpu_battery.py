@@ -121,13 +121,15 @@ def test_battery_constant_block(ph, torch):
 
 
 def test_battery_split_calls_and_chunks_agree(ph, torch):
-    """40 blocks (more than one internal chunk) in one call, or in calls of
-    1, 7 and 32 blocks, give the same histograms."""
-    rng = np.random.default_rng(99)
-    r = torch.from_numpy(rng.random(40 * M)).to("cuda:0")
+    """130 blocks (more than one internal pass of 128 blocks) in one call, or
+    in calls of 1, 7 and 122 blocks, give the same histograms."""
+    nb = 130
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(99)
+    r = torch.rand(nb * M, dtype=torch.float64, device="cuda:0", generator=g)
     one, split = ph.Battery(0), ph.Battery(0)
     one.accumulate(r)
-    for a, b in ((0, 1), (1, 8), (8, 40)):
+    for a, b in ((0, 1), (1, 8), (8, nb)):
         split.accumulate(r[a * M: b * M])
     for i in range(len(ph.BATTERY_TESTS)):
         assert np.array_equal(one.counts(i), split.counts(i)), ph.BATTERY_TESTS[i]
@@ -135,7 +137,6 @@ def test_battery_split_calls_and_chunks_agree(ph, torch):
     for name in ph.BATTERY_TESTS:
         assert ra[name][3] == rb[name][3]
     # totals that hold at any size
-    nb = 40
     assert ra["frequency"][3] == nb * M and ra["serial3"][3] == nb * (M // 3)
     assert ra["serial5"][3] == nb * (M // 5) and ra["poker"][3] == nb * (M // 5)
     assert ra["collision"][3] == nb * 64 and ra["fourier"][3] == nb * M
