@@ -4,6 +4,9 @@
 // chi-square reduction, and the interstream interleave.
 #include "battery.hpp"
 
+#include "arith.hpp"
+#include "wavefft.hpp"
+
 namespace phprng {
 namespace bat {
 
@@ -173,109 +176,50 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place decimation-in-frequency transform with the positive exponent on
-// NCOL columns of length LEN (512 or 1024) held in LDS (column c at re/im +
-// c * STRIDE): radix-4 stages, then one radix-2 stage when LEN is not a power
-// of 4.  Position p ends up holding frequency out_freq<LEN>(p).
-template <int LEN, int NCOL, int STRIDE, int NT>
-__device__ void lds_fft(double *re, double *im, const double2 *__restrict__ w1024) {
-  for (int len = LEN; len >= 4; len >>= 2) {
-    const int q = len >> 2;
-    const int step = 1024 / len;
-    for (int b = threadIdx.x; b < NCOL * (LEN / 4); b += NT) {
-      const int col = b / (LEN / 4);
-      const int bb = b % (LEN / 4);
-      const int i = bb % q;
-      const int p0 = col * STRIDE + (bb / q) * len + i;
-      const double a0r = re[p0], a0i = im[p0];
-      const double a1r = re[p0 + q], a1i = im[p0 + q];
-      const double a2r = re[p0 + 2 * q], a2i = im[p0 + 2 * q];
-      const double a3r = re[p0 + 3 * q], a3i = im[p0 + 3 * q];
-      const double b0r = a0r + a2r, b0i = a0i + a2i;
-      const double b1r = a0r - a2r, b1i = a0i - a2i;
-      const double b2r = a1r + a3r, b2i = a1i + a3i;
-      const double b3r = -(a1i - a3i), b3i = a1r - a3r;  // i (a1 - a3)
-      re[p0] = b0r + b2r;
-      im[p0] = b0i + b2i;
-      const double2 y1 = cmul(make_double2(b1r + b3r, b1i + b3i), w1024[i * step]);
-      const double2 y2 = cmul(make_double2(b0r - b2r, b0i - b2i), w1024[2 * i * step]);
-      const double2 y3 = cmul(make_double2(b1r - b3r, b1i - b3i), w1024[3 * i * step]);
-      re[p0 + q] = y1.x;
-      im[p0 + q] = y1.y;
-      re[p0 + 2 * q] = y2.x;
-      im[p0 + 2 * q] = y2.y;
-      re[p0 + 3 * q] = y3.x;
-      im[p0 + 3 * q] = y3.y;
-    }
-    __syncthreads();
-  }
-  if ((LEN & 0x55555555) == 0) {  // LEN = 2 * 4^k: last stage is radix 2
-    for (int b = threadIdx.x; b < NCOL * (LEN / 2); b += NT) {
-      const int p0 = (b / (LEN / 2)) * STRIDE + 2 * (b % (LEN / 2));
-      const double a0r = re[p0], a0i = im[p0], a1r = re[p0 + 1], a1i = im[p0 + 1];
-      re[p0] = a0r + a1r;
-      im[p0] = a0i + a1i;
-      re[p0 + 1] = a0r - a1r;
-      im[p0 + 1] = a0i - a1i;
-    }
-    __syncthreads();
-  }
-}
-
-template <int LEN>
-__device__ __forceinline__ int out_freq(int p) {
-  int k = 0, mul = 1, len = LEN;
-  while (len >= 4) {
-    const int q = len >> 2;
-    k += (p / q) * mul;
-    p %= q;
-    mul *= 4;
-    len = q;
-  }
-  if (len == 2) k += p * mul;
-  return k;
-}
-
-template <int LEN>
-__device__ __forceinline__ int pos_of(int k) {
-  int p = 0, len = LEN;
-  while (len >= 4) {
-    const int q = len >> 2;
-    p += (k & 3) * q;
-    k >>= 2;
-    len = q;
-  }
-  if (len == 2) p += k;
-  return p;
-}
-
-constexpr int kP1Stride = kFftN1 + 2;  // LDS column stride (doubles), spreads banks
+// Pass-1 LDS layout: column c of a workgroup's 8 columns at c * kP1Stride
+// (double2); 529 = 16 * 33 + 1 holds the column and then, in place, the
+// wave transform's transpose, and spreads the columns over the banks.
+constexpr int kP1Stride = 529;
 
 // Pass 1 of the four-step transform of z_n = (x_2n - 1/2) + i (x_2n+1 - 1/2),
-// n = 1024 j1 + j2: the 512-point transforms over j1 of kFftCols columns j2,
-// times exp(2 pi i j2 k1 / 2^19), written as rows Y[k1][j2].
+// n = 1024 j1 + j2: the 512-point transforms over j1 of kFftCols columns j2
+// (two per wave, one per half-wave), times exp(2 pi i j2 k1 / 2^19), written
+// as rows Y[k1][j2].
 __global__ __launch_bounds__(256) void fft_pass1_kernel(const double *__restrict__ r, double2 *__restrict__ y,
                                                         Twiddles tw) {
-  __shared__ double re[kFftCols * kP1Stride], im[kFftCols * kP1Stride];
+  __shared__ double2 st[kFftCols * kP1Stride];
   const uint64_t blk = blockIdx.x / kFftPass1Groups;
   const uint32_t c0 = (blockIdx.x % kFftPass1Groups) * kFftCols;
   const double2 *src = reinterpret_cast<const double2 *>(r + blk * kBlock);
   for (uint32_t e = threadIdx.x; e < kFftCols * kFftN1; e += 256) {
     const uint32_t j1 = e / kFftCols, col = e % kFftCols;
     const double2 v = src[(uint64_t)j1 * kFftN2 + c0 + col];
-    re[col * kP1Stride + j1] = v.x - 0.5;
-    im[col * kP1Stride + j1] = v.y - 0.5;
+    st[col * kP1Stride + j1] = make_double2(v.x - 0.5, v.y - 0.5);
   }
   __syncthreads();
-  lds_fft<kFftN1, kFftCols, kP1Stride, 256>(re, im, tw.w1024);
+  const uint32_t lane = threadIdx.x & 63, l = lane & 31;
+  const uint32_t col = 2 * (threadIdx.x >> 6) + (lane >> 5);
+  double2 *cs = st + col * kP1Stride;
+  double2 v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = cs[l + 32 * m];
+  wf::wave_fft<32>(v, cs, tw.w1024, l);
+  // v[kb] = F[k1], k1 = k_a + 16 kb + 256 q; times the twiddle, back to the
+  // column in frequency order
+  const uint32_t ka = l >> 1, q = wf::wave_fft_q<32>(l);
+  const uint32_t j2 = c0 + col;
+  dev::wave_lds_sync();
+#pragma unroll
+  for (int kb = 0; kb < 16; ++kb) {
+    const uint32_t k1 = ka + 16 * kb + 256 * q;
+    const uint32_t t = j2 * k1;  // < 2^19
+    cs[k1] = cmul(v[kb], cmul(tw.fineN[t & 1023], tw.w1024[2 * (t >> 10)]));
+  }
+  __syncthreads();
   double2 *dst = y + blk * (uint64_t)kFftN;
   for (uint32_t e = threadIdx.x; e < kFftCols * kFftN1; e += 256) {
-    const uint32_t p = e / kFftCols, col = e % kFftCols;
-    const uint32_t k1 = out_freq<kFftN1>(p);
-    const uint32_t j2 = c0 + col;
-    const uint32_t t = j2 * k1;  // < 2^19
-    const double2 w = cmul(tw.fineN[t & 1023], tw.w1024[2 * (t >> 10)]);
-    dst[(uint64_t)k1 * kFftN2 + j2] = cmul(make_double2(re[col * kP1Stride + p], im[col * kP1Stride + p]), w);
+    const uint32_t k1 = e / kFftCols, c = e % kFftCols;
+    dst[(uint64_t)k1 * kFftN2 + c0 + c] = st[c * kP1Stride + k1];
   }
 }
 
@@ -285,60 +229,68 @@ __device__ __forceinline__ uint32_t fourier_cat(double v, double scale) {
   return (uint32_t)(int)(c + kFourierHalf + 1);
 }
 
+// Pass-2 LDS: per wave a 16 x 65 transpose area, reused for its row of 1024
+// coefficients in frequency order with one pad slot every 256.
+constexpr int kP2Area = 16 * 65;
+__device__ __forceinline__ uint32_t p2_slot(uint32_t k2) { return k2 + (k2 >> 8); }
+
 // Pass 2: the 1024-point transforms of rows k1 and 512 - k1 (rows 0 and 256
-// pair with themselves), which give F_k for k = k1 + 512 k2 and the partner
-// N - k of each; then the real-input split
+// pair with themselves), one wave per row, which give F_k for
+// k = k1 + 512 k2 and the partner N - k of each; then the real-input split
 //   E = (F_k + conj F_{N-k}) / 2,  O = (F_k - conj F_{N-k}) / (2i),
 //   X_k = E + w_M^k O,  X_{N-k} = conj(E - w_M^k O),
 // scaled by 1/sqrt(M), and the categories of their real and imaginary parts.
-__global__ __launch_bounds__(256) void fft_pass2_kernel(const double2 *__restrict__ y, unsigned long long *hist,
+__global__ __launch_bounds__(128) void fft_pass2_kernel(const double2 *__restrict__ y, unsigned long long *hist,
                                                         double *__restrict__ coef, Twiddles tw, double scale) {
   constexpr int L = kFftN2;
-  __shared__ double re[2 * L], im[2 * L];
+  __shared__ double2 buf[2 * kP2Area];
   __shared__ uint32_t h[kFourierCats];
   const uint64_t blk = blockIdx.x / kFftPass2Groups;
   const uint32_t ra = blockIdx.x % kFftPass2Groups;  // 0 .. 256
   const uint32_t rb = (ra == 0 || ra == kFftN1 / 2) ? ra : kFftN1 - ra;
-  const double2 *src = y + blk * (uint64_t)kFftN;
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (threadIdx.x < kFourierCats) h[threadIdx.x] = 0;
-  for (uint32_t e = threadIdx.x; e < 2 * L; e += 256) {
-    const uint32_t row = e < (uint32_t)L ? ra : rb;
-    const double2 v = src[(uint64_t)row * L + (e % L)];
-    re[e] = v.x;
-    im[e] = v.y;
-  }
+  const double2 *row = y + blk * (uint64_t)kFftN + (uint64_t)(w ? rb : ra) * L;
+  double2 *area = buf + w * kP2Area;
+  double2 v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = row[lane + 64 * m];
+  wf::wave_fft<64>(v, area, tw.w1024, lane);
+  const uint32_t ka = lane >> 2, q = wf::wave_fft_q<64>(lane);
+  dev::wave_lds_sync();
+#pragma unroll
+  for (int kb = 0; kb < 16; ++kb) area[p2_slot(ka + 16 * kb + 256 * q)] = v[kb];
   __syncthreads();
-  lds_fft<L, 2, L, 256>(re, im, tw.w1024);
   const double fs = 1.0 / 1024.0;  // 1 / sqrt(M), exact
   double *cb = coef ? coef + blk * (uint64_t)kBlock : nullptr;
-  // Work items: all 1024 k2 of a row pair, k2 = 0..512 for row 0, k2 = 0..511
-  // for row 256.  For the rows other than 0 the items walk LDS positions in
-  // order (k2 = out_freq(p)); the partner 1023 - k2 then sits at position
-  // 1023 - p (complementing every base-4 digit commutes with reversing them),
-  // so neither read strides across the banks.  Row 256 takes the positions
-  // whose lowest digit is 0 or 1, i.e. k2 < 512.
+  // k2 = 0..1023 for a row pair (partner 1023 - k2 in the other row),
+  // 0..512 for row 0 (partner 1024 - k2 in the same row), 0..511 for row 256
   const uint32_t nk2 = ra == 0 ? 513u : (ra == kFftN1 / 2 ? 512u : 1024u);
-  for (uint32_t j = threadIdx.x; j < nk2; j += 256) {
+  // k = ra + 512 k2 with ra < 512: k mod 1024 is ra or ra + 512 (two fine
+  // roots per workgroup) and k >> 10 = k2 >> 1
+  const double2 fine0 = tw.fineM[ra], fine1 = tw.fineM[ra + 512];
+#pragma unroll
+  for (uint32_t it = 0; it < (1024 + 127) / 128 + 1; ++it) {
+    const uint32_t k2 = threadIdx.x + 128 * it;
+    if (k2 >= nk2) break;
     uint32_t k, kp, pa, pb;
     if (ra == 0) {
-      const uint32_t k2 = j, k2p = (1024 - k2) & 1023;
       k = kFftN1 * k2;
       kp = (kFftN - k) % kFftN;
-      pa = pos_of<L>(k2);
-      pb = pos_of<L>(k2p);
+      pa = p2_slot(k2);
+      pb = p2_slot((1024 - k2) & 1023);
     } else {
-      const uint32_t p = ra == kFftN1 / 2 ? ((j >> 1) << 2) | (j & 1) : j;
-      const uint32_t k2 = out_freq<L>(p);
       k = ra + kFftN1 * k2;
       kp = kFftN - k;
-      pa = p;
-      pb = L + (L - 1 - p);  // row rb sits in the second column (for row 256 it is the same row)
+      pa = p2_slot(k2);
+      pb = kP2Area + p2_slot(1023 - k2);  // row rb in the second wave's area (row 256: the same row)
     }
-    const double ar = re[pa], ai = im[pa], br = re[pb], bi = im[pb];
+    const double2 A = buf[pa], B = buf[pb];
+    const double ar = A.x, ai = A.y, br = B.x, bi = B.y;
     const double er = (ar + br) * 0.5, ei = (ai - bi) * 0.5;
     const double orr = (ai + bi) * 0.5, oi = (br - ar) * 0.5;
-    const double2 w = cmul(tw.fineM[k & 1023], tw.w1024[k >> 10]);
-    const double tr = orr * w.x - oi * w.y, ti = orr * w.y + oi * w.x;
+    const double2 wk = cmul((k2 & 1) ? fine1 : fine0, tw.w1024[k2 >> 1]);
+    const double tr = orr * wk.x - oi * wk.y, ti = orr * wk.y + oi * wk.x;
     const double xr = (er + tr) * fs, xi = (ei + ti) * fs;
     atomicAdd(&h[fourier_cat(xr, scale)], 1u);
     atomicAdd(&h[fourier_cat(xi, scale)], 1u);
@@ -436,7 +388,7 @@ hipError_t launch_fft_pass1(const double *r, uint64_t nblocks, double2 *y, Twidd
 
 hipError_t launch_fft_pass2(const double2 *y, uint64_t nblocks, unsigned long long *fourier, double *coef,
                             Twiddles tw, double scale, hipStream_t st) {
-  fft_pass2_kernel<<<dim3((unsigned)(nblocks * kFftPass2Groups)), dim3(256), 0, st>>>(y, fourier, coef, tw, scale);
+  fft_pass2_kernel<<<dim3((unsigned)(nblocks * kFftPass2Groups)), dim3(128), 0, st>>>(y, fourier, coef, tw, scale);
   return hipGetLastError();
 }
 
