@@ -209,11 +209,14 @@ __global__ __launch_bounds__(256) void fft_pass1_kernel(const double *__restrict
   const uint32_t ka = l >> 1, q = wf::wave_fft_q<32>(l);
   const uint32_t j2 = c0 + col;
   dev::wave_lds_sync();
+  // w_N^{j2 k1} = w_N^{j2 (ka + 256 q)} (w_N^{16 j2})^kb: two roots loaded, then products
+  const uint32_t t0 = j2 * (ka + 256 * q), t1 = 16 * j2;  // < 2^19
+  double2 wt = cmul(tw.fineN[t0 & 1023], tw.w1024[2 * (t0 >> 10)]);
+  const double2 ws = cmul(tw.fineN[t1 & 1023], tw.w1024[2 * (t1 >> 10)]);
 #pragma unroll
   for (int kb = 0; kb < 16; ++kb) {
-    const uint32_t k1 = ka + 16 * kb + 256 * q;
-    const uint32_t t = j2 * k1;  // < 2^19
-    cs[k1] = cmul(v[kb], cmul(tw.fineN[t & 1023], tw.w1024[2 * (t >> 10)]));
+    cs[ka + 16 * kb + 256 * q] = cmul(v[kb], wt);
+    wt = cmul(wt, ws);
   }
   __syncthreads();
   double2 *dst = y + blk * (uint64_t)kFftN;
@@ -269,6 +272,9 @@ __global__ __launch_bounds__(128) void fft_pass2_kernel(const double2 *__restric
   // k = ra + 512 k2 with ra < 512: k mod 1024 is ra or ra + 512 (two fine
   // roots per workgroup) and k >> 10 = k2 >> 1
   const double2 fine0 = tw.fineM[ra], fine1 = tw.fineM[ra + 512];
+  // w_1024^{k2 >> 1} with k2 >> 1 = (tid >> 1) + 64 it: one loaded root times
+  // the exact 16th root w_16^it
+  const double2 coarse0 = tw.w1024[threadIdx.x >> 1];
 #pragma unroll
   for (uint32_t it = 0; it < (1024 + 127) / 128 + 1; ++it) {
     const uint32_t k2 = threadIdx.x + 128 * it;
@@ -289,7 +295,7 @@ __global__ __launch_bounds__(128) void fft_pass2_kernel(const double2 *__restric
     const double ar = A.x, ai = A.y, br = B.x, bi = B.y;
     const double er = (ar + br) * 0.5, ei = (ai - bi) * 0.5;
     const double orr = (ai + bi) * 0.5, oi = (br - ar) * 0.5;
-    const double2 wk = cmul((k2 & 1) ? fine1 : fine0, tw.w1024[k2 >> 1]);
+    const double2 wk = cmul((k2 & 1) ? fine1 : fine0, cmul(coarse0, wf::w16((int)it)));
     const double tr = orr * wk.x - oi * wk.y, ti = orr * wk.y + oi * wk.x;
     const double xr = (er + tr) * fs, xi = (ei + ti) * fs;
     atomicAdd(&h[fourier_cat(xr, scale)], 1u);

@@ -7,7 +7,10 @@
 //      transform over l_b of the points l = l_a + R l_b, times w_P^{l_a k_b1};
 //   4. R-point transform across the R lanes of each k_a group with DPP moves
 //      (radix 2 per lane bit, R = 2 or 4).
-// No workgroup barrier is involved: the LDS area belongs to the wave.
+// No workgroup barrier is involved: the LDS area belongs to the wave.  The
+// twiddles of steps 1 and 3 are powers of one root per lane (15 products
+// each; about 15 ulp of accumulated rounding, far below the transform's own
+// error), so a lane loads two roots instead of thirty.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -68,6 +71,21 @@ __device__ __forceinline__ void dft16(double2 (&v)[16]) {
   for (int k = 0; k < 16; ++k) v[k] = o[k];
 }
 
+// exp(2 pi i j / 16), j = 0 .. 8.
+__device__ __forceinline__ double2 w16(int j) {
+  switch (j) {
+    case 0: return make_double2(1.0, 0.0);
+    case 1: return make_double2(kC1, kS1);
+    case 2: return make_double2(kR2, kR2);
+    case 3: return make_double2(kS1, kC1);
+    case 4: return make_double2(0.0, 1.0);
+    case 5: return make_double2(-kS1, kC1);
+    case 6: return make_double2(-kR2, kR2);
+    case 7: return make_double2(-kC1, kS1);
+    default: return make_double2(-1.0, 0.0);
+  }
+}
+
 // Lane exchange inside groups of 4 lanes (DPP quad permutations).
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
@@ -95,8 +113,14 @@ __device__ __forceinline__ void wave_fft(double2 (&v)[16], double2 *lds, const d
   constexpr int N = 16 * P, R = P / 16, S = P + 1;
   static_assert(P == 32 || P == 64, "wave transform sizes");
   dft16(v);
+  // w_N^{l ka} as powers of one loaded root (15 products, no further loads)
+  const double2 wl = w1024[l * (1024 / N)];
+  double2 wk = wl;
 #pragma unroll
-  for (int ka = 1; ka < 16; ++ka) v[ka] = cmulw(v[ka], w1024[(l * ka) * (1024 / N)]);
+  for (int ka = 1; ka < 16; ++ka) {
+    v[ka] = cmulw(v[ka], wk);
+    wk = cmulw(wk, wl);
+  }
   // transpose: row k_a, column l
 #pragma unroll
   for (int ka = 0; ka < 16; ++ka) lds[ka * S + l] = v[ka];
@@ -107,8 +131,13 @@ __device__ __forceinline__ void wave_fft(double2 (&v)[16], double2 *lds, const d
 #pragma unroll
   for (int lb = 0; lb < 16; ++lb) v[lb] = lds[ka * S + la + R * lb];
   dft16(v);
+  const double2 wa = w1024[la * (1024 / P)];
+  double2 wb = wa;
 #pragma unroll
-  for (int kb = 1; kb < 16; ++kb) v[kb] = cmulw(v[kb], w1024[(la * kb) * (1024 / P)]);
+  for (int kb = 1; kb < 16; ++kb) {
+    v[kb] = cmulw(v[kb], wb);
+    wb = cmulw(wb, wa);
+  }
   if constexpr (R == 2) {
     // lane pair (a = 0, 1): X_0 = C_0 + C_1 on a = 0, X_1 = C_0 - C_1 on a = 1
     const bool hi = (la & 1) != 0;
