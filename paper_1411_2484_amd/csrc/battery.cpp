@@ -238,7 +238,6 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
     const uint32_t cells = kCats[PHPRNG_TEST_FREQUENCY + t];
     const uint32_t np = (cells + ph::kPartCells - 1) / ph::kPartCells;
     b->bparts.p0[t] = npart;
-    b->bparts.np[t] = np;
     for (uint32_t q = 0; q < np; ++q) {
       phist.push_back(b->d_cat[PHPRNG_TEST_FREQUENCY + t] + (uint64_t)q * ph::kPartCells);
       pncell.push_back(std::min<uint32_t>(ph::kPartCells, cells - q * ph::kPartCells));

@@ -40,11 +40,11 @@ constexpr uint32_t kFftPass1Groups = kFftN2 / kFftCols;   // workgroups per bloc
 constexpr uint32_t kFftPass2Groups = kFftN1 / 2 + 1;      // row pairs per block, pass 2
 
 // The frequency and serial tests go through partitioned histograms: test t
-// owns partitions [p0[t], p0[t] + np[t]) of one partition space.
+// owns the partitions from p0[t] on in one partition space.
 constexpr int kPartTests = 5;
 constexpr uint32_t kMaxParts = 160;  // 32 + 32 + 31 + 32 + 32 partitions of 2^15 cells
 struct BatteryParts {
-  uint32_t p0[kPartTests], np[kPartTests];
+  uint32_t p0[kPartTests];
 };
 
 // Roots of unity with the positive exponent of the paper's Fourier sum:

@@ -35,39 +35,9 @@ struct PartSet {
 
 // Stage 1 for keys held in registers: key[it] of thread t is item t + it * NT;
 // keys are (partition << 15) | offset with partition in [p0, p0 + np), or
-// kNoKey.  cnt and base are LDS arrays of np words.  Ends with a barrier.
-template <int NT, int K>
-__device__ __forceinline__ void scatter_regs(const uint32_t (&key)[K], const PartSet &P, uint32_t p0, uint32_t np,
-                                             uint32_t *cnt, uint32_t *base) {
-  for (uint32_t i = threadIdx.x; i < np; i += NT) cnt[i] = 0;
-  __syncthreads();
-  uint32_t rank[K];
-#pragma unroll
-  for (int it = 0; it < K; ++it)
-    rank[it] = key[it] != kNoKey ? atomicAdd(&cnt[(key[it] >> kPartBits) - p0], 1u) : 0u;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < np; i += NT) {
-    const uint32_t c = cnt[i];
-    base[i] = c ? atomicAdd(&P.fill[p0 + i], c) : 0u;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < K; ++it) {
-    if (key[it] == kNoKey) continue;
-    const uint32_t p = key[it] >> kPartBits;
-    const uint32_t off = key[it] & (kPartCells - 1);
-    const uint32_t j = base[p - p0] + rank[it];
-    if (j < P.cap)
-      P.data[(uint64_t)p * P.cap + j] = (uint16_t)off;
-    else
-      atomicAdd(&P.hist[p][off], 1ull);
-  }
-  __syncthreads();
-}
-
-// Stage 1 with the keys sorted by partition in LDS before they leave, so
-// that the bucket writes of a wave fall in one or two contiguous runs instead
-// of one narrow store per partition.  cnt, off and base are LDS arrays of np
+// kNoKey.  The keys are sorted by partition in LDS before they leave, so that
+// the bucket writes of a wave fall in one or two contiguous runs instead of
+// one narrow store per partition.  cnt, off and base are LDS arrays of np
 // words, stage an LDS array of NT * K words; np <= 8 * 64.  Ends with a barrier.
 template <int NT, int K>
 __device__ __forceinline__ void scatter_staged(const uint32_t (&key)[K], const PartSet &P, uint32_t p0, uint32_t np,
