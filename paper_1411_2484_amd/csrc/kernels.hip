@@ -152,52 +152,98 @@ __device__ __forceinline__ uint64_t tile_of(uint64_t x, bool w64) {
   return (q << kTileShift32) | (r / kTile);
 }
 
-// One block of 1024 threads: per request first tile, tile count and chunk
-// count, then an exclusive scan of chunk counts; resets the work counter.
-__global__ void __launch_bounds__(1024) plan_kernel(const InstRec *inst, ReqRec *req, uint64_t nreq, PlanHdr *hdr,
-                                                    uint32_t tiles_per_chunk) {
-  __shared__ uint64_t part[1024];
-  const uint32_t tid = threadIdx.x;
-  const uint64_t per = (nreq + 1023) / 1024;
-  const uint64_t lo = min((uint64_t)tid * per, nreq), hi = min(lo + per, nreq);
-  uint64_t local = 0;
-  for (uint64_t r = lo; r < hi; ++r) {
-    ReqRec q = req[r];
-    const InstRec &I = inst[q.inst];
-    bool w64 = I.width == 64 || I.sched == kSchedConstant;  // no skip period to respect
-    uint64_t g1 = 0, nt = 0;
-    if (q.count > 0) {
-      g1 = tile_of(q.k, w64);
-      nt = tile_of(q.k + q.count - 1, w64) - g1 + 1;
-    }
-    uint64_t nc = (nt + tiles_per_chunk - 1) / tiles_per_chunk;
-    req[r].g1 = g1;
-    req[r].ntiles = nt;
-    req[r].nchunks = (uint32_t)nc;
-    local += nc;
-  }
-  part[tid] = local;
+// Inclusive scan of v over a workgroup of kPlanGroup threads; *total gets the
+// sum.  ws: LDS scratch of kPlanGroup / 64 words.  Starts and ends with a barrier.
+__device__ __forceinline__ uint64_t plan_scan(uint64_t v, uint64_t *ws, uint64_t *total) {
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
-  // Hillis-Steele inclusive scan over the 1024 partial sums.
-  for (uint32_t d = 1; d < 1024; d <<= 1) {
-    uint64_t v = tid >= d ? part[tid - d] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  uint64_t incl = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t u = dev::shfl_up_u64(incl, d);
+    if ((int)lane >= d) incl += u;
   }
-  uint64_t run = part[tid] - local;
-  for (uint64_t r = lo; r < hi; ++r) {
-    req[r].chunk_base = run;
-    run += req[r].nchunks;
+  if (lane == 63) ws[w] = incl;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kPlanGroup / 64; ++j) {
+    before += j < w ? ws[j] : 0;
+    all += ws[j];
   }
-  if (tid == 1023) {
-    hdr->total_chunks = part[1023];
+  *total = all;
+  __syncthreads();
+  return before + incl;
+}
+
+// One workgroup per kPlanGroup requests.  The host-written requests are read
+// with system-scope loads (src is pinned host memory, or device memory for
+// graph replays); per request the first tile, tile count and chunk count are
+// found, scanned inside the group, and the group's total goes to gbase.  The
+// last workgroup to finish turns gbase into exclusive prefixes, stores the
+// batch total, and clears the work counter and its own completion counter.
+__global__ void __launch_bounds__(kPlanGroup) plan_kernel(const InstRec *inst, const HostReq *src, ReqRec *req,
+                                                          uint64_t nreq, uint64_t *gbase, PlanHdr *hdr,
+                                                          uint32_t tiles_per_chunk) {
+  constexpr uint32_t kWords = sizeof(HostReq) / 8;
+  __shared__ uint64_t words[kPlanGroup * kWords];
+  __shared__ uint64_t ws[kPlanGroup / 64];
+  __shared__ uint32_t last;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t r0 = (uint64_t)blockIdx.x * kPlanGroup;
+  const uint32_t nin = (uint32_t)min((uint64_t)kPlanGroup, nreq - r0);
+  // consecutive lanes read consecutive words: whole lines over the bus
+  const uint64_t *sw = reinterpret_cast<const uint64_t *>(src + r0);
+  for (uint32_t i = tid; i < nin * kWords; i += kPlanGroup)
+    words[i] = __hip_atomic_load(sw + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __syncthreads();
+  ReqRec R{};
+  if (tid < nin) {
+    R.k = words[tid * kWords];
+    R.count = words[tid * kWords + 1];
+    R.out_off = words[tid * kWords + 2];
+    R.inst = (uint32_t)words[tid * kWords + 3];
+    const InstRec &I = inst[R.inst];
+    const bool w64 = I.width == 64 || I.sched == kSchedConstant;  // no skip period to respect
+    if (R.count > 0) {
+      R.g1 = tile_of(R.k, w64);
+      R.ntiles = tile_of(R.k + R.count - 1, w64) - R.g1 + 1;
+    }
+    R.nchunks = (uint32_t)((R.ntiles + tiles_per_chunk - 1) / tiles_per_chunk);
+  }
+  uint64_t gtotal;
+  const uint64_t incl = plan_scan(R.nchunks, ws, &gtotal);
+  if (tid < nin) {
+    R.chunk_base = incl - R.nchunks;
+    req[r0 + tid] = R;
+  }
+  if (tid == 0) {
+    gbase[blockIdx.x] = gtotal;
+    __threadfence();
+    last = atomicAdd(&hdr->done, 1u) == gridDim.x - 1 ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // last workgroup: exclusive scan of the group totals, in place
+  const uint32_t ng = gridDim.x;
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < ng; base += kPlanGroup) {
+    const uint32_t j = base + tid;
+    const uint64_t v = j < ng ? __hip_atomic_load(gbase + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    uint64_t rtotal;
+    const uint64_t in = plan_scan(v, ws, &rtotal);
+    if (j < ng) gbase[j] = carry + in - v;
+    carry += rtotal;
+  }
+  if (tid == 0) {
+    hdr->total_chunks = carry;
     hdr->counter = 0;
+    hdr->done = 0;
   }
 }
 
 // Graph replays: every request continues where it ended.
-__global__ void __launch_bounds__(256) advance_kernel(ReqRec *req, uint64_t nreq) {
+__global__ void __launch_bounds__(256) advance_kernel(HostReq *req, uint64_t nreq) {
   uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < nreq) req[r].k += req[r].count;
 }
@@ -568,14 +614,19 @@ __device__ void run_chunk64_cs(const GenArgs &A, const InstRec &I, const ReqRec 
   }
 }
 
-// Wave-cooperative search: the request r with chunk_base[r] <= c < chunk_base[r+1]
-// (the last such r when empty requests share a base).
-__device__ __forceinline__ uint64_t find_request(const ReqRec *req, uint64_t nreq, uint64_t c, uint32_t lane) {
-  uint64_t lo = 0, hi = nreq;
+// First chunk of request r in the batch.
+__device__ __forceinline__ uint64_t chunk_base_of(const GenArgs &A, uint64_t r) {
+  return A.gbase[r / kPlanGroup] + A.req[r].chunk_base;
+}
+
+// Wave-cooperative search: the request r whose first chunk is <= c < the next
+// request's (the last such r when empty requests share a first chunk).
+__device__ __forceinline__ uint64_t find_request(const GenArgs &A, uint64_t c, uint32_t lane) {
+  uint64_t lo = 0, hi = A.nreq;
   while (hi - lo > 1) {
     uint64_t step = (hi - lo + 63) / 64;
     uint64_t idx = lo + (uint64_t)lane * step;
-    bool le = idx < hi && req[idx].chunk_base <= c;
+    bool le = idx < hi && chunk_base_of(A, idx) <= c;
     uint64_t mask = __ballot(le);
     uint64_t k = (uint64_t)__popcll(mask);
     lo = lo + (k - 1) * step;
@@ -605,10 +656,10 @@ __global__ void __launch_bounds__(BLOCK) gen_persistent(GenArgs A) {
   uint64_t c = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
   for (;;) {
     if (c >= total) break;
-    const uint64_t r = dev::uniform_u64(find_request(A.req, A.nreq, c, lane));
+    const uint64_t r = dev::uniform_u64(find_request(A, c, lane));
     const ReqRec R = A.req[r];
     const InstRec &I = A.inst[R.inst];
-    const uint64_t chunk = c - R.chunk_base;
+    const uint64_t chunk = c - (A.gbase[r / kPlanGroup] + R.chunk_base);
     if (I.sched == kSchedConstant) {
       if (HAS64 && I.width == 64) run_chunk64_cs<UNROLL>(A, I, R, chunk, lane);
       else run_chunk32_cs<UNROLL>(A, I, R, chunk, lane);
@@ -673,13 +724,17 @@ hipError_t launch_build_records(const uint64_t *n, const uint64_t *e, uint64_t c
   return hipGetLastError();
 }
 
-hipError_t launch_plan(const InstRec *inst, ReqRec *req, uint64_t nreq, PlanHdr *hdr, uint32_t tiles_per_chunk,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, inst, req, nreq, hdr, tiles_per_chunk);
+hipError_t launch_plan(const InstRec *inst, const HostReq *src, ReqRec *req, uint64_t nreq, uint64_t *gbase,
+                       PlanHdr *hdr, uint32_t tiles_per_chunk, hipStream_t st) {
+  if (nreq == 0) return hipErrorInvalidValue;
+  const uint64_t groups = (nreq + kPlanGroup - 1) / kPlanGroup;
+  if (groups > 0x7fffffffull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(plan_kernel, dim3((unsigned)groups), dim3(kPlanGroup), 0, st, inst, src, req, nreq, gbase, hdr,
+                     tiles_per_chunk);
   return hipGetLastError();
 }
 
-hipError_t launch_advance(ReqRec *req, uint64_t nreq, hipStream_t st) {
+hipError_t launch_advance(HostReq *req, uint64_t nreq, hipStream_t st) {
   if (nreq == 0) return hipSuccess;
   unsigned blocks = (unsigned)((nreq + 255) / 256);
   hipLaunchKernelGGL(advance_kernel, dim3(blocks), dim3(256), 0, st, req, nreq);

@@ -50,15 +50,31 @@ constexpr uint32_t kSchedSkipLcg = 0;
 constexpr uint32_t kSchedConstant = 1;
 static_assert(sizeof(InstRec) == 128, "InstRec must be one 128-byte line");
 
-// Device request record.  The host fills inst, k, count, out_off; the plan
-// kernel fills the tile/chunk bookkeeping.
+// Request as the host writes it (32 bytes).  The plan kernel reads the list
+// straight from pinned host memory, so no copy precedes it.
+struct alignas(32) HostReq {
+  uint64_t k;        // internal index of the state before the first draw
+  uint64_t count;    // number of draws
+  uint64_t out_off;  // output element offset
+  uint32_t inst;     // instance id
+  uint32_t pad;
+};
+static_assert(sizeof(HostReq) == 32, "HostReq must be 32 bytes");
+
+// Requests per plan workgroup.  chunk_base below counts from the first chunk
+// of the request's plan group; gbase[r / kPlanGroup] holds that group's first
+// chunk in the whole batch.
+constexpr uint32_t kPlanGroup = 256;
+
+// Device request record: the host's request plus the plan kernel's tile and
+// chunk bookkeeping.
 struct alignas(64) ReqRec {
   uint64_t k;           // internal index of the state before the first draw
   uint64_t count;       // number of draws
   uint64_t out_off;     // output element offset
   uint64_t g1;          // first tile (global tile index q * tiles_per_period + j)
   uint64_t ntiles;      // tiles touched
-  uint64_t chunk_base;  // exclusive prefix of chunks over the request list
+  uint64_t chunk_base;  // exclusive prefix of chunks inside the plan group
   uint32_t inst;        // instance id
   uint32_t nchunks;     // chunks of this request
   uint64_t pad;
@@ -68,7 +84,8 @@ static_assert(sizeof(ReqRec) == 64, "ReqRec must be 64 bytes");
 struct alignas(64) PlanHdr {
   uint64_t total_chunks;
   uint32_t counter;  // work-stealing counter
-  uint32_t pad[13];
+  uint32_t done;     // plan workgroups finished (back to 0 when the plan ends)
+  uint32_t pad[12];
 };
 
 // Pointers to the universal skip-prefix tables: entry i holds U(i * stride)
@@ -91,6 +108,7 @@ struct LaneMul {
 struct GenArgs {
   const InstRec *inst;
   ReqRec *req;
+  const uint64_t *gbase;  // first chunk of each plan group
   PlanHdr *hdr;
   uint64_t nreq;
   SkipTables tab;

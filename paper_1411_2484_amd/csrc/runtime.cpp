@@ -67,7 +67,9 @@ struct phprng_graph {
   phprng_ctx *ctx = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  HostReq *d_src = nullptr;  // requests; the graph's last node advances them
   ReqRec *d_req = nullptr;
+  uint64_t *d_gbase = nullptr;
   PlanHdr *d_hdr = nullptr;
   std::vector<uint32_t> inst;
   std::vector<uint64_t> count;
@@ -93,8 +95,10 @@ struct phprng_ctx {
   // different streams) never overwrite a request list still in use.  A slot
   // is reused only after the event recorded behind its last kernel.
   struct Slot {
+    HostReq *h_req = nullptr;            // pinned, mapped
+    const HostReq *h_req_dev = nullptr;  // h_req's address for kernels
     ReqRec *d_req = nullptr;
-    ReqRec *h_req = nullptr;  // pinned
+    uint64_t *d_gbase = nullptr;         // ceil(cap / kPlanGroup) words
     uint64_t cap = 0;
     PlanHdr *d_hdr = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
@@ -106,7 +110,10 @@ struct phprng_ctx {
   int last_timed = -1;
   double acc_ms = 0;        // cumulative kernel time of recycled slots
   uint64_t acc_calls = 0;
-  ReqRec *h_req = nullptr;  // staging array of the slot being prepared
+  HostReq *h_req = nullptr;  // staging array of the slot being prepared
+  // Per instance: its index in the touched list of the batch being prepared;
+  // -1 between calls, so that a batch costs O(requests), not O(instances).
+  std::vector<int64_t> where;
   phprng_tuning tuning{256, 4, 8, 4};
   std::string err;
 
@@ -234,18 +241,29 @@ struct phprng_ctx {
       if ((e = hipEventCreate(&s.ev1)) != hipSuccess) return hip_fail(e, "event");
       if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
       if ((e = hipMalloc(&s.d_hdr, sizeof(PlanHdr))) != hipSuccess) return fail(PHPRNG_E_NOMEM, "plan header");
+      // the plan kernel expects a zero completion counter and leaves it so
+      if ((e = hipMemset(s.d_hdr, 0, sizeof(PlanHdr))) != hipSuccess) return hip_fail(e, "plan header");
     }
     if (nreq > s.cap) {
       uint64_t cap = std::max<uint64_t>(nreq, 2 * s.cap);
       if (s.d_req) (void)hipFree(s.d_req);
+      if (s.d_gbase) (void)hipFree(s.d_gbase);
       if (s.h_req) (void)hipHostFree(s.h_req);
       s.d_req = nullptr;
+      s.d_gbase = nullptr;
       s.h_req = nullptr;
+      s.h_req_dev = nullptr;
       s.cap = 0;
       if ((e = hipMalloc(&s.d_req, cap * sizeof(ReqRec))) != hipSuccess)
         return fail(PHPRNG_E_NOMEM, "request buffer: %s", hipGetErrorString(e));
-      if ((e = hipHostMalloc(&s.h_req, cap * sizeof(ReqRec), hipHostMallocDefault)) != hipSuccess)
+      if ((e = hipMalloc(&s.d_gbase, (cap + kPlanGroup - 1) / kPlanGroup * sizeof(uint64_t))) != hipSuccess)
+        return fail(PHPRNG_E_NOMEM, "plan buffer: %s", hipGetErrorString(e));
+      if ((e = hipHostMalloc(&s.h_req, cap * sizeof(HostReq), hipHostMallocMapped)) != hipSuccess)
         return fail(PHPRNG_E_NOMEM, "pinned request buffer: %s", hipGetErrorString(e));
+      void *dp = nullptr;
+      if ((e = hipHostGetDevicePointer(&dp, s.h_req, 0)) != hipSuccess || !dp)
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidValue, "pinned request buffer address");
+      s.h_req_dev = static_cast<const HostReq *>(dp);
       s.cap = cap;
     }
     h_req = s.h_req;
@@ -455,6 +473,7 @@ extern "C" phprng_status phprng_destroy(phprng_ctx *c) {
   (void)hipFree(c->d_s64);
   for (auto &s : c->slots) {
     (void)hipFree(s.d_req);
+    (void)hipFree(s.d_gbase);
     if (s.h_req) (void)hipHostFree(s.h_req);
     (void)hipFree(s.d_hdr);
     if (s.ev0) (void)hipEventDestroy(s.ev0);
@@ -702,7 +721,15 @@ phprng_status prepare_requests(phprng_ctx *c, const phprng_request *reqs, uint64
   // tentative positions, in request order
   std::vector<uint32_t> touched;
   std::vector<uint64_t> cur;
-  std::vector<int64_t> where(c->inst.size(), -1);
+  if (c->where.size() < c->inst.size()) c->where.resize(c->inst.size(), -1);
+  std::vector<int64_t> &where = c->where;
+  struct Reset {  // back to -1 on every way out
+    std::vector<int64_t> &w;
+    const std::vector<uint32_t> &t;
+    ~Reset() {
+      for (uint32_t i : t) w[i] = -1;
+    }
+  } reset{where, touched};
   for (uint64_t i = 0; i < nreq; ++i) {
     const phprng_request &r = reqs[i];
     const HostInst &h = c->inst[r.instance];
@@ -724,7 +751,7 @@ phprng_status prepare_requests(phprng_ctx *c, const phprng_request *reqs, uint64
     const phprng_request &r = reqs[i];
     const HostInst &h = c->inst[r.instance];
     uint64_t &x = cur[(size_t)where[r.instance]];
-    ReqRec rec;
+    HostReq rec;
     memset(&rec, 0, sizeof rec);
     rec.k = x;
     rec.count = r.count;
@@ -740,11 +767,12 @@ phprng_status prepare_requests(phprng_ctx *c, const phprng_request *reqs, uint64
 
 }  // namespace
 
-static GenArgs make_args(phprng_ctx *c, ReqRec *d_req, PlanHdr *d_hdr, uint64_t nreq, uint32_t *out_c32,
-                         uint64_t *out_c64, double *out_r, uint32_t tpc) {
+static GenArgs make_args(phprng_ctx *c, ReqRec *d_req, const uint64_t *d_gbase, PlanHdr *d_hdr, uint64_t nreq,
+                         uint32_t *out_c32, uint64_t *out_c64, double *out_r, uint32_t tpc) {
   GenArgs A;
   A.inst = c->d_inst;
   A.req = d_req;
+  A.gbase = d_gbase;
   A.hdr = d_hdr;
   A.nreq = nreq;
   A.tab = SkipTables{c->d_u32, c->d_s32, c->d_u64lo, c->d_u64hi, c->d_s64, c->u32.size(), c->s64.size()};
@@ -779,11 +807,10 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
   const uint64_t waves = (uint64_t)c->num_cus * T.blocks_per_cu * (T.block_threads / 64);
   // Small batches: shrink the chunk so that every resident wave gets work.
   while (tpc > 1 && tiles < 4 * waves * tpc) tpc >>= 1;
-  hipError_t e = hipMemcpyAsync(slot->d_req, slot->h_req, nreq * sizeof(ReqRec), hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return c->hip_fail(e, "request upload");
-  if ((e = launch_plan(c->d_inst, slot->d_req, nreq, slot->d_hdr, tpc, s)) != hipSuccess)
-    return c->hip_fail(e, "plan");
-  GenArgs A = make_args(c, slot->d_req, slot->d_hdr, nreq, out_c32, out_c64, out_r, tpc);
+  // the plan reads the request list from the slot's pinned buffer directly
+  hipError_t e = launch_plan(c->d_inst, slot->h_req_dev, slot->d_req, nreq, slot->d_gbase, slot->d_hdr, tpc, s);
+  if (e != hipSuccess) return c->hip_fail(e, "plan");
+  GenArgs A = make_args(c, slot->d_req, slot->d_gbase, slot->d_hdr, nreq, out_c32, out_c64, out_r, tpc);
   if ((e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
   if (mode == PHPRNG_MODE_PERSISTENT) {
     // no more blocks than the batch can keep busy
@@ -795,7 +822,7 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
     if (e != hipSuccess) return c->hip_fail(e, "persistent launch");
   } else {
     for (uint64_t i = 0; i < nreq; ++i) {
-      const ReqRec &r = slot->h_req[i];
+      const HostReq &r = slot->h_req[i];
       const unsigned grid = r.count ? (unsigned)(r.count / kTile + 3) : 0u;
       e = launch_plain(A, i, grid, T.unroll, c->inst[r.inst].width == 64, s);
       if (e != hipSuccess) return c->hip_fail(e, "plain launch");
@@ -1062,9 +1089,13 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
   if (!g) return PHPRNG_E_NOMEM;
   g->ctx = c;
   hipError_t e;
+  if ((e = hipMalloc(&g->d_src, nreq * sizeof(HostReq))) != hipSuccess) return c->hip_fail(e, "graph alloc");
   if ((e = hipMalloc(&g->d_req, nreq * sizeof(ReqRec))) != hipSuccess) return c->hip_fail(e, "graph alloc");
+  if ((e = hipMalloc(&g->d_gbase, (nreq + kPlanGroup - 1) / kPlanGroup * sizeof(uint64_t))) != hipSuccess)
+    return c->hip_fail(e, "graph alloc");
   if ((e = hipMalloc(&g->d_hdr, sizeof(PlanHdr))) != hipSuccess) return c->hip_fail(e, "graph alloc");
-  if ((e = hipMemcpy(g->d_req, c->h_req, nreq * sizeof(ReqRec), hipMemcpyHostToDevice)) != hipSuccess)
+  if ((e = hipMemset(g->d_hdr, 0, sizeof(PlanHdr))) != hipSuccess) return c->hip_fail(e, "graph alloc");
+  if ((e = hipMemcpy(g->d_src, c->h_req, nreq * sizeof(HostReq), hipMemcpyHostToDevice)) != hipSuccess)
     return c->hip_fail(e, "graph upload");
   for (uint64_t i = 0; i < nreq; ++i) {
     g->inst.push_back(c->h_req[i].inst);
@@ -1073,12 +1104,14 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
   hipStream_t cap_stream;
   if ((e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking)) != hipSuccess) return c->hip_fail(e, "stream");
   const phprng_tuning &T = c->tuning;
-  GenArgs A = make_args(c, g->d_req, g->d_hdr, nreq, out_c32, out_c64, out_r, (uint32_t)T.tiles_per_chunk);
+  GenArgs A = make_args(c, g->d_req, g->d_gbase, g->d_hdr, nreq, out_c32, out_c64, out_r,
+                        (uint32_t)T.tiles_per_chunk);
   e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) e = launch_plan(c->d_inst, g->d_req, nreq, g->d_hdr, A.tiles_per_chunk, cap_stream);
+  if (e == hipSuccess)
+    e = launch_plan(c->d_inst, g->d_src, g->d_req, nreq, g->d_gbase, g->d_hdr, A.tiles_per_chunk, cap_stream);
   if (e == hipSuccess)
     e = launch_persistent(A, (unsigned)(c->num_cus * T.blocks_per_cu), T.block_threads, T.unroll, has64, cap_stream);
-  if (e == hipSuccess) e = launch_advance(g->d_req, nreq, cap_stream);
+  if (e == hipSuccess) e = launch_advance(g->d_src, nreq, cap_stream);
   hipError_t e2 = hipStreamEndCapture(cap_stream, &g->graph);
   (void)hipStreamDestroy(cap_stream);
   if (e != hipSuccess || e2 != hipSuccess) return c->hip_fail(e != hipSuccess ? e : e2, "graph capture");
@@ -1119,7 +1152,9 @@ extern "C" phprng_status phprng_graph_destroy(phprng_graph *g) {
   (void)hipDeviceSynchronize();
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  (void)hipFree(g->d_src);
   (void)hipFree(g->d_req);
+  (void)hipFree(g->d_gbase);
   (void)hipFree(g->d_hdr);
   delete g;
   return PHPRNG_OK;
