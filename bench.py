@@ -220,11 +220,18 @@ def workload_e(args, torch, ph):
         arr["t_ns"] = np.cumsum(rng.exponential(1e9 / lam, n)).astype(np.int64)
         arr["instance"] = rng.integers(0, n32 + n64, n)
         arr["count"] = np.floor(2.0 ** (8 + 12 * rng.random(n))).astype(np.uint64)
-        lat, wall = srv.replay(arr)
+        srv.counters(reset=True)
+        lat, adm, wall = srv.replay_detail(arr)
+        cnt = srv.counters(reset=True)
         draws = int(arr["count"].sum())
         pt = {"rate_req_s": lam, "requests": n, "uniforms_per_s": draws / wall / 1e9,
               "p50_ms": float(np.percentile(lat, 50)) / 1e6, "p99_ms": float(np.percentile(lat, 99)) / 1e6,
-              "offered_guniforms_s": draws / (arr["t_ns"][-1] * 1e-9) / 1e9, "wall_s": wall}
+              "admit_p50_ms": float(np.percentile(adm, 50)) / 1e6, "admit_p99_ms": float(np.percentile(adm, 99)) / 1e6,
+              "offered_guniforms_s": float(draws / (arr["t_ns"][-1] * 1e-9) / 1e9), "wall_s": wall,
+              "batches": cnt["batches"], "requests_per_batch": cnt["requests"] / max(cnt["batches"], 1),
+              "launch_us_mean": cnt["launch_ns"] / max(cnt["batches"], 1) / 1e3,
+              "launch_us_max": cnt["launch_ns_max"] / 1e3, "arena_stalls": cnt["arena_stalls"],
+              "arena_peak": cnt["arena_peak"]}
         log("serve: %s" % pt)
         points.append(pt)
     srv.close()

@@ -282,14 +282,37 @@ phprng_status phprng_server_poll(phprng_server *server, phprng_completion *out, 
                                  int64_t timeout_us);
 /* Return a completed request's arena range. */
 phprng_status phprng_server_release(phprng_server *server, uint64_t ticket);
+/* Return the ranges of n completed requests under one lock; an unknown
+ * ticket gives PHPRNG_E_INVALID after the others are released. */
+phprng_status phprng_server_release_many(phprng_server *server, const uint64_t *tickets, uint64_t n);
 phprng_status phprng_server_stats(phprng_server *server, uint64_t *pending, uint64_t *arena_used);
+/* Launch counters since creation or the last reset: batched launches, the
+ * requests and uniforms they held, and the host time spent issuing them
+ * (position reservation, planning inputs, kernel launches), summed and the
+ * longest single launch; how often a batch was cut short because the arena
+ * had no room for the next request, and the most arena elements in use at
+ * a launch.  reset != 0 clears them after the read. */
+typedef struct {
+  uint64_t batches;
+  uint64_t requests;
+  uint64_t draws;
+  int64_t launch_ns;
+  int64_t launch_ns_max;
+  uint64_t arena_stalls;
+  uint64_t arena_peak;
+} phprng_server_counters;
+phprng_status phprng_server_read_counters(phprng_server *server, phprng_server_counters *out, int reset);
 /* Drains the batches on the device, stops the scheduler, frees the arena. */
 phprng_status phprng_server_destroy(phprng_server *server);
 
 /* Open-loop load: a native thread submits arrival i at t_ns nanoseconds after
  * the start (non-decreasing), each completed result is released at once, and
  * latency_ns[i] receives completion minus scheduled arrival (-1 on error).
- * *wall_s receives the time from the start to the last completion. */
+ * admit_ns (may be NULL) receives, per arrival, the time from its scheduled
+ * arrival to its admission (t_admit_ns: its batch is formed and about to be
+ * launched), i.e. queueing and the scheduler's reaction; the launch and the
+ * device work make up the rest of the latency.  *wall_s receives the time
+ * from the start to the last completion. */
 typedef struct {
   int64_t t_ns;
   uint32_t instance;
@@ -298,7 +321,7 @@ typedef struct {
 } phprng_arrival;
 
 phprng_status phprng_server_replay(phprng_server *server, const phprng_arrival *arrivals, uint64_t n,
-                                   int64_t *latency_ns, double *wall_s);
+                                   int64_t *latency_ns, int64_t *admit_ns, double *wall_s);
 
 
 /* ---- statistical battery: the chi-square tests of the Tests section ---------*/

@@ -75,6 +75,12 @@ class phprng_completion(ctypes.Structure):
                 ("t_done_ns", ctypes.c_int64)]
 
 
+class phprng_server_counters(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("requests", ctypes.c_uint64), ("draws", ctypes.c_uint64),
+                ("launch_ns", ctypes.c_int64), ("launch_ns_max", ctypes.c_int64),
+                ("arena_stalls", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64)]
+
+
 ARRIVAL_DTYPE = np.dtype([("t_ns", np.int64), ("instance", np.uint32), ("reserved", np.uint32),
                           ("count", np.uint64)])
 
@@ -116,10 +122,12 @@ SIGNATURES = {
     "phprng_server_submit": (ctypes.c_int, [_vp, ctypes.c_uint32, _u64, _u64, _pu64]),
     "phprng_server_poll": (ctypes.c_int, [_vp, ctypes.POINTER(phprng_completion), _u64, _pu64, ctypes.c_int64]),
     "phprng_server_release": (ctypes.c_int, [_vp, _u64]),
+    "phprng_server_release_many": (ctypes.c_int, [_vp, _vp, _u64]),
     "phprng_server_stats": (ctypes.c_int, [_vp, _pu64, _pu64]),
+    "phprng_server_read_counters": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
     "phprng_server_destroy": (ctypes.c_int, [_vp]),
     "phprng_server_replay": (ctypes.c_int, [_vp, _vp, _u64, ctypes.POINTER(ctypes.c_int64),
-                                            ctypes.POINTER(ctypes.c_double)]),
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "phprng_timing_reset": (ctypes.c_int, [_vp]),
     "phprng_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
     "phprng_battery_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int]),
@@ -434,19 +442,38 @@ class Server:
     def release(self, ticket):
         _check(lib().phprng_server_release(self._h, int(ticket)))
 
+    def release_many(self, tickets):
+        t = np.ascontiguousarray(tickets, dtype=np.uint64)
+        _check(lib().phprng_server_release_many(self._h, t.ctypes.data, t.size))
+
     def stats(self):
         p, u = _u64(), _u64()
         _check(lib().phprng_server_stats(self._h, ctypes.byref(p), ctypes.byref(u)))
         return p.value, u.value
 
+    def counters(self, reset=False):
+        """Launch counters (batches, requests, draws, launch_ns, launch_ns_max,
+        arena_stalls, arena_peak) as a dict; reset clears them after the read."""
+        c = phprng_server_counters()
+        _check(lib().phprng_server_read_counters(self._h, ctypes.byref(c), 1 if reset else 0))
+        return {k: getattr(c, k) for k, _ in phprng_server_counters._fields_}
+
     def replay(self, arrivals):
         """arrivals: numpy array of ARRIVAL_DTYPE.  Returns (latency_ns array, wall seconds)."""
+        lat, _, wall = self.replay_detail(arrivals)
+        return lat, wall
+
+    def replay_detail(self, arrivals):
+        """As replay, plus the per-arrival admission delay: returns (latency_ns,
+        admit_ns, wall seconds)."""
         arr = np.ascontiguousarray(arrivals, dtype=ARRIVAL_DTYPE)
         lat = np.zeros(arr.size, dtype=np.int64)
+        adm = np.zeros(arr.size, dtype=np.int64)
         wall = ctypes.c_double()
-        _check(lib().phprng_server_replay(self._h, arr.ctypes.data, arr.size,
-                                          lat.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(wall)))
-        return lat, wall.value
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        _check(lib().phprng_server_replay(self._h, arr.ctypes.data, arr.size, lat.ctypes.data_as(i64p),
+                                          adm.ctypes.data_as(i64p), ctypes.byref(wall)))
+        return lat, adm, wall.value
 
     def close(self):
         if getattr(self, "_h", None):

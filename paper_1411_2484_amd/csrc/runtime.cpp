@@ -105,6 +105,7 @@ struct phprng_ctx {
     bool busy = false;
   };
   static constexpr int kSlots = 8;
+  static constexpr uint64_t kMinSlotRequests = 8192;
   Slot slots[kSlots];
   int cur_slot = 0;
   int last_timed = -1;
@@ -245,7 +246,9 @@ struct phprng_ctx {
       if ((e = hipMemset(s.d_hdr, 0, sizeof(PlanHdr))) != hipSuccess) return hip_fail(e, "plan header");
     }
     if (nreq > s.cap) {
-      uint64_t cap = std::max<uint64_t>(nreq, 2 * s.cap);
+      // room for typical batches from the start: growing frees buffers,
+      // which waits for the device
+      uint64_t cap = std::max<uint64_t>({nreq, 2 * s.cap, kMinSlotRequests});
       if (s.d_req) (void)hipFree(s.d_req);
       if (s.d_gbase) (void)hipFree(s.d_gbase);
       if (s.h_req) (void)hipHostFree(s.h_req);

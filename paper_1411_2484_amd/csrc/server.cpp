@@ -103,20 +103,34 @@ struct phprng_server {
   std::vector<Batch> batches;  // max_inflight entries
   int next_stream = 0;
 
+  // Two locks, so that submitters, the scheduler and releasers rarely wait
+  // for each other: mu guards the request queue and the completions, amu
+  // the arena, the live ranges and the counters.  Never hold amu while
+  // taking mu.
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Pending> pending;
+  // pending.size(), readable without the lock: the scheduler polls it while
+  // batches run, and taking mu in that loop would starve submitters
+  std::atomic<size_t> npending{0};
   std::deque<phprng_completion> completions;
-  std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> live;  // ticket -> (offset, count)
   uint64_t next_ticket = 1;
+
+  std::mutex amu;
+  std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> live;  // ticket -> (offset, count)
+  phprng_server_counters counters{};
+  std::atomic<uint64_t> releases{0};     // arena releases so far
+  std::atomic<bool> arena_blocked{false};  // the oldest request did not fit
+  uint64_t blocked_at = 0;               // releases when that was found (scheduler only)
+
   uint64_t ninst = 0;
   std::atomic<bool> stop{false};
   std::thread thread;
-  phprng_status sticky = PHPRNG_OK;
 
   void loop();
   bool retire_finished();
   bool launch_batch(Batch &b);
+  phprng_status release_many(const uint64_t *tickets, uint64_t n);
 };
 
 bool phprng_server::retire_finished() {
@@ -141,18 +155,35 @@ bool phprng_server::retire_finished() {
 }
 
 bool phprng_server::launch_batch(Batch &b) {
-  std::vector<phprng_request> reqs;
-  std::vector<phprng_completion> meta;
+  // take the batch's candidates off the queue (batch limits only) ...
+  std::vector<Pending> take;
   {
     std::lock_guard<std::mutex> lk(mu);
     uint64_t draws = 0;
-    while (!pending.empty() && reqs.size() < cfg.max_batch_requests) {
+    while (!pending.empty() && take.size() < cfg.max_batch_requests) {
       const Pending &p = pending.front();
-      if (!reqs.empty() && draws + p.count > cfg.max_batch_draws) break;
+      if (!take.empty() && draws + p.count > cfg.max_batch_draws) break;
+      draws += p.count;
+      take.push_back(p);
+      pending.pop_front();
+    }
+    npending.store(pending.size());
+  }
+  if (take.empty()) return false;
+  // ... then admit them in FIFO order while the arena has room
+  std::vector<phprng_request> reqs;
+  std::vector<phprng_completion> meta;
+  size_t fit = 0;
+  {
+    std::lock_guard<std::mutex> lk(amu);
+    for (; fit < take.size(); ++fit) {
+      const Pending &p = take[fit];
       uint64_t off = 0;
-      if (!arena->alloc(p.count, &off)) break;  // memory admission: wait for releases
-      phprng_request r{p.instance, 0, p.count, off};
-      reqs.push_back(r);
+      if (!arena->alloc(p.count, &off)) {
+        counters.arena_stalls += 1;
+        break;
+      }
+      reqs.push_back(phprng_request{p.instance, 0, p.count, off});
       phprng_completion c;
       memset(&c, 0, sizeof c);
       c.ticket = p.ticket;
@@ -163,9 +194,16 @@ bool phprng_server::launch_batch(Batch &b) {
       c.t_submit_ns = p.t_submit;
       live[p.ticket] = {off, p.count};
       meta.push_back(c);
-      draws += p.count;
-      pending.pop_front();
     }
+    counters.arena_peak = std::max(counters.arena_peak, arena->used());
+    if (fit == 0) blocked_at = releases.load();
+    arena_blocked.store(fit == 0);
+  }
+  if (fit < take.size()) {
+    // the rest waits for arena room, still at the head of the queue
+    std::lock_guard<std::mutex> lk(mu);
+    pending.insert(pending.begin(), take.begin() + (std::ptrdiff_t)fit, take.end());
+    npending.store(pending.size());
   }
   if (reqs.empty()) return false;
   // positions before the draws of each request (request order = FIFO order)
@@ -186,6 +224,17 @@ bool phprng_server::launch_batch(Batch &b) {
   phprng_status st = phprng_generate(ctx, reqs.data(), reqs.size(), nullptr, nullptr, arena_ptr,
                                      cfg.arena_doubles, (void *)s, PHPRNG_MODE_PERSISTENT);
   if (st == PHPRNG_OK && hipEventRecord(b.done, s) != hipSuccess) st = PHPRNG_E_DEVICE;
+  {
+    const int64_t dt = now_ns() - t_admit;
+    uint64_t draws = 0;
+    for (const auto &r : reqs) draws += r.count;
+    std::lock_guard<std::mutex> lk(amu);
+    counters.batches += 1;
+    counters.requests += reqs.size();
+    counters.draws += draws;
+    counters.launch_ns += dt;
+    counters.launch_ns_max = std::max(counters.launch_ns_max, dt);
+  }
   for (auto &c : meta) {
     c.t_admit_ns = t_admit;
     c.status = st;
@@ -207,27 +256,28 @@ void phprng_server::loop() {
     bool progress = retire_finished();
     for (auto &b : batches) {
       if (b.active) continue;
-      bool have;
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        have = !pending.empty();
-      }
-      if (!have) break;
+      if (npending.load() == 0) break;
+      if (arena_blocked.load() && releases.load() == blocked_at) break;  // no room yet
       if (!launch_batch(b)) break;
       progress = true;
     }
     if (!progress) {
       bool inflight = false;
       for (auto &b : batches) inflight = inflight || b.active;
-      std::unique_lock<std::mutex> lk(mu);
       if (inflight) {
         // a batch is on the device: keep polling its event (completion times
-        // are taken here, so the loop spins rather than sleeps)
-        lk.unlock();
+        // are taken here, so the loop spins rather than sleeps) without
+        // touching the lock
         std::this_thread::yield();
       } else {
-        cv_work.wait_for(lk, std::chrono::microseconds(200),
-                         [&] { return stop.load() || !pending.empty(); });
+        // idle, or the arena has no room for the oldest request: sleep until
+        // a submission, or a release in the second case
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait_for(lk, std::chrono::microseconds(200), [&] {
+          if (stop.load()) return true;
+          if (arena_blocked.load() && releases.load() == blocked_at) return false;
+          return !pending.empty();
+        });
       }
     }
   }
@@ -279,6 +329,7 @@ extern "C" phprng_status phprng_server_submit(phprng_server *s, uint32_t instanc
     std::lock_guard<std::mutex> lk(s->mu);
     *ticket = s->next_ticket++;
     s->pending.push_back(Pending{*ticket, tag, count, instance, now_ns()});
+    s->npending.store(s->pending.size());
   }
   s->cv_work.notify_one();
   return PHPRNG_OK;
@@ -299,22 +350,62 @@ extern "C" phprng_status phprng_server_poll(phprng_server *s, phprng_completion 
   return PHPRNG_OK;
 }
 
+phprng_status phprng_server::release_many(const uint64_t *tickets, uint64_t n) {
+  phprng_status st = PHPRNG_OK;
+  uint64_t k = 0;
+  {
+    std::lock_guard<std::mutex> lk(amu);
+    for (uint64_t i = 0; i < n; ++i) {
+      auto it = live.find(tickets[i]);
+      if (it == live.end()) {
+        st = PHPRNG_E_INVALID;
+        continue;
+      }
+      arena->release(it->second.first, it->second.second);
+      live.erase(it);
+      ++k;
+    }
+    releases.fetch_add(k);
+  }
+  if (k) {
+    // a scheduler blocked on the arena checks `releases` under mu before it
+    // sleeps: passing through mu orders this release before its next check
+    if (arena_blocked.load()) {
+      std::lock_guard<std::mutex> lk(mu);
+    }
+    cv_work.notify_one();
+  }
+  return st;
+}
+
 extern "C" phprng_status phprng_server_release(phprng_server *s, uint64_t ticket) {
   if (!s) return PHPRNG_E_INVALID;
-  std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->live.find(ticket);
-  if (it == s->live.end()) return PHPRNG_E_INVALID;
-  s->arena->release(it->second.first, it->second.second);
-  s->live.erase(it);
-  s->cv_work.notify_one();
-  return PHPRNG_OK;
+  return s->release_many(&ticket, 1);
+}
+
+extern "C" phprng_status phprng_server_release_many(phprng_server *s, const uint64_t *tickets, uint64_t n) {
+  if (!s || (n > 0 && !tickets)) return PHPRNG_E_INVALID;
+  return s->release_many(tickets, n);
 }
 
 extern "C" phprng_status phprng_server_stats(phprng_server *s, uint64_t *pending, uint64_t *arena_used) {
   if (!s) return PHPRNG_E_INVALID;
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (pending) *pending = s->pending.size();
-  if (arena_used) *arena_used = s->arena->used();
+  if (pending) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    *pending = s->pending.size();
+  }
+  if (arena_used) {
+    std::lock_guard<std::mutex> lk(s->amu);
+    *arena_used = s->arena->used();
+  }
+  return PHPRNG_OK;
+}
+
+extern "C" phprng_status phprng_server_read_counters(phprng_server *s, phprng_server_counters *out, int reset) {
+  if (!s || !out) return PHPRNG_E_INVALID;
+  std::lock_guard<std::mutex> lk(s->amu);
+  *out = s->counters;
+  if (reset) s->counters = phprng_server_counters{};
   return PHPRNG_OK;
 }
 
@@ -333,26 +424,32 @@ extern "C" phprng_status phprng_server_destroy(phprng_server *s) {
 }
 
 extern "C" phprng_status phprng_server_replay(phprng_server *s, const phprng_arrival *arr, uint64_t n,
-                                              int64_t *latency_ns, double *wall_s) {
+                                              int64_t *latency_ns, int64_t *admit_ns, double *wall_s) {
   if (!s || (n > 0 && (!arr || !latency_ns)) || !wall_s) return PHPRNG_E_INVALID;
   for (uint64_t i = 0; i < n; ++i)
     if (arr[i].instance >= s->ninst || arr[i].count > s->cfg.arena_doubles) return PHPRNG_E_INVALID;
   const int64_t t0 = now_ns() + 2000000;  // first arrival 2 ms from now
   std::atomic<int> submit_status{PHPRNG_OK};
   std::thread submitter([&] {
-    for (uint64_t i = 0; i < n; ++i) {
-      const int64_t due = t0 + arr[i].t_ns;
-      while (now_ns() < due) {
+    // every arrival that is due goes into the queue under one lock; tag =
+    // arrival index, and latency is measured from the scheduled arrival
+    uint64_t i = 0;
+    while (i < n) {
+      if (now_ns() < t0 + arr[i].t_ns) continue;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const int64_t t = now_ns();
+        for (; i < n && t0 + arr[i].t_ns <= t; ++i)
+          s->pending.push_back(Pending{s->next_ticket++, i, arr[i].count, arr[i].instance, t});
+        s->npending.store(s->pending.size());
       }
-      uint64_t ticket;
-      // tag = arrival index; latency is measured from the scheduled arrival
-      if (phprng_server_submit(s, arr[i].instance, arr[i].count, i, &ticket) != PHPRNG_OK)
-        submit_status.store(PHPRNG_E_INVALID);
+      s->cv_work.notify_one();
     }
   });
   phprng_status result = PHPRNG_OK;
   uint64_t done = 0;
   std::vector<phprng_completion> buf(1024);
+  std::vector<uint64_t> tickets(buf.size());
   int64_t t_last = t0;
   const int64_t deadline = t0 + (n ? arr[n - 1].t_ns : 0) + 120ll * 1000000000ll;
   while (done < n) {
@@ -363,12 +460,14 @@ extern "C" phprng_status phprng_server_replay(phprng_server *s, const phprng_arr
       const uint64_t i = c.tag;
       if (i < n) {
         latency_ns[i] = c.status == PHPRNG_OK ? c.t_done_ns - (t0 + arr[i].t_ns) : -1;
+        if (admit_ns) admit_ns[i] = c.status == PHPRNG_OK ? c.t_admit_ns - (t0 + arr[i].t_ns) : -1;
         if (c.status != PHPRNG_OK) result = (phprng_status)c.status;
       }
       t_last = std::max(t_last, c.t_done_ns);
-      phprng_server_release(s, c.ticket);
+      tickets[j] = c.ticket;
       ++done;
     }
+    s->release_many(tickets.data(), k);
     if (now_ns() > deadline) {
       result = PHPRNG_E_DEVICE;
       break;

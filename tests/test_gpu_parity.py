@@ -116,6 +116,42 @@ def test_same_instance_in_several_requests(ph, ctx, orc, tabs):
     assert _positions(ctx, [a, b]) == [k_a + 6001, k_b + 5048]
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_plan_groups_ragged_and_empty(ph, ctx, orc, tabs, mode):
+    """700 requests, planned in groups of 256, 256 and a ragged 188: the
+    whole second group asks for nothing, empty requests are scattered through
+    the others, and every instance appears twice, the second time in a later
+    group, so that positions carry across groups.  Nothing outside the
+    requested ranges is written."""
+    rng = random.Random(300 + mode)
+    ids = [int(x) for x in ctx.seed_instances(32, SEED0 + 300 + mode, 350, (9, 17), 0, 1 << 40)]
+    pos = dict(zip(ids, _positions(ctx, ids)))
+    order = ids + ids[::-1]
+    counts = []
+    for j in range(len(order)):
+        if 256 <= j < 512:
+            counts.append(0)
+        elif j % 7 == 0:
+            counts.append(rng.choice([0, 1, 2047, 2048, 2049]))
+        else:
+            counts.append(rng.randrange(1, 5000))
+    specs = list(zip(order, counts))
+    starts = []
+    for iid, c in specs:
+        starts.append(pos[iid])
+        pos[iid] += c
+    host, offs = _run(ph, ctx, specs, mode=mode, gap=3)
+    keep = [i for i, c in enumerate(counts) if c > 0]
+    _check(orc, tabs, ctx, [specs[i] for i in keep], [starts[i] for i in keep], host, [offs[i] for i in keep],
+           "plan groups")
+    assert _positions(ctx, ids) == [pos[i] for i in ids]
+    covered = np.zeros(host[2].size, dtype=bool)
+    for (iid, c), off in zip(specs, offs):
+        covered[off:off + c] = True
+    assert np.all(host[0][~covered] == np.uint32(0xffffffff))
+    assert np.all(host[2][~covered] == -1.0)
+
+
 def test_exponents_fixed_and_generic_chains(ph, ctx, orc, tabs):
     rng = random.Random(7)
     ns, es = [], []

@@ -88,7 +88,16 @@ def test_server_results_match_oracle_alone_and_in_mix(ph, orc, tabs):
         data = _read(c.data, c.count)
         _check_completion(ph, params, orc, tabs, c, data)
         checked.append((c.instance, c.k, c.count, data))
-        srv.release(c.ticket)
+    # half released one by one, the rest in one call; a ticket already
+    # released is refused while the others in the same call still go back
+    tickets = [c.ticket for c in got]
+    half = len(tickets) // 2
+    for t in tickets[:half]:
+        srv.release(t)
+    assert srv.stats()[1] > 0
+    with pytest.raises(ph.PhprngError):
+        srv.release_many(tickets[half:] + [tickets[0]])
+    assert srv.stats()[1] == 0
     srv.close()
     ctx.close()
     # the same ranges requested alone, one request per fresh context, give the same bits
@@ -144,8 +153,13 @@ def test_server_open_loop_replay(ph):
     arr["t_ns"] = np.cumsum(rng.exponential(1e9 / 20000.0, n)).astype(np.int64)  # 20k req/s
     arr["instance"] = rng.integers(0, 1000, n)
     arr["count"] = np.floor(2.0 ** (8 + 8 * rng.random(n))).astype(np.uint64)
-    lat, wall = srv.replay(arr)
+    srv.counters(reset=True)
+    lat, adm, wall = srv.replay_detail(arr)
+    cnt = srv.counters()
+    assert cnt["requests"] == n and cnt["draws"] == int(arr["count"].sum())
+    assert 1 <= cnt["batches"] <= n and cnt["launch_ns_max"] * cnt["batches"] >= cnt["launch_ns"] > 0
     assert (lat > 0).all()
+    assert (adm >= 0).all() and (adm <= lat).all()
     assert np.percentile(lat, 50) < 5e6  # well under 5 ms at this light load
     assert wall > 0
     srv.close()
