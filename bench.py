@@ -169,12 +169,21 @@ def workload_c(args, torch, ph):
     steps = max(2, args.steps // 5)
     ms, kms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, c32, None, r, capacity=arena), steps, 1)
     rms, rkms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, None, None, r, capacity=arena), steps, 1)
+    # draw-weighted algorithmic op count over the instances' exponents
+    es = np.array([ctx.get_params(int(i))[1] for i in ids])
+    ops = float(np.sum(lens.astype(np.float64) * np.array([algorithmic_ops_32(e) for e in es])) / total)
     ctx.close()
     value = total / (ms * 1e-3) / 1e9
+    gbs = total * 12.0 / (kms * 1e-3) / 1e9
+    alu = total * ops / (kms * 1e-3)
+    roofs = {"alu": {"achieved": alu / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Top/s",
+                     "frac": alu / ALU_PEAK_OPS, "ops_per_draw": ops},
+             "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "bytes_per_draw": 12.0}}
     return common_line(value, "Guniforms/s", steps, 1, ms,
                        {"workload": "65536 seeded 32-bit instances, log-uniform lengths 2^10..2^22 (%d draws), "
                                     "random starts in [0, 2^40), one persistent launch, u32 c + f64 R" % total},
-                       kernel_ms=kms, hbm_gbs=total * 12.0 / (kms * 1e-3) / 1e9,
+                       kernel_ms=kms, hbm_gbs=gbs, roofline_fractions=roofs,
                        uniforms_only={"value": total / (rms * 1e-3) / 1e9, "kernel_ms": rkms})
 
 
@@ -500,7 +509,7 @@ def main():
                     help="workload F: also test one stream of this many uniforms (multiple of 2^30)")
     ap.add_argument("--serve-instances", type=int, default=1000000)
     ap.add_argument("--serve-arena", type=int, default=1 << 31, help="serving arena, FP64 uniforms")
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=[1e3, 1e4, 1e5, 1e6])
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[1e3, 3e3, 1e4, 3e4, 1e5, 3e5, 1e6, 3e6])
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--serve-max-requests", type=int, default=200000)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,

@@ -34,6 +34,19 @@ __device__ __forceinline__ uint32_t powmod_p31(uint32_t b, uint64_t e) {
   return r;
 }
 
+// One in an SGPR that the compiler cannot fold to a constant.
+__device__ __forceinline__ uint32_t opaque_one() {
+  uint32_t one;
+  asm volatile("s_mov_b32 %0, 1" : "=s"(one));
+  return one;
+}
+
+// acc + x as a single v_mad_u64_u32 (x * one + acc, one == 1): the 32-bit
+// addend needs no zero-extended register pair.
+__device__ __forceinline__ uint64_t acc_u32(uint64_t acc, uint32_t x, uint32_t one) {
+  return (uint64_t)x * one + acc;
+}
+
 // ---- 32-bit Montgomery arithmetic modulo n in [2^31, 2^32) ----------------
 
 // x y 2^{-32} mod n for x, y < n; ninv = n^{-1} mod 2^32.  The low words of
@@ -329,6 +342,22 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
 }
 
 // ---- wave helpers ---------------------------------------------------------
+
+// Load of a record that no kernel writes while this one runs, at an address
+// that is the same in every lane: through the constant address space, so that
+// the compiler reads it with scalar loads into SGPRs and the arithmetic on it
+// runs on the scalar unit instead of in every lane.
+template <typename T>
+__device__ __forceinline__ T const_load(const T *p) {
+  static_assert(sizeof(T) % 8 == 0, "records of whole 64-bit words");
+  using CP = const __attribute__((address_space(4))) uint64_t *;
+  const CP q = (CP)p;
+  T out;
+  uint64_t *o = reinterpret_cast<uint64_t *>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 8); ++i) o[i] = q[i];
+  return out;
+}
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 

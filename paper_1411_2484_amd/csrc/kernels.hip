@@ -310,6 +310,7 @@ __device__ void run_chunk32(const GenArgs &A, const InstRec &I, const ReqRec &R,
   const double den = I.den, rcp = I.rcp;
   const uint64_t pm1 = (uint64_t)kP32 - 1;
   const uint32_t lane_mul = A.lanemul->m32[lane];
+  const uint32_t one = dev::opaque_one();
 
   const uint64_t g_begin = R.g1 + chunk * A.tiles_per_chunk;
   const uint64_t g_end = min(g_begin + A.tiles_per_chunk, R.g1 + R.ntiles);
@@ -336,7 +337,7 @@ __device__ void run_chunk32(const GenArgs &A, const InstRec &I, const ReqRec &R,
     for (int i = 0; i < kRun; ++i) {
       s = dev::mulmod_p31(kA32, s);
       row[i] = s;
-      sum += s;
+      sum = dev::acc_u32(sum, s, one);
     }
     // ---- pass B: exclusive wave scan of run sums -> run start message
     uint64_t incl = sum;
@@ -646,7 +647,7 @@ __global__ void __launch_bounds__(BLOCK) gen_persistent(GenArgs A) {
   using LT = typename WaveLds<HAS64>::T;
   __shared__ LT lds[BLOCK / 64][WaveLds<HAS64>::kWords];
   const uint32_t lane = dev::lane_id();
-  const uint32_t wave = threadIdx.x / 64;
+  const uint32_t wave = dev::uniform_u32(threadIdx.x / 64);  // wave-uniform: keeps chunk math scalar
   LT *L = lds[wave];
   const uint64_t total = dev::uniform_u64(A.hdr->total_chunks);
   // The first chunk of every wave is its global wave index; later chunks come
@@ -657,9 +658,9 @@ __global__ void __launch_bounds__(BLOCK) gen_persistent(GenArgs A) {
   for (;;) {
     if (c >= total) break;
     const uint64_t r = dev::uniform_u64(find_request(A, c, lane));
-    const ReqRec R = A.req[r];
-    const InstRec &I = A.inst[R.inst];
-    const uint64_t chunk = c - (A.gbase[r / kPlanGroup] + R.chunk_base);
+    const ReqRec R = dev::const_load(A.req + r);
+    const InstRec I = dev::const_load(A.inst + R.inst);
+    const uint64_t chunk = c - (dev::const_load(A.gbase + r / kPlanGroup) + R.chunk_base);
     if (I.sched == kSchedConstant) {
       if (HAS64 && I.width == 64) run_chunk64_cs<UNROLL>(A, I, R, chunk, lane);
       else run_chunk32_cs<UNROLL>(A, I, R, chunk, lane);
@@ -680,9 +681,9 @@ __global__ void __launch_bounds__(64) gen_plain(GenArgs A, uint64_t r) {
   using LT = typename WaveLds<HAS64>::T;
   __shared__ LT lds[WaveLds<HAS64>::kWords];
   const uint32_t lane = dev::lane_id();
-  const ReqRec R = A.req[r];
+  const ReqRec R = dev::const_load(A.req + r);
   if ((uint64_t)blockIdx.x >= R.nchunks) return;
-  const InstRec &I = A.inst[R.inst];
+  const InstRec I = dev::const_load(A.inst + R.inst);
   if (I.sched == kSchedConstant) {
     if (HAS64 && I.width == 64) run_chunk64_cs<UNROLL>(A, I, R, blockIdx.x, lane);
     else run_chunk32_cs<UNROLL>(A, I, R, blockIdx.x, lane);
