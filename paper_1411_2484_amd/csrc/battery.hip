@@ -32,7 +32,7 @@ __device__ __forceinline__ uint32_t poker_cat(const uint32_t d[5]) {
 }
 
 // Keys of one test for one tile, held in registers for the partitioned
-// histogram: item j = threadIdx.x + it * 256 is the j-th D-tuple of the tile
+// histogram: item j = threadIdx.x + it * kHistThreads is the j-th D-tuple of the tile
 // (D = 1: the j-th uniform), its key the partition-space offset of the test
 // plus its cell (first element most significant).
 template <int D, uint32_t B, int K>
@@ -40,7 +40,7 @@ __device__ __forceinline__ void tuple_keys(const double *t, uint32_t len, uint32
   const uint32_t ntup = len / D;
 #pragma unroll
   for (int it = 0; it < K; ++it) {
-    const uint32_t j = threadIdx.x + it * 256;
+    const uint32_t j = threadIdx.x + it * kHistThreads;
     uint32_t cell = 0;
     if (j < ntup) {
 #pragma unroll
@@ -51,37 +51,59 @@ __device__ __forceinline__ void tuple_keys(const double *t, uint32_t len, uint32
 }
 
 // Registers per thread for the keys of one tile: 15 + 8 + 5 + 4 + 3.
-constexpr int kK1 = kHistTile / 256, kK2 = (kHistTile / 2 + 255) / 256, kK3 = (kHistTile / 3 + 255) / 256;
-constexpr int kK4 = (kHistTile / 4 + 255) / 256, kK5 = (kHistTile / 5 + 255) / 256;
+constexpr int kT = (int)kHistThreads;
+constexpr int kK1 = kHistTile / kT, kK2 = (kHistTile / 2 + kT - 1) / kT, kK3 = (kHistTile / 3 + kT - 1) / kT;
+constexpr int kK4 = (kHistTile / 4 + kT - 1) / kT, kK5 = (kHistTile / 5 + kT - 1) / kT;
 constexpr int kKeys = kK1 + kK2 + kK3 + kK4 + kK5;
 
 // One tile of one block: frequency and serial D = 2..5 keys into the
 // partitioned histograms, the poker histogram, and the bits R > 1/2 packed
 // one 64-bit word per 64 uniforms (for the runs test).
-__global__ __launch_bounds__(256) void hist_kernel(const double *__restrict__ r, ph::PartSet P, BatteryParts bp,
+__global__ __launch_bounds__(kHistThreads) void hist_kernel(const double *__restrict__ r, ph::PartSet P, BatteryParts bp,
                                                    unsigned long long *poker_hist, uint64_t *__restrict__ bits) {
   // the tile of uniforms, later reused as the key staging area of the scatter
-  __shared__ __align__(16) uint32_t buf[kKeys * 256];
-  static_assert(kKeys * 256 * 4 >= kHistTile * 8, "staging area must hold the tile");
+  __shared__ __align__(16) uint32_t buf[kKeys * kHistThreads];
+  static_assert(kKeys * kHistThreads * 4 >= kHistTile * 8, "staging area must hold the tile");
   __shared__ uint32_t poker[kPokerCats];
   __shared__ uint32_t cnt[kMaxParts], poff[kMaxParts], base[kMaxParts];
   double *t = reinterpret_cast<double *>(buf);
   const uint32_t tile = blockIdx.x % kHistTilesPerBlock;
   const uint64_t blk = blockIdx.x / kHistTilesPerBlock;
   const uint32_t off = tile * kHistTile;
-  const uint32_t len = (kBlock - off) < kHistTile ? (kBlock - off) : kHistTile;  // 3840 or 256
+  const uint32_t len = (kBlock - off) < kHistTile ? (kBlock - off) : kHistTile;  // 7680 or 4096
   const uint64_t base_i = blk * kBlock + off;
   if (threadIdx.x < kPokerCats) poker[threadIdx.x] = 0;
-  // len is a multiple of 256, so every wave covers 64 consecutive uniforms per step
-  for (uint32_t i = threadIdx.x; i < len; i += 256) {
-    const double x = r[base_i + i];
-    t[i] = x;
-    const uint64_t word = __ballot(x > 0.5);
-    if ((threadIdx.x & 63) == 0) bits[(base_i + i) >> 6] = word;
+  // all of the thread's loads in flight at once (a loop that waits for each
+  // load before the next pays the memory latency 15 times), then the LDS copy
+  // and the run bits; len is a multiple of the workgroup size, so the bounds
+  // test is uniform and every wave covers 64 consecutive uniforms per step
+  constexpr uint32_t kPer = kHistTile / kHistThreads;
+  static_assert(kHistTile % kHistThreads == 0 && (kBlock % kHistTile) % kHistThreads == 0,
+                "whole steps of the workgroup");
+  double x[kPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t i = threadIdx.x + kHistThreads * k;
+    x[k] = i < len ? r[base_i + i] : 0.0;
   }
+  // the wave's k-th run-bit word is kept by lane k and all are stored at the
+  // end with one instruction: a store inside the loop would make every later
+  // step wait for it
+  const uint32_t lane = threadIdx.x & 63, wbase = threadIdx.x - lane;
+  uint64_t mine = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t i = threadIdx.x + kHistThreads * k;
+    if (i < len) {
+      t[i] = x[k];
+      const uint64_t word = __ballot(x[k] > 0.5);
+      if (lane == k) mine = word;
+    }
+  }
+  if (lane < kPer && wbase + kHistThreads * lane < len) bits[(base_i + wbase + kHistThreads * lane) >> 6] = mine;
   __syncthreads();
   const uint32_t nhand = len / 5;
-  for (uint32_t j = threadIdx.x; j < nhand; j += 256) {
+  for (uint32_t j = threadIdx.x; j < nhand; j += kHistThreads) {
     uint32_t d[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) d[i] = bin_of(t[j * 5 + i], 10);
@@ -96,7 +118,7 @@ __global__ __launch_bounds__(256) void hist_kernel(const double *__restrict__ r,
   tuple_keys<3, kAxis3, kK3>(t, len, bp.p0[2] << ph::kPartBits, key + kK1 + kK2);
   tuple_keys<4, kAxis4, kK4>(t, len, bp.p0[3] << ph::kPartBits, key + kK1 + kK2 + kK3);
   tuple_keys<5, kAxis5, kK5>(t, len, bp.p0[4] << ph::kPartBits, key + kK1 + kK2 + kK3 + kK4);
-  ph::scatter_staged<256, kKeys>(key, P, 0, P.npart, cnt, poff, base, buf);
+  ph::scatter_staged<kHistThreads, kKeys>(key, P, 0, P.npart, cnt, poff, base, buf);
   if (threadIdx.x < kPokerCats && poker[threadIdx.x])
     atomicAdd(&poker_hist[threadIdx.x], (unsigned long long)poker[threadIdx.x]);
 }
@@ -107,12 +129,18 @@ __global__ __launch_bounds__(1024) void collision_kernel(const double *__restric
   __shared__ uint32_t bm[kCollUrns / 32];
   __shared__ uint32_t total;
   const double *src = r + (uint64_t)blockIdx.x * kCollBalls;
+  // the balls' loads go out before the bitmap is cleared, all at once
+  constexpr uint32_t kPer = kCollBalls / 1024;
+  double x[kPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) x[k] = src[threadIdx.x + 1024 * k];
   for (uint32_t i = threadIdx.x; i < kCollUrns / 32; i += 1024) bm[i] = 0;
   if (threadIdx.x == 0) total = 0;
   __syncthreads();
   uint32_t coll = 0;
-  for (uint32_t i = threadIdx.x; i < kCollBalls; i += 1024) {
-    const uint32_t u = bin_of(src[i], kCollUrns);
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t u = bin_of(x[k], kCollUrns);
     const uint32_t bit = 1u << (u & 31);
     const uint32_t old = atomicOr(&bm[u >> 5], bit);
     coll += (old & bit) ? 1u : 0u;
@@ -191,10 +219,18 @@ __global__ __launch_bounds__(256) void fft_pass1_kernel(const double *__restrict
   const uint64_t blk = blockIdx.x / kFftPass1Groups;
   const uint32_t c0 = (blockIdx.x % kFftPass1Groups) * kFftCols;
   const double2 *src = reinterpret_cast<const double2 *>(r + blk * kBlock);
-  for (uint32_t e = threadIdx.x; e < kFftCols * kFftN1; e += 256) {
-    const uint32_t j1 = e / kFftCols, col = e % kFftCols;
-    const double2 v = src[(uint64_t)j1 * kFftN2 + c0 + col];
-    st[col * kP1Stride + j1] = make_double2(v.x - 0.5, v.y - 0.5);
+  // the thread's 16 loads in flight at once, then into the columns
+  constexpr uint32_t kPer = kFftCols * kFftN1 / 256;
+  double2 in[kPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t e = threadIdx.x + 256 * k, j1 = e / kFftCols, col = e % kFftCols;
+    in[k] = src[(uint64_t)j1 * kFftN2 + c0 + col];
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t e = threadIdx.x + 256 * k, j1 = e / kFftCols, col = e % kFftCols;
+    st[col * kP1Stride + j1] = make_double2(in[k].x - 0.5, in[k].y - 0.5);
   }
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63, l = lane & 31;
@@ -372,7 +408,7 @@ __global__ __launch_bounds__(256) void interleave_kernel(const double *__restric
 
 hipError_t launch_hist(const double *r, uint64_t nblocks, const ph::PartSet &P, const BatteryParts &bp,
                        unsigned long long *poker, uint64_t *bits, hipStream_t st) {
-  hist_kernel<<<dim3((unsigned)(nblocks * kHistTilesPerBlock)), dim3(256), 0, st>>>(r, P, bp, poker, bits);
+  hist_kernel<<<dim3((unsigned)(nblocks * kHistTilesPerBlock)), dim3(kHistThreads), 0, st>>>(r, P, bp, poker, bits);
   return hipGetLastError();
 }
 

@@ -27,9 +27,12 @@ constexpr int kFourierHalf = 32;
 constexpr uint32_t kFourierCats = 2 * kFourierHalf + 2;
 constexpr uint32_t kWordsPerBlock = kBlock / 64;
 
-// Histogram tile: 3840 = 60 * 64 uniforms, a multiple of every tuple length
-// (2..5) and of the wave width; a block is 273 full tiles and a 256-uniform tail.
-constexpr uint32_t kHistTile = 3840;
+// Histogram tile: 7680 = 120 * 64 uniforms for a workgroup of 512 threads, a
+// multiple of every tuple length (2..5) and of the workgroup; a block is 136
+// full tiles and a 4096-uniform tail.  Every tile reserves bucket room once
+// per partition with a global atomic, so a larger tile means fewer of them.
+constexpr uint32_t kHistThreads = 512;
+constexpr uint32_t kHistTile = 7680;
 constexpr uint32_t kHistTilesPerBlock = (kBlock + kHistTile - 1) / kHistTile;
 
 // Real transform of M = 2^20 points through one complex transform of

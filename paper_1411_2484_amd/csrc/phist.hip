@@ -18,15 +18,27 @@ __global__ __launch_bounds__(1024) void count_kernel(PartSet P) {
   const uint32_t lo = (uint32_t)((uint64_t)fill * s / P.nslice) & ~7u;
   const uint32_t hi = s + 1 == P.nslice ? fill : (uint32_t)((uint64_t)fill * (s + 1) / P.nslice) & ~7u;
   const uint16_t *d = P.data + (uint64_t)p * P.cap;  // cap is a multiple of 8
-  // 16-byte loads keep enough bytes in flight to cover the memory latency
+  // 16-byte loads, kU of them in flight per thread before any is counted:
+  // a loop that waits for each load pays the full memory latency per step
+  constexpr uint32_t kU = 8;
   const uint4 *dv = reinterpret_cast<const uint4 *>(d);
-  for (uint32_t v = lo / 8 + threadIdx.x; v < hi / 8; v += 1024) {
-    const uint4 w = dv[v];
-    const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+  const uint32_t vend = hi / 8;
+  for (uint32_t v0 = lo / 8 + threadIdx.x; v0 < vend; v0 += 1024 * kU) {
+    uint4 w[kU];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      atomicAdd(&c[q[k] & 0xffffu], 1u);
-      atomicAdd(&c[q[k] >> 16], 1u);
+    for (uint32_t u = 0; u < kU; ++u) {
+      const uint32_t v = v0 + 1024 * u;
+      w[u] = v < vend ? dv[v] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) {
+      if (v0 + 1024 * u >= vend) break;
+      const uint32_t q[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        atomicAdd(&c[q[k] & 0xffffu], 1u);
+        atomicAdd(&c[q[k] >> 16], 1u);
+      }
     }
   }
   for (uint32_t i = (hi & ~7u) + threadIdx.x; i < hi; i += 1024) atomicAdd(&c[d[i]], 1u);
