@@ -114,7 +114,10 @@ struct phprng_battery {
   Chi2Job *d_jobs = nullptr;
   double *d_chi2 = nullptr;
   unsigned long long *d_total = nullptr;
-  unsigned long long *d_discard = nullptr;  // Fourier categories of phprng_battery_fourier calls
+  unsigned long long *d_discard = nullptr;  // Fourier category replicas of phprng_battery_fourier calls
+  // per-workgroup replicas [kRep][categories] of the small histograms
+  unsigned long long *d_rep = nullptr;
+  unsigned long long *rep[PHPRNG_TEST_COUNT] = {};
   Twiddles tw{};
   double fourier_scale = 0;
   std::vector<Pending> pending;
@@ -220,7 +223,8 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
             hipMalloc(&b->d_jobs, PHPRNG_TEST_COUNT * sizeof(Chi2Job)) == hipSuccess &&
             hipMalloc(&b->d_chi2, PHPRNG_TEST_COUNT * sizeof(double)) == hipSuccess &&
             hipMalloc(&b->d_total, PHPRNG_TEST_COUNT * sizeof(unsigned long long)) == hipSuccess &&
-            hipMalloc(&b->d_discard, kFourierCats * sizeof(unsigned long long)) == hipSuccess;
+            hipMalloc(&b->d_discard, kRep * kFourierCats * sizeof(unsigned long long)) == hipSuccess &&
+            hipMalloc(&b->d_rep, kRep * nprob * sizeof(unsigned long long)) == hipSuccess;
   if (!ok) {
     phprng_battery_destroy(b);
     return PHPRNG_E_NOMEM;
@@ -230,6 +234,10 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
     b->d_cat[t] = b->d_hist + off;
     off += kCats[t];
   }
+  b->rep[PHPRNG_TEST_POKER] = b->d_rep;
+  b->rep[PHPRNG_TEST_COLLISION] = b->d_rep + kRep * kPokerCats;
+  b->rep[PHPRNG_TEST_RUNS] = b->d_rep + kRep * (kPokerCats + kCollCats);
+  b->rep[PHPRNG_TEST_FOURIER] = b->d_rep + kRep * (kPokerCats + kCollCats + kRunsCats);
   // partition space: the frequency and serial tests, 2^15 cells per partition
   std::vector<unsigned long long *> phist;
   std::vector<uint32_t> pncell;
@@ -248,22 +256,24 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
     phprng_battery_destroy(b);
     return PHPRNG_E_INVALID;
   }
-  // bucket room per partition and chunk: the frequency test's share (2^20 keys
-  // per partition for a chunk) with a margin; any surplus goes to atomics
-  const uint32_t cap = (uint32_t)(kChunkBlocks * kBlock / 32 * 5 / 4 + 4096) & ~7u;
+  // bucket room per sub-bucket and chunk: the frequency test's share of a
+  // partition (2^22 keys for a chunk) over the sub-buckets, with a margin;
+  // any surplus goes to atomics
+  const uint32_t nsub = 8;
+  const uint32_t cap = (uint32_t)(kChunkBlocks * kBlock / 32 / nsub * 5 / 4 + 4096) & ~7u;
   const uint32_t nslice = 2;
-  ok = hipMalloc(&b->d_pdata, (uint64_t)npart * cap * sizeof(uint16_t)) == hipSuccess &&
-       hipMalloc(&b->d_pfill, npart * sizeof(uint32_t)) == hipSuccess &&
+  ok = hipMalloc(&b->d_pdata, (uint64_t)npart * nsub * cap * sizeof(uint16_t)) == hipSuccess &&
+       hipMalloc(&b->d_pfill, npart * nsub * sizeof(uint32_t)) == hipSuccess &&
        hipMalloc(&b->d_pncell, npart * sizeof(uint32_t)) == hipSuccess &&
        hipMalloc(&b->d_pslices, (uint64_t)npart * nslice * ph::kPartCells * sizeof(uint32_t)) == hipSuccess &&
        hipMalloc(&b->d_phist, npart * sizeof(unsigned long long *)) == hipSuccess;
   if (!ok || hipMemcpy(b->d_phist, phist.data(), npart * sizeof(void *), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->d_pncell, pncell.data(), npart * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(b->d_pfill, 0, npart * sizeof(uint32_t)) != hipSuccess) {
+      hipMemset(b->d_pfill, 0, npart * nsub * sizeof(uint32_t)) != hipSuccess) {
     phprng_battery_destroy(b);
     return PHPRNG_E_NOMEM;
   }
-  b->parts = ph::PartSet{b->d_pdata, b->d_pfill, b->d_phist, b->d_pncell, b->d_pslices, npart, cap, nslice, 0};
+  b->parts = ph::PartSet{b->d_pdata, b->d_pfill, b->d_phist, b->d_pncell, b->d_pslices, npart, cap, nslice, nsub};
   // roots of unity in extended precision, then rounded
   std::vector<double2> tw(3 * 1024);
   const long double two_pi = 6.283185307179586476925286766559005768L;
@@ -287,7 +297,9 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
   if (hipMemcpy(b->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->d_probs, probs.data(), nprob * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->d_jobs, jobs, sizeof jobs, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(b->d_hist, 0, total * sizeof(unsigned long long)) != hipSuccess) {
+      hipMemset(b->d_hist, 0, total * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(b->d_rep, 0, kRep * nprob * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(b->d_discard, 0, kRep * kFourierCats * sizeof(unsigned long long)) != hipSuccess) {
     phprng_battery_destroy(b);
     return PHPRNG_E_DEVICE;
   }
@@ -303,7 +315,8 @@ phprng_status phprng_battery_destroy(phprng_battery *b) {
   resolve(b, true);
   for (hipEvent_t e : b->free_events) (void)hipEventDestroy(e);
   void *bufs[] = {b->d_hist,  b->d_bits,  b->d_y,      b->d_tw,     b->d_probs,   b->d_jobs,   b->d_chi2,
-                  b->d_total, b->d_discard, b->d_pdata, b->d_pfill, b->d_pncell, b->d_pslices, b->d_phist};
+                  b->d_total, b->d_discard, b->d_pdata, b->d_pfill, b->d_pncell, b->d_pslices, b->d_phist,
+                  b->d_rep};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   delete b;
@@ -317,7 +330,9 @@ phprng_status phprng_battery_reset(phprng_battery *b, void *stream) {
   (void)hipSetDevice(b->device);
   uint64_t total = 0;
   for (int t = 0; t < PHPRNG_TEST_COUNT; ++t) total += kCats[t];
+  const uint64_t nprob = kPokerCats + kCollCats + kRunsCats + kFourierCats;
   hipError_t e = hipMemsetAsync(b->d_hist, 0, total * sizeof(unsigned long long), (hipStream_t)stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_rep, 0, kRep * nprob * sizeof(unsigned long long), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(b, e, "reset");
   resolve(b, true);
   for (int i = 0; i < kKernelClasses; ++i) {
@@ -338,21 +353,28 @@ phprng_status phprng_battery_accumulate(phprng_battery *b, const double *r, uint
     const double *src = r + b0 * kBlock;
     if ((s = timed(b, 0, st, "hist kernel",
                    [&] {
-                     return launch_hist(src, nb, b->parts, b->bparts, b->d_cat[PHPRNG_TEST_POKER], b->d_bits, st);
+                     return launch_hist(src, nb, b->parts, b->bparts, b->rep[PHPRNG_TEST_POKER], b->d_bits, st);
                    })) != PHPRNG_OK ||
         (s = timed(b, 1, st, "collision kernel",
-                   [&] { return launch_collision(src, nb, b->d_cat[PHPRNG_TEST_COLLISION], st); })) != PHPRNG_OK ||
+                   [&] { return launch_collision(src, nb, b->rep[PHPRNG_TEST_COLLISION], st); })) != PHPRNG_OK ||
         (s = timed(b, 2, st, "runs kernel",
-                   [&] { return launch_runs(b->d_bits, nb, b->d_cat[PHPRNG_TEST_RUNS], st); })) != PHPRNG_OK ||
+                   [&] { return launch_runs(b->d_bits, nb, b->rep[PHPRNG_TEST_RUNS], st); })) != PHPRNG_OK ||
         (s = timed(b, 3, st, "fft pass 1", [&] { return launch_fft_pass1(src, nb, b->d_y, b->tw, st); })) != PHPRNG_OK ||
         (s = timed(b, 4, st, "fft pass 2", [&] {
-           return launch_fft_pass2(b->d_y, nb, b->d_cat[PHPRNG_TEST_FOURIER], nullptr, b->tw, b->fourier_scale, st);
+           return launch_fft_pass2(b->d_y, nb, b->rep[PHPRNG_TEST_FOURIER], nullptr, b->tw, b->fourier_scale, st);
          })) != PHPRNG_OK ||
         (s = timed(b, 5, st, "histogram count", [&] {
            hipError_t e = ph::launch_count(b->parts, st);
            return e == hipSuccess ? ph::launch_add(b->parts, st) : e;
          })) != PHPRNG_OK)
       return s;
+  }
+  // the small histograms' replicas into their histograms
+  if (nblocks) {
+    for (int t : {PHPRNG_TEST_POKER, PHPRNG_TEST_COLLISION, PHPRNG_TEST_RUNS, PHPRNG_TEST_FOURIER}) {
+      hipError_t e = launch_fold(b->rep[t], b->d_cat[t], kCats[t], st);
+      if (e != hipSuccess) return hip_fail(b, e, "fold");
+    }
   }
   return PHPRNG_OK;
 }

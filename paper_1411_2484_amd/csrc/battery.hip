@@ -32,19 +32,32 @@ __device__ __forceinline__ uint32_t poker_cat(const uint32_t d[5]) {
 }
 
 // Keys of one test for one tile, held in registers for the partitioned
-// histogram: item j = threadIdx.x + it * kHistThreads is the j-th D-tuple of the tile
-// (D = 1: the j-th uniform), its key the partition-space offset of the test
-// plus its cell (first element most significant).
-template <int D, uint32_t B, int K>
-__device__ __forceinline__ void tuple_keys(const double *t, uint32_t len, uint32_t key0, uint32_t *key) {
+// histogram: item j = threadIdx.x + it * kHistThreads is the j-th D-tuple of
+// the tile (D = 1: the j-th uniform), its key the partition-space offset of
+// the test plus its cell (first element most significant).  The cells come
+// from each uniform's bins, found once per uniform: b20 among 2^20 bins, whose
+// top 10, 5 and 4 bits are the bins among 1024, 32 and 16 (x 2^k is exact, so
+// floor(x 2^k) = floor(x 2^20) >> (20 - k)), and b100 among 100.
+template <int D, int K>
+__device__ __forceinline__ void tuple_keys(const uint32_t *b20, const uint8_t *b100, uint32_t len, uint32_t key0,
+                                           uint32_t *key) {
+  static_assert(kFreqBins == 1u << 20 && kAxis2 == 1024 && kAxis3 == 100 && kAxis4 == 32 && kAxis5 == 16,
+                "bins derived from the 2^20 bin");
   const uint32_t ntup = len / D;
 #pragma unroll
   for (int it = 0; it < K; ++it) {
     const uint32_t j = threadIdx.x + it * kHistThreads;
     uint32_t cell = 0;
     if (j < ntup) {
+      if constexpr (D == 1) {
+        cell = b20[j];
+      } else if constexpr (D == 3) {
+        cell = (b100[3 * j] * 100u + b100[3 * j + 1]) * 100u + b100[3 * j + 2];
+      } else {
+        constexpr int kShift = D == 2 ? 10 : (D == 4 ? 15 : 16), kBits = 20 - kShift;
 #pragma unroll
-      for (int i = 0; i < D; ++i) cell = cell * B + bin_of(t[j * D + i], B);
+        for (int i = 0; i < D; ++i) cell = (cell << kBits) | (b20[j * D + i] >> kShift);
+      }
     }
     key[it] = j < ntup ? key0 + cell : ph::kNoKey;
   }
@@ -61,12 +74,14 @@ constexpr int kKeys = kK1 + kK2 + kK3 + kK4 + kK5;
 // one 64-bit word per 64 uniforms (for the runs test).
 __global__ __launch_bounds__(kHistThreads) void hist_kernel(const double *__restrict__ r, ph::PartSet P, BatteryParts bp,
                                                    unsigned long long *poker_hist, uint64_t *__restrict__ bits) {
-  // the tile of uniforms, later reused as the key staging area of the scatter
+  // the tile's bins (b20 among 2^20, b100 among 100, b10 among 10 for the
+  // poker digits), later reused as the key staging area of the scatter
   __shared__ __align__(16) uint32_t buf[kKeys * kHistThreads];
-  static_assert(kKeys * kHistThreads * 4 >= kHistTile * 8, "staging area must hold the tile");
+  static_assert(kKeys * kHistThreads * 4 >= kHistTile * 6, "staging area must hold the tile's bins");
   __shared__ uint32_t poker[kPokerCats];
   __shared__ uint32_t cnt[kMaxParts], poff[kMaxParts], base[kMaxParts];
-  double *t = reinterpret_cast<double *>(buf);
+  uint32_t *b20 = buf;
+  uint8_t *b100 = reinterpret_cast<uint8_t *>(buf + kHistTile), *b10 = b100 + kHistTile;
   const uint32_t tile = blockIdx.x % kHistTilesPerBlock;
   const uint64_t blk = blockIdx.x / kHistTilesPerBlock;
   const uint32_t off = tile * kHistTile;
@@ -95,7 +110,9 @@ __global__ __launch_bounds__(kHistThreads) void hist_kernel(const double *__rest
   for (uint32_t k = 0; k < kPer; ++k) {
     const uint32_t i = threadIdx.x + kHistThreads * k;
     if (i < len) {
-      t[i] = x[k];
+      b20[i] = bin_of(x[k], kFreqBins);
+      b100[i] = (uint8_t)bin_of(x[k], kAxis3);
+      b10[i] = (uint8_t)bin_of(x[k], 10);
       const uint64_t word = __ballot(x[k] > 0.5);
       if (lane == k) mine = word;
     }
@@ -106,21 +123,21 @@ __global__ __launch_bounds__(kHistThreads) void hist_kernel(const double *__rest
   for (uint32_t j = threadIdx.x; j < nhand; j += kHistThreads) {
     uint32_t d[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) d[i] = bin_of(t[j * 5 + i], 10);
+    for (int i = 0; i < 5; ++i) d[i] = b10[j * 5 + i];
     atomicAdd(&poker[poker_cat(d)], 1u);
   }
   // all five tests' keys of the tile in registers, then one scatter over the
   // partition space (its first barrier orders the last reads of the tile
   // before the staging area is overwritten)
   uint32_t key[kKeys];
-  tuple_keys<1, kFreqBins, kK1>(t, len, bp.p0[0] << ph::kPartBits, key);
-  tuple_keys<2, kAxis2, kK2>(t, len, bp.p0[1] << ph::kPartBits, key + kK1);
-  tuple_keys<3, kAxis3, kK3>(t, len, bp.p0[2] << ph::kPartBits, key + kK1 + kK2);
-  tuple_keys<4, kAxis4, kK4>(t, len, bp.p0[3] << ph::kPartBits, key + kK1 + kK2 + kK3);
-  tuple_keys<5, kAxis5, kK5>(t, len, bp.p0[4] << ph::kPartBits, key + kK1 + kK2 + kK3 + kK4);
+  tuple_keys<1, kK1>(b20, b100, len, bp.p0[0] << ph::kPartBits, key);
+  tuple_keys<2, kK2>(b20, b100, len, bp.p0[1] << ph::kPartBits, key + kK1);
+  tuple_keys<3, kK3>(b20, b100, len, bp.p0[2] << ph::kPartBits, key + kK1 + kK2);
+  tuple_keys<4, kK4>(b20, b100, len, bp.p0[3] << ph::kPartBits, key + kK1 + kK2 + kK3);
+  tuple_keys<5, kK5>(b20, b100, len, bp.p0[4] << ph::kPartBits, key + kK1 + kK2 + kK3 + kK4);
   ph::scatter_staged<kHistThreads, kKeys>(key, P, 0, P.npart, cnt, poff, base, buf);
   if (threadIdx.x < kPokerCats && poker[threadIdx.x])
-    atomicAdd(&poker_hist[threadIdx.x], (unsigned long long)poker[threadIdx.x]);
+    atomicAdd(&poker_hist[(blockIdx.x % kRep) * kPokerCats + threadIdx.x], (unsigned long long)poker[threadIdx.x]);
 }
 
 // One collision trial per workgroup: 2^14 uniforms into 2^20 urns held as a
@@ -150,7 +167,7 @@ __global__ __launch_bounds__(1024) void collision_kernel(const double *__restric
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t c = total < kCollLo ? kCollLo : (total > kCollHi ? kCollHi : total);
-    atomicAdd(&hist[c - kCollLo], 1ull);
+    atomicAdd(&hist[(blockIdx.x % kRep) * kCollCats + (c - kCollLo)], 1ull);
   }
 }
 
@@ -197,7 +214,8 @@ __global__ __launch_bounds__(256) void runs_kernel(const uint64_t *__restrict__ 
     }
   }
   __syncthreads();
-  if (threadIdx.x < kRunsCats && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+  if (threadIdx.x < kRunsCats && h[threadIdx.x])
+    atomicAdd(&hist[(blockIdx.x % kRep) * kRunsCats + threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -268,28 +286,111 @@ __device__ __forceinline__ uint32_t fourier_cat(double v, double scale) {
   return (uint32_t)(int)(c + kFourierHalf + 1);
 }
 
-// Pass-2 LDS: per wave a 16 x 65 transpose area, reused for its row of 1024
-// coefficients in frequency order with one pad slot every 256.
-constexpr int kP2Area = 16 * 65;
-__device__ __forceinline__ uint32_t p2_slot(uint32_t k2) { return k2 + (k2 >> 8); }
-
 // Pass 2: the 1024-point transforms of rows k1 and 512 - k1 (rows 0 and 256
 // pair with themselves), one wave per row, which give F_k for
 // k = k1 + 512 k2 and the partner N - k of each; then the real-input split
 //   E = (F_k + conj F_{N-k}) / 2,  O = (F_k - conj F_{N-k}) / (2i),
 //   X_k = E + w_M^k O,  X_{N-k} = conj(E - w_M^k O),
 // scaled by 1/sqrt(M), and the categories of their real and imaginary parts.
-__global__ __launch_bounds__(128) void fft_pass2_kernel(const double2 *__restrict__ y, unsigned long long *hist,
-                                                        double *__restrict__ coef, Twiddles tw, double scale) {
+// split_and_bin takes A = F_k, B = F_{N-k} and wk = w_M^k.
+__device__ __forceinline__ void split_and_bin(double2 A, double2 B, double2 wk, uint32_t k, double scale,
+                                              uint32_t *h, double *cb) {
+  const double fs = 1.0 / 1024.0;  // 1 / sqrt(M), exact
+  const double ar = A.x, ai = A.y, br = B.x, bi = B.y;
+  const double er = (ar + br) * 0.5, ei = (ai - bi) * 0.5;
+  const double orr = (ai + bi) * 0.5, oi = (br - ar) * 0.5;
+  const double tr = orr * wk.x - oi * wk.y, ti = orr * wk.y + oi * wk.x;
+  const double xr = (er + tr) * fs, xi = (ei + ti) * fs;
+  atomicAdd(&h[fourier_cat(xr, scale)], 1u);
+  atomicAdd(&h[fourier_cat(xi, scale)], 1u);
+  if (cb) {
+    cb[2 * k] = xr;
+    cb[2 * k + 1] = xi;
+  }
+  const uint32_t kp = (kFftN - k) % kFftN;
+  if (kp != k) {  // the partner coefficient, unless it is the same one (k = 0 or N/2)
+    const double pr = (er - tr) * fs, pi = -(ei - ti) * fs;
+    atomicAdd(&h[fourier_cat(pr, scale)], 1u);
+    atomicAdd(&h[fourier_cat(pi, scale)], 1u);
+    if (cb) {
+      cb[2 * kp] = pr;
+      cb[2 * kp + 1] = pi;
+    }
+  }
+}
+
+// Row pairs (k1, 512 - k1) with 1 <= k1 <= 255.  Each wave transforms its row
+// with the split transpose (half the LDS of a complex one, so more
+// workgroups fit on a CU), then the two waves swap half of their
+// coefficients through the same areas.  Lane t holds F[c], c = ka + 16 kb +
+// 256 q (ka = t / 4, q its output index); the mirror index 1023 - c of the
+// other row sits in lane 63 - t of the other wave, register 15 - kb.  Wave 0
+// (row k1) takes the pairs whose row-k1 index has kb < 8, wave 1 the pairs
+// whose row-(512 - k1) index has kb < 8: every pair once.
+constexpr int kP2Half = 16 * 65;  // doubles per wave
+constexpr uint32_t kP2PairRows = kFftN1 / 2 - 1;
+__global__ __launch_bounds__(128) void fft_pass2_pairs_kernel(const double2 *__restrict__ y, unsigned long long *hist,
+                                                              double *__restrict__ coef, Twiddles tw, double scale) {
   constexpr int L = kFftN2;
-  __shared__ double2 buf[2 * kP2Area];
+  __shared__ __align__(16) double buf[2 * kP2Half];
+  static_assert(8 * 64 * 2 <= kP2Half && (kP2Half * 8) % 16 == 0, "swap slots fit the area");
   __shared__ uint32_t h[kFourierCats];
-  const uint64_t blk = blockIdx.x / kFftPass2Groups;
-  const uint32_t ra = blockIdx.x % kFftPass2Groups;  // 0 .. 256
-  const uint32_t rb = (ra == 0 || ra == kFftN1 / 2) ? ra : kFftN1 - ra;
+  const uint64_t blk = blockIdx.x / kP2PairRows;
+  const uint32_t ra = 1 + blockIdx.x % kP2PairRows, rb = kFftN1 - ra;
   const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (threadIdx.x < kFourierCats) h[threadIdx.x] = 0;
   const double2 *row = y + blk * (uint64_t)kFftN + (uint64_t)(w ? rb : ra) * L;
+  double *area = buf + w * kP2Half;
+  double2 v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = row[lane + 64 * m];
+  wf::wave_fft_split<64>(v, area, tw.w1024, lane);
+  // registers 8..15 to the other wave: slot j * 64 + t holds v[8 + j] of lane t
+  double2 *mine = reinterpret_cast<double2 *>(area);
+  wf::wave_lds_fence();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) mine[j * 64 + lane] = v[8 + j];
+  __syncthreads();
+  const double2 *other = reinterpret_cast<const double2 *>(buf + (1 - w) * kP2Half);
+  double *cb = coef ? coef + blk * (uint64_t)kBlock : nullptr;
+  // k = ra + 512 k2: w_M^k = fineM[ra + 512 (k2 & 1)] w_1024^{k2 >> 1}, with
+  // k2 >> 1 = c0 + 8 kb (wave 0) or 511 - c0 - 8 kb (wave 1): one loaded root
+  // and its products with w_1024^{+-8}
+  const uint32_t ka = lane >> 2, q = wf::wave_fft_q<64>(lane);
+  const uint32_t c0 = (ka >> 1) + 128 * q;
+  const double2 fine = tw.fineM[ra + 512 * ((ka & 1) ^ w)];
+  const double2 s8 = tw.w1024[8];
+  const double2 step = w ? make_double2(s8.x, -s8.y) : s8;
+  double2 wc = tw.w1024[w ? 511 - c0 : c0];
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) {
+    const uint32_t cown = ka + 16 * kb + 256 * q;
+    const uint32_t k2 = w ? 1023 - cown : cown;
+    const double2 pv = other[(7 - kb) * 64 + (63 - lane)];
+    // A = row ra at k2, B = row rb at 1023 - k2
+    split_and_bin(w ? pv : v[kb], w ? v[kb] : pv, cmul(fine, wc), ra + kFftN1 * k2, scale, h, cb);
+    wc = cmul(wc, step);
+  }
+  __syncthreads();
+  if (threadIdx.x < kFourierCats && h[threadIdx.x])
+    atomicAdd(&hist[(blockIdx.x % kRep) * kFourierCats + threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+// Rows 0 and 256, each paired with itself: one wave per copy of the row,
+// the coefficients in frequency order in LDS (one pad slot every 256).
+constexpr int kP2Area = 16 * 65;
+__device__ __forceinline__ uint32_t p2_slot(uint32_t k2) { return k2 + (k2 >> 8); }
+
+__global__ __launch_bounds__(128) void fft_pass2_self_kernel(const double2 *__restrict__ y, unsigned long long *hist,
+                                                             double *__restrict__ coef, Twiddles tw, double scale) {
+  constexpr int L = kFftN2;
+  __shared__ double2 buf[2 * kP2Area];
+  __shared__ uint32_t h[kFourierCats];
+  const uint64_t blk = blockIdx.x >> 1;
+  const uint32_t ra = (blockIdx.x & 1) ? kFftN1 / 2 : 0u;
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (threadIdx.x < kFourierCats) h[threadIdx.x] = 0;
+  const double2 *row = y + blk * (uint64_t)kFftN + (uint64_t)ra * L;
   double2 *area = buf + w * kP2Area;
   double2 v[16];
 #pragma unroll
@@ -300,58 +401,32 @@ __global__ __launch_bounds__(128) void fft_pass2_kernel(const double2 *__restric
 #pragma unroll
   for (int kb = 0; kb < 16; ++kb) area[p2_slot(ka + 16 * kb + 256 * q)] = v[kb];
   __syncthreads();
-  const double fs = 1.0 / 1024.0;  // 1 / sqrt(M), exact
   double *cb = coef ? coef + blk * (uint64_t)kBlock : nullptr;
-  // k2 = 0..1023 for a row pair (partner 1023 - k2 in the other row),
-  // 0..512 for row 0 (partner 1024 - k2 in the same row), 0..511 for row 256
-  const uint32_t nk2 = ra == 0 ? 513u : (ra == kFftN1 / 2 ? 512u : 1024u);
-  // k = ra + 512 k2 with ra < 512: k mod 1024 is ra or ra + 512 (two fine
-  // roots per workgroup) and k >> 10 = k2 >> 1
+  // row 0: k2 = 0..512 with partner 1024 - k2; row 256: k2 = 0..511 with
+  // partner 1023 - k2 (in the second wave's copy of the row)
+  const uint32_t nk2 = ra == 0 ? 513u : 512u;
   const double2 fine0 = tw.fineM[ra], fine1 = tw.fineM[ra + 512];
-  // w_1024^{k2 >> 1} with k2 >> 1 = (tid >> 1) + 64 it: one loaded root times
-  // the exact 16th root w_16^it
-  const double2 coarse0 = tw.w1024[threadIdx.x >> 1];
-#pragma unroll
-  for (uint32_t it = 0; it < (1024 + 127) / 128 + 1; ++it) {
-    const uint32_t k2 = threadIdx.x + 128 * it;
-    if (k2 >= nk2) break;
-    uint32_t k, kp, pa, pb;
-    if (ra == 0) {
-      k = kFftN1 * k2;
-      kp = (kFftN - k) % kFftN;
-      pa = p2_slot(k2);
-      pb = p2_slot((1024 - k2) & 1023);
-    } else {
-      k = ra + kFftN1 * k2;
-      kp = kFftN - k;
-      pa = p2_slot(k2);
-      pb = kP2Area + p2_slot(1023 - k2);  // row rb in the second wave's area (row 256: the same row)
-    }
-    const double2 A = buf[pa], B = buf[pb];
-    const double ar = A.x, ai = A.y, br = B.x, bi = B.y;
-    const double er = (ar + br) * 0.5, ei = (ai - bi) * 0.5;
-    const double orr = (ai + bi) * 0.5, oi = (br - ar) * 0.5;
-    const double2 wk = cmul((k2 & 1) ? fine1 : fine0, cmul(coarse0, wf::w16((int)it)));
-    const double tr = orr * wk.x - oi * wk.y, ti = orr * wk.y + oi * wk.x;
-    const double xr = (er + tr) * fs, xi = (ei + ti) * fs;
-    atomicAdd(&h[fourier_cat(xr, scale)], 1u);
-    atomicAdd(&h[fourier_cat(xi, scale)], 1u);
-    if (cb) {
-      cb[2 * k] = xr;
-      cb[2 * k + 1] = xi;
-    }
-    if (kp != k) {  // the partner coefficient, unless it is the same one (k = 0 or N/2)
-      const double pr = (er - tr) * fs, pi = -(ei - ti) * fs;
-      atomicAdd(&h[fourier_cat(pr, scale)], 1u);
-      atomicAdd(&h[fourier_cat(pi, scale)], 1u);
-      if (cb) {
-        cb[2 * kp] = pr;
-        cb[2 * kp + 1] = pi;
-      }
-    }
+  for (uint32_t k2 = threadIdx.x; k2 < nk2; k2 += 128) {
+    const uint32_t pa = p2_slot(k2);
+    const uint32_t pb = ra == 0 ? p2_slot((1024 - k2) & 1023) : kP2Area + p2_slot(1023 - k2);
+    const double2 wk = cmul((k2 & 1) ? fine1 : fine0, tw.w1024[k2 >> 1]);
+    split_and_bin(buf[pa], buf[pb], wk, ra + kFftN1 * k2, scale, h, cb);
   }
   __syncthreads();
-  if (threadIdx.x < kFourierCats && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+  if (threadIdx.x < kFourierCats && h[threadIdx.x])
+    atomicAdd(&hist[(blockIdx.x % kRep) * kFourierCats + threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+// dst[c] += sum of the kRep replicas of bin c, which are cleared.
+__global__ __launch_bounds__(256) void fold_kernel(unsigned long long *rep, unsigned long long *dst, uint32_t ncat) {
+  const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncat) return;
+  unsigned long long s = 0;
+  for (uint32_t r = 0; r < kRep; ++r) {
+    s += rep[(uint64_t)r * ncat + c];
+    rep[(uint64_t)r * ncat + c] = 0;
+  }
+  if (s) dst[c] += s;
 }
 
 // One workgroup per test: the total count, then sum (O - E)^2 / E with
@@ -430,7 +505,13 @@ hipError_t launch_fft_pass1(const double *r, uint64_t nblocks, double2 *y, Twidd
 
 hipError_t launch_fft_pass2(const double2 *y, uint64_t nblocks, unsigned long long *fourier, double *coef,
                             Twiddles tw, double scale, hipStream_t st) {
-  fft_pass2_kernel<<<dim3((unsigned)(nblocks * kFftPass2Groups)), dim3(128), 0, st>>>(y, fourier, coef, tw, scale);
+  fft_pass2_pairs_kernel<<<dim3((unsigned)(nblocks * kP2PairRows)), dim3(128), 0, st>>>(y, fourier, coef, tw, scale);
+  fft_pass2_self_kernel<<<dim3((unsigned)(nblocks * 2)), dim3(128), 0, st>>>(y, fourier, coef, tw, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold(unsigned long long *rep, unsigned long long *dst, uint32_t ncat, hipStream_t st) {
+  fold_kernel<<<dim3((ncat + 255) / 256), dim3(256), 0, st>>>(rep, dst, ncat);
   return hipGetLastError();
 }
 

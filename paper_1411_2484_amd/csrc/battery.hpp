@@ -40,7 +40,6 @@ constexpr uint32_t kHistTilesPerBlock = (kBlock + kHistTile - 1) / kHistTile;
 constexpr uint32_t kFftN = kBlock / 2, kFftN1 = 512, kFftN2 = 1024;
 constexpr uint32_t kFftCols = 8;                           // pass-1 columns per workgroup
 constexpr uint32_t kFftPass1Groups = kFftN2 / kFftCols;   // workgroups per block, pass 1
-constexpr uint32_t kFftPass2Groups = kFftN1 / 2 + 1;      // row pairs per block, pass 2
 
 // The frequency and serial tests go through partitioned histograms: test t
 // owns the partitions from p0[t] on in one partition space.
@@ -64,14 +63,22 @@ struct Chi2Job {
   uint32_t pad;
 };
 
+// The small histograms (poker, collision, runs, Fourier categories) take a
+// count from every workgroup.  Global atomics on the same address serialise
+// (about 5e7 per second per address, measured), so a workgroup adds into
+// replica blockIdx.x % kRep of the histogram, an array [kRep][categories]
+// that launch_fold sums into the histogram (and clears).
+constexpr uint32_t kRep = 256;
+
 hipError_t launch_hist(const double *r, uint64_t nblocks, const ph::PartSet &P, const BatteryParts &bp,
-                       unsigned long long *poker, uint64_t *bits, hipStream_t st);
-hipError_t launch_collision(const double *r, uint64_t nblocks, unsigned long long *coll, hipStream_t st);
-hipError_t launch_runs(const uint64_t *bits, uint64_t nblocks, unsigned long long *runs, hipStream_t st);
+                       unsigned long long *poker_rep, uint64_t *bits, hipStream_t st);
+hipError_t launch_collision(const double *r, uint64_t nblocks, unsigned long long *coll_rep, hipStream_t st);
+hipError_t launch_runs(const uint64_t *bits, uint64_t nblocks, unsigned long long *runs_rep, hipStream_t st);
 hipError_t launch_fft_pass1(const double *r, uint64_t nblocks, double2 *y, Twiddles tw, hipStream_t st);
 // coef (may be null): per block, M doubles = (Re, Im) of coefficients 0 .. M/2 - 1.
-hipError_t launch_fft_pass2(const double2 *y, uint64_t nblocks, unsigned long long *fourier, double *coef,
+hipError_t launch_fft_pass2(const double2 *y, uint64_t nblocks, unsigned long long *fourier_rep, double *coef,
                             Twiddles tw, double scale, hipStream_t st);
+hipError_t launch_fold(unsigned long long *rep, unsigned long long *dst, uint32_t ncat, hipStream_t st);
 hipError_t launch_chi2(const Chi2Job *jobs, int njobs, double *chi2, unsigned long long *total, hipStream_t st);
 hipError_t launch_interleave(const double *in, double *out, uint64_t nstreams, uint64_t length, hipStream_t st);
 

@@ -242,13 +242,16 @@ phprng_status phprng_pattern_histogram(const phprng_pattern *P, uint64_t *hist, 
   const uint64_t round_keys = fp_per_round * s_step;
   const uint32_t npart = (uint32_t)((ncell + ph::kPartCells - 1) / ph::kPartCells);
   const uint32_t nslice = std::max<uint32_t>(1, 512 / npart);
-  // bucket room: the expected share of a full partition plus a margin (any
-  // surplus is added with atomics)
+  const uint32_t nsub = 8;
+  // bucket room: the expected share of a full partition over its sub-buckets
+  // plus a margin (any surplus is added with atomics)
   const uint64_t share = (round_keys * std::min<uint64_t>(ph::kPartCells, ncell) + ncell - 1) / ncell;
-  const uint32_t cap = (uint32_t)std::min<uint64_t>(share + share / 4 + 4096, 0xfffffff0ull) & ~7u;
-  const uint64_t bytes_data = ((uint64_t)npart * cap * 2 + 255) / 256 * 256;
+  const uint64_t sub_share = (share + nsub - 1) / nsub;
+  const uint32_t cap = (uint32_t)std::min<uint64_t>(sub_share + sub_share / 4 + 4096, 0xfffffff0ull) & ~7u;
+  const uint64_t bytes_data = ((uint64_t)npart * nsub * cap * 2 + 255) / 256 * 256;
   const uint64_t bytes_slices = (uint64_t)npart * nslice * ph::kPartCells * 4;
-  const uint64_t bytes = bytes_data + bytes_slices + npart * 16;
+  // table: hist pointers[npart] | fill[npart][nsub] | ncell[npart]
+  const uint64_t bytes = bytes_data + bytes_slices + (uint64_t)npart * (8 + 4 * nsub + 4);
   hipStream_t s = (hipStream_t)stream;
   void *mem = nullptr;
   if (hipMallocAsync(&mem, bytes, s) != hipSuccess) return PHPRNG_E_NOMEM;
@@ -256,21 +259,21 @@ phprng_status phprng_pattern_histogram(const phprng_pattern *P, uint64_t *hist, 
   ph::PartSet PS;
   PS.data = (uint16_t *)cm;
   PS.slices = (uint32_t *)(cm + bytes_data);
-  PS.fill = (uint32_t *)(cm + bytes_data + bytes_slices);
-  uint32_t *ncell_d = PS.fill + npart;
-  // pointer table after fill[npart] and ncell[npart]: 8 npart bytes past a
-  // 256-byte aligned base, so 8-byte aligned
-  unsigned long long **hist_d = (unsigned long long **)(PS.fill + 2 * npart);
+  // the pointer table first, at a 256-byte aligned offset
+  unsigned long long **hist_d = (unsigned long long **)(cm + bytes_data + bytes_slices);
+  PS.fill = (uint32_t *)(hist_d + npart);
+  uint32_t *ncell_d = PS.fill + (uint64_t)npart * nsub;
   PS.ncell = ncell_d;
   PS.hist = hist_d;
   PS.npart = npart;
   PS.cap = cap;
   PS.nslice = nslice;
-  PS.pad = 0;
-  std::vector<uint32_t> tab32(2 * npart, 0);  // fill = 0 | ncell
+  PS.nsub = nsub;
+  std::vector<uint32_t> tab32((uint64_t)npart * (nsub + 1), 0);  // fill = 0 | ncell
   std::vector<unsigned long long *> tabp(npart);
   for (uint32_t q = 0; q < npart; ++q) {
-    tab32[npart + q] = (uint32_t)std::min<uint64_t>(ph::kPartCells, ncell - (uint64_t)q * ph::kPartCells);
+    tab32[(uint64_t)npart * nsub + q] =
+        (uint32_t)std::min<uint64_t>(ph::kPartCells, ncell - (uint64_t)q * ph::kPartCells);
     tabp[q] = reinterpret_cast<unsigned long long *>(hist) + (uint64_t)q * ph::kPartCells;
   }
   hipError_t e = hipMemcpyAsync(PS.fill, tab32.data(), tab32.size() * 4, hipMemcpyHostToDevice, s);

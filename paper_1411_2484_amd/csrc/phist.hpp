@@ -9,8 +9,12 @@
 //      offsets in a 128 KB LDS histogram and stores the counts;
 //   3. add: the per-slice counts are summed into the uint64 histogram and the
 //      bucket fill counters are cleared for the next round.
-// A bucket that runs full sends its surplus keys straight to the histogram
-// with global atomics, so the result is exact for any key distribution.
+// Atomics on one address serialise (about 5e7 per second), and every
+// workgroup reserves in every partition, so each partition's bucket is split
+// into nsub sub-buckets with fill counters of their own, and a workgroup
+// reserves in sub-bucket blockIdx.x % nsub.  A sub-bucket that runs full
+// sends its surplus keys straight to the histogram with global atomics, so
+// the result is exact for any key distribution.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,12 +29,12 @@ constexpr uint32_t kPartCells = 1u << kPartBits;
 constexpr uint32_t kNoKey = 0xffffffffu;
 
 struct PartSet {
-  uint16_t *data;                     // [npart][cap] cell offsets (16-byte aligned, cap a multiple of 8)
-  uint32_t *fill;                     // [npart] entries written this round
+  uint16_t *data;                     // [npart][nsub][cap] cell offsets (16-byte aligned, cap a multiple of 8)
+  uint32_t *fill;                     // [npart][nsub] entries written this round
   unsigned long long *const *hist;    // [npart] first cell of each partition in its histogram
   const uint32_t *ncell;              // [npart] cells of each partition (<= 2^15)
   uint32_t *slices;                   // [npart][nslice][2^15] stage-2 counts
-  uint32_t npart, cap, nslice, pad;
+  uint32_t npart, cap, nslice, nsub;  // cap: entries per sub-bucket; nsub a power of two <= 256
 };
 
 // Stage 1 for keys held in registers: key[it] of thread t is item t + it * NT;
@@ -53,9 +57,10 @@ __device__ __forceinline__ void scatter_staged(const uint32_t (&key)[K], const P
   // global atomics), and the exclusive scan of the counts by the first wave
   // (up to 8 per lane)
   __shared__ uint32_t total;
+  const uint32_t sub = blockIdx.x & (P.nsub - 1);
   for (uint32_t i = threadIdx.x; i < np; i += NT) {
     const uint32_t c = cnt[i];
-    base[i] = c ? atomicAdd(&P.fill[p0 + i], c) : 0u;
+    base[i] = c ? atomicAdd(&P.fill[(p0 + i) * P.nsub + sub], c) : 0u;
   }
   if (threadIdx.x < 64) {
     const uint32_t lane = threadIdx.x;
@@ -92,7 +97,7 @@ __device__ __forceinline__ void scatter_staged(const uint32_t (&key)[K], const P
     const uint32_t o = k & (kPartCells - 1);
     const uint32_t j = base[q] + (i - off[q]);
     if (j < P.cap)
-      P.data[(uint64_t)(p0 + q) * P.cap + j] = (uint16_t)o;
+      P.data[((uint64_t)(p0 + q) * P.nsub + sub) * P.cap + j] = (uint16_t)o;
     else
       atomicAdd(&P.hist[p0 + q][o], 1ull);
   }

@@ -101,16 +101,14 @@ __device__ __forceinline__ double2 dpp_c(double2 a) {
   return make_double2(dpp_d<CTRL>(a.x), dpp_d<CTRL>(a.y));
 }
 
-// The transform of N = 16 P points held by the P lanes [base, base + P) of a
-// wave (lane l = threadIdx.x % 64 - base): on entry v[m] = x[l + P m]; on exit
-// v[k_b1] = X[k_a + 16 k_b1 + 256 q] for lane t = l with k_a = t / R and q the
-// lane's output index in its group (q = t % 2 for R = 2; for R = 4 the two
-// bits of t % 4 swapped).  lds: this lane group's area of 16 (P + 1) double2.
-// w1024[j] = exp(2 pi i j / 1024).
+// Steps 1 and 3-4 of the wave transform below (the parts outside the
+// transpose).  wave_before: the 16-point transform over m and the products
+// w_N^{l k_a}.  wave_after: for lane t = (k_a, l_a), the 16-point transform
+// over l_b, the products w_P^{l_a k_b1}, and the R-point transform across the
+// lanes of the k_a group.
 template <int P>
-__device__ __forceinline__ void wave_fft(double2 (&v)[16], double2 *lds, const double2 *__restrict__ w1024,
-                                         uint32_t l) {
-  constexpr int N = 16 * P, R = P / 16, S = P + 1;
+__device__ __forceinline__ void wave_before(double2 (&v)[16], const double2 *__restrict__ w1024, uint32_t l) {
+  constexpr int N = 16 * P;
   static_assert(P == 32 || P == 64, "wave transform sizes");
   dft16(v);
   // w_N^{l ka} as powers of one loaded root (15 products, no further loads)
@@ -121,15 +119,11 @@ __device__ __forceinline__ void wave_fft(double2 (&v)[16], double2 *lds, const d
     v[ka] = cmulw(v[ka], wk);
     wk = cmulw(wk, wl);
   }
-  // transpose: row k_a, column l
-#pragma unroll
-  for (int ka = 0; ka < 16; ++ka) lds[ka * S + l] = v[ka];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const uint32_t ka = l / R, la = l % R;
-#pragma unroll
-  for (int lb = 0; lb < 16; ++lb) v[lb] = lds[ka * S + la + R * lb];
+}
+
+template <int P>
+__device__ __forceinline__ void wave_after(double2 (&v)[16], const double2 *__restrict__ w1024, uint32_t la) {
+  constexpr int R = P / 16;
   dft16(v);
   const double2 wa = w1024[la * (1024 / P)];
   double2 wb = wa;
@@ -160,6 +154,58 @@ __device__ __forceinline__ void wave_fft(double2 (&v)[16], double2 *lds, const d
       v[kb] = a0 ? csub(o2, d) : cadd(d, o2);
     }
   }
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The transform of N = 16 P points held by the P lanes [base, base + P) of a
+// wave (lane l = threadIdx.x % 64 - base): on entry v[m] = x[l + P m]; on exit
+// v[k_b1] = X[k_a + 16 k_b1 + 256 q] for lane t = l with k_a = t / R and q the
+// lane's output index in its group (q = t % 2 for R = 2; for R = 4 the two
+// bits of t % 4 swapped).  lds: this lane group's area of 16 (P + 1) double2.
+// w1024[j] = exp(2 pi i j / 1024).
+template <int P>
+__device__ __forceinline__ void wave_fft(double2 (&v)[16], double2 *lds, const double2 *__restrict__ w1024,
+                                         uint32_t l) {
+  constexpr int R = P / 16, S = P + 1;
+  wave_before<P>(v, w1024, l);
+  // transpose: row k_a, column l
+#pragma unroll
+  for (int ka = 0; ka < 16; ++ka) lds[ka * S + l] = v[ka];
+  wave_lds_fence();
+  const uint32_t ka = l / R, la = l % R;
+#pragma unroll
+  for (int lb = 0; lb < 16; ++lb) v[lb] = lds[ka * S + la + R * lb];
+  wave_after<P>(v, w1024, la);
+}
+
+// wave_fft with the transpose taken in two rounds through an area of doubles,
+// real parts then imaginary parts: half the LDS, and no more live registers
+// (the real parts of v are dead once written; the imaginary parts are read
+// in their own round).  lds: this lane group's area of 16 (P + 1) doubles.
+template <int P>
+__device__ __forceinline__ void wave_fft_split(double2 (&v)[16], double *lds, const double2 *__restrict__ w1024,
+                                               uint32_t l) {
+  constexpr int R = P / 16, S = P + 1;
+  wave_before<P>(v, w1024, l);
+  const uint32_t ka = l / R, la = l % R;
+  double re[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) lds[k * S + l] = v[k].x;
+  wave_lds_fence();
+#pragma unroll
+  for (int lb = 0; lb < 16; ++lb) re[lb] = lds[ka * S + la + R * lb];
+  wave_lds_fence();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) lds[k * S + l] = v[k].y;
+  wave_lds_fence();
+#pragma unroll
+  for (int lb = 0; lb < 16; ++lb) v[lb] = make_double2(re[lb], lds[ka * S + la + R * lb]);
+  wave_after<P>(v, w1024, la);
 }
 
 // Output index q of lane t within its group (see wave_fft).
