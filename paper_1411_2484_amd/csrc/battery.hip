@@ -19,6 +19,12 @@ __device__ __forceinline__ uint32_t bin_of(double x, uint32_t b) {
   return u < b ? u : b - 1;
 }
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+  const uint32_t lo = __shfl_xor((int)(uint32_t)v, mask, 64);
+  const uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Poker hand category from the number of equal pairs among the five digits:
 // 0 all different, 1 one pair, 2 two pairs, 3 three of a kind, 4 full house,
 // 6 four of a kind, 10 five of a kind.
@@ -182,6 +188,11 @@ __global__ __launch_bounds__(256) void runs_kernel(const uint64_t *__restrict__ 
   if (threadIdx.x < kRunsCats) h[threadIdx.x] = 0;
   __syncthreads();
   const uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  // Runs of length 1..8 (all but 0.4% of them) are counted in registers, four
+  // 16-bit fields per word (lengths 1-4 in lo4, 5-8 in hi4; at most 64 runs
+  // start in a word, and a wave's sums stay below 2^16); longer runs go to the
+  // LDS histogram.  An LDS atomic per run queued on the few short-run bins.
+  uint64_t lo4 = 0, hi4 = 0;
   if (w < nwords) {
     const uint32_t wi = (uint32_t)(w & (kWordsPerBlock - 1));
     const uint64_t word = bits[w];
@@ -210,7 +221,25 @@ __global__ __launch_bounds__(256) void runs_kernel(const uint64_t *__restrict__ 
         }
         if (!found) break;
       }
-      atomicAdd(&h[(len < kRunsCats ? len : kRunsCats) - 1], 1u);
+      if (len <= 4)
+        lo4 += 1ull << (16 * (len - 1));
+      else if (len <= 8)
+        hi4 += 1ull << (16 * (len - 5));
+      else
+        atomicAdd(&h[(len < kRunsCats ? len : kRunsCats) - 1], 1u);
+    }
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    lo4 += shfl_xor_u64(lo4, d);
+    hi4 += shfl_xor_u64(hi4, d);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint32_t a = (uint32_t)(lo4 >> (16 * b)) & 0xffffu, c = (uint32_t)(hi4 >> (16 * b)) & 0xffffu;
+      if (a) atomicAdd(&h[b], a);
+      if (c) atomicAdd(&h[4 + b], c);
     }
   }
   __syncthreads();
