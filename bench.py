@@ -517,7 +517,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU share of the generator "
+        print("bench.py runs on one GPU only: it measures the single-GPU share of the generator "
               "(instances shard across GPUs with no communication); --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
