@@ -262,6 +262,8 @@ phprng_status phprng_battery_create(phprng_battery **out, int device) {
   const uint32_t nsub = 8;
   const uint32_t cap = (uint32_t)(kChunkBlocks * kBlock / 32 / nsub * 5 / 4 + 4096) & ~7u;
   const uint32_t nslice = 2;
+  static_assert((uint64_t)kMaxParts * 8 * ((kChunkBlocks * kBlock / 32 / 8 * 5 / 4 + 4096) & ~7u) < (1ull << 32),
+                "32-bit bucket indexing");
   ok = hipMalloc(&b->d_pdata, (uint64_t)npart * nsub * cap * sizeof(uint16_t)) == hipSuccess &&
        hipMalloc(&b->d_pfill, npart * nsub * sizeof(uint32_t)) == hipSuccess &&
        hipMalloc(&b->d_pncell, npart * sizeof(uint32_t)) == hipSuccess &&

@@ -248,6 +248,7 @@ phprng_status phprng_pattern_histogram(const phprng_pattern *P, uint64_t *hist, 
   const uint64_t share = (round_keys * std::min<uint64_t>(ph::kPartCells, ncell) + ncell - 1) / ncell;
   const uint64_t sub_share = (share + nsub - 1) / nsub;
   const uint32_t cap = (uint32_t)std::min<uint64_t>(sub_share + sub_share / 4 + 4096, 0xfffffff0ull) & ~7u;
+  if ((uint64_t)npart * nsub * cap >= (1ull << 32)) return PHPRNG_E_RANGE;  // 32-bit bucket indexing
   const uint64_t bytes_data = ((uint64_t)npart * nsub * cap * 2 + 255) / 256 * 256;
   const uint64_t bytes_slices = (uint64_t)npart * nslice * ph::kPartCells * 4;
   // table: hist pointers[npart] | fill[npart][nsub] | ncell[npart]

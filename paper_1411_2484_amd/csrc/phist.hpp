@@ -28,6 +28,7 @@ constexpr int kPartBits = 15;
 constexpr uint32_t kPartCells = 1u << kPartBits;
 constexpr uint32_t kNoKey = 0xffffffffu;
 
+// npart * nsub * cap < 2^32: the scatter indexes the data with 32 bits.
 struct PartSet {
   uint16_t *data;                     // [npart][nsub][cap] cell offsets (16-byte aligned, cap a multiple of 8)
   uint32_t *fill;                     // [npart][nsub] entries written this round
@@ -89,15 +90,23 @@ __device__ __forceinline__ void scatter_staged(const uint32_t (&key)[K], const P
 #pragma unroll
   for (int it = 0; it < K; ++it)
     if (key[it] != kNoKey) stage[off[(key[it] >> kPartBits) - p0] + rank[it]] = key[it];
+  // meanwhile, per partition: base becomes the data index of the staged key
+  // at position 0 (index = base + staged position, modulo 2^32), and cnt the
+  // staged position where the keys that do not fit the sub-bucket begin
+  for (uint32_t i = threadIdx.x; i < np; i += NT) {
+    const uint32_t b = base[i], o = off[i], c = cnt[i];
+    const uint32_t room = P.cap > b ? P.cap - b : 0u;
+    base[i] = ((p0 + i) * P.nsub + sub) * P.cap + b - o;
+    cnt[i] = o + (c < room ? c : room);
+  }
   __syncthreads();
   const uint32_t n = total;
   for (uint32_t i = threadIdx.x; i < n; i += NT) {
     const uint32_t k = stage[i];
     const uint32_t q = (k >> kPartBits) - p0;
     const uint32_t o = k & (kPartCells - 1);
-    const uint32_t j = base[q] + (i - off[q]);
-    if (j < P.cap)
-      P.data[((uint64_t)(p0 + q) * P.nsub + sub) * P.cap + j] = (uint16_t)o;
+    if (i < cnt[q])
+      P.data[base[q] + i] = (uint16_t)o;
     else
       atomicAdd(&P.hist[p0 + q][o], 1ull);
   }
