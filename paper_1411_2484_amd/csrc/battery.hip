@@ -69,16 +69,16 @@ __device__ __forceinline__ void tuple_keys(const uint32_t *b20, const uint8_t *b
   }
 }
 
-// Registers per thread for the keys of one tile: 15 + 8 + 5 + 4 + 3.
+// Registers per thread for the keys of one tile: 8 + 4 + 3 + 2 + 2.
 constexpr int kT = (int)kHistThreads;
-constexpr int kK1 = kHistTile / kT, kK2 = (kHistTile / 2 + kT - 1) / kT, kK3 = (kHistTile / 3 + kT - 1) / kT;
+constexpr int kK1 = (kHistTile + kT - 1) / kT, kK2 = (kHistTile / 2 + kT - 1) / kT, kK3 = (kHistTile / 3 + kT - 1) / kT;
 constexpr int kK4 = (kHistTile / 4 + kT - 1) / kT, kK5 = (kHistTile / 5 + kT - 1) / kT;
 constexpr int kKeys = kK1 + kK2 + kK3 + kK4 + kK5;
 
 // One tile of one block: frequency and serial D = 2..5 keys into the
 // partitioned histograms, the poker histogram, and the bits R > 1/2 packed
 // one 64-bit word per 64 uniforms (for the runs test).
-__global__ __launch_bounds__(kHistThreads) void hist_kernel(const double *__restrict__ r, ph::PartSet P, BatteryParts bp,
+__global__ __launch_bounds__(kHistThreads, 8) void hist_kernel(const double *__restrict__ r, ph::PartSet P, BatteryParts bp,
                                                    unsigned long long *poker_hist, uint64_t *__restrict__ bits) {
   // the tile's bins (b20 among 2^20, b100 among 100, b10 among 10 for the
   // poker digits), later reused as the key staging area of the scatter
@@ -95,12 +95,11 @@ __global__ __launch_bounds__(kHistThreads) void hist_kernel(const double *__rest
   const uint64_t base_i = blk * kBlock + off;
   if (threadIdx.x < kPokerCats) poker[threadIdx.x] = 0;
   // all of the thread's loads in flight at once (a loop that waits for each
-  // load before the next pays the memory latency 15 times), then the LDS copy
-  // and the run bits; len is a multiple of the workgroup size, so the bounds
-  // test is uniform and every wave covers 64 consecutive uniforms per step
-  constexpr uint32_t kPer = kHistTile / kHistThreads;
-  static_assert(kHistTile % kHistThreads == 0 && (kBlock % kHistTile) % kHistThreads == 0,
-                "whole steps of the workgroup");
+  // load before the next pays the memory latency every step), then the LDS
+  // copy and the run bits; len is a multiple of 64, so the bounds test is
+  // uniform over a wave and every wave covers 64 consecutive uniforms per step
+  constexpr uint32_t kPer = (kHistTile + kHistThreads - 1) / kHistThreads;
+  static_assert(kHistTile % 64 == 0 && (kBlock % kHistTile) % 64 == 0, "whole wave steps");
   double x[kPer];
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {

@@ -27,11 +27,13 @@ constexpr int kFourierHalf = 32;
 constexpr uint32_t kFourierCats = 2 * kFourierHalf + 2;
 constexpr uint32_t kWordsPerBlock = kBlock / 64;
 
-// Histogram tile: 7680 = 120 * 64 uniforms for a workgroup of 512 threads, a
-// multiple of every tuple length (2..5) and of the workgroup; a block is 136
-// full tiles and a 4096-uniform tail.  Every tile reserves bucket room once
-// per partition with a global atomic, so a larger tile means fewer of them.
-constexpr uint32_t kHistThreads = 512;
+// Histogram tile: 7680 = 120 * 64 uniforms for a workgroup of 1024 threads,
+// a multiple of every tuple length (2..5) and of the wave width; a block is
+// 136 full tiles and a 4096-uniform tail.  Every tile reserves bucket room
+// once per partition with a global atomic, so a larger tile means fewer of
+// them; 1024 threads keep the registers per thread low enough for two
+// workgroups per CU.
+constexpr uint32_t kHistThreads = 1024;
 constexpr uint32_t kHistTile = 7680;
 constexpr uint32_t kHistTilesPerBlock = (kBlock + kHistTile - 1) / kHistTile;
 
