@@ -93,6 +93,7 @@ def cpu_baseline(e_arr, n_arr, target_s=12.0):
             break
     draws = done_inst * PER
     return {"value": draws / el / 1e9, "unit": "Guniforms/s", "cores": nthreads, "kind": "oracle",
+            "ns_per_uniform_per_core": el * nthreads / draws * 1e9,
             "sample": "%d instance-streams of the headline workload (2^18 draws each from position 0, "
                       "%d draws) in %.1f s" % (done_inst, draws, el)}
 
