@@ -221,7 +221,8 @@ def workload_e(args, torch, ph):
     ctx.seed_instances(32, 0x14112484 + 5, n32, (9, 17), 0, 1 << 40)
     ctx.seed_instances(64, 0x14112484 + 6, n64, (9, 17), 0, 1 << 32)
     log("serve: %d instances seeded in %.1f s" % (n32 + n64, time.perf_counter() - t0))
-    srv = ph.Server(ctx, arena_doubles=args.serve_arena, streams=2)
+    srv = ph.Server(ctx, arena_doubles=args.serve_arena, streams=args.serve_streams,
+                    max_inflight=args.serve_inflight)
     rng = np.random.default_rng(0x14112484 + 7)
     points = []
     for lam in args.serve_rates:
@@ -240,7 +241,10 @@ def workload_e(args, torch, ph):
               "offered_guniforms_s": float(draws / (arr["t_ns"][-1] * 1e-9) / 1e9), "wall_s": wall,
               "batches": cnt["batches"], "requests_per_batch": cnt["requests"] / max(cnt["batches"], 1),
               "launch_us_mean": cnt["launch_ns"] / max(cnt["batches"], 1) / 1e3,
-              "launch_us_max": cnt["launch_ns_max"] / 1e3, "arena_stalls": cnt["arena_stalls"],
+              "launch_us_max": cnt["launch_ns_max"] / 1e3,
+              "form_us_mean": cnt["admit_ns"] / max(cnt["batches"], 1) / 1e3,
+              "retire_us_mean": cnt["retire_ns"] / max(cnt["batches"], 1) / 1e3,
+              "arena_stalls": cnt["arena_stalls"],
               "arena_peak": cnt["arena_peak"]}
         log("serve: %s" % pt)
         points.append(pt)
@@ -249,7 +253,8 @@ def workload_e(args, torch, ph):
     best = max(points, key=lambda p: p["uniforms_per_s"])
     return common_line(best["uniforms_per_s"], "Guniforms/s", len(points), 0, None,
                        {"workload": "serving: %d resident instances (90%% 32-bit, 10%% 64-bit), Poisson arrivals, "
-                                    "log-uniform 2^8..2^20 FP64 uniforms per request" % (n32 + n64)},
+                                    "log-uniform 2^8..2^20 FP64 uniforms per request" % (n32 + n64),
+                        "streams": args.serve_streams, "inflight": args.serve_inflight or min(args.serve_streams + 1, 6)},
                        serve=points)
 
 
@@ -513,6 +518,9 @@ def main():
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[1e3, 3e3, 1e4, 3e4, 1e5, 3e5, 1e6, 3e6])
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--serve-max-requests", type=int, default=200000)
+    ap.add_argument("--serve-streams", type=int, default=2, help="streams of the server")
+    ap.add_argument("--serve-inflight", type=int, default=0,
+                    help="batches in flight (0: the server's default, streams + 1)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="first run one device copy of this many GiB (known-size kernel for traffic counters)")
     args = ap.parse_args()

@@ -248,7 +248,10 @@ phprng_status phprng_timing_read(phprng_ctx *ctx, double *total_ms, uint64_t *ca
  * depends only on its instance and the position range reserved for it, not
  * on what else is in its batch.  While a server exists, only the server may
  * use `ctx`.  Zero fields take defaults (arena 2^28 uniforms, 2 streams,
- * max_inflight = streams, 8192 requests / 2^28 draws per batch). */
+ * max_inflight = streams + 1 but at most 6, 8192 requests / 2^28 draws per
+ * batch).  More batches in flight than streams queue a formed batch behind a
+ * running one, so that the device does not idle while the host forms the
+ * next batch. */
 typedef struct phprng_server phprng_server;
 
 typedef struct {
@@ -293,7 +296,10 @@ phprng_status phprng_server_stats(phprng_server *server, uint64_t *pending, uint
  * (position reservation, planning inputs, kernel launches), summed and the
  * longest single launch; how often a batch was cut short because the arena
  * had no room for the next request, and the most arena elements in use at
- * a launch.  reset != 0 clears them after the read. */
+ * a launch; the scheduler's host time spent forming batches before the
+ * launch (taking requests off the queue, arena admission, reading start
+ * positions) and moving finished batches into the completion queue.
+ * reset != 0 clears them after the read. */
 typedef struct {
   uint64_t batches;
   uint64_t requests;
@@ -302,6 +308,8 @@ typedef struct {
   int64_t launch_ns_max;
   uint64_t arena_stalls;
   uint64_t arena_peak;
+  int64_t admit_ns;
+  int64_t retire_ns;
 } phprng_server_counters;
 phprng_status phprng_server_read_counters(phprng_server *server, phprng_server_counters *out, int reset);
 /* Drains the batches on the device, stops the scheduler, frees the arena. */

@@ -23,62 +23,20 @@
 #include <mutex>
 #include <new>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "phprng.h"
+#include "serve_ranges.hpp"
 
 namespace {
+
+using phprng::serve::Arena;
+using phprng::serve::LiveRanges;
 
 int64_t now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
       .count();
 }
-
-// First-fit allocator over [0, capacity) elements with coalescing frees.
-class Arena {
- public:
-  explicit Arena(uint64_t cap) { free_[0] = cap; }
-  bool alloc(uint64_t n, uint64_t *off) {
-    if (n == 0) {
-      *off = 0;
-      return true;
-    }
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        *off = it->first;
-        const uint64_t rest = it->second - n, start = it->first + n;
-        free_.erase(it);
-        if (rest) free_[start] = rest;
-        used_ += n;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(uint64_t off, uint64_t n) {
-    if (n == 0) return;
-    used_ -= n;
-    auto it = free_.emplace(off, n).first;
-    auto next = std::next(it);
-    if (next != free_.end() && it->first + it->second == next->first) {
-      it->second += next->second;
-      free_.erase(next);
-    }
-    if (it != free_.begin()) {
-      auto prev = std::prev(it);
-      if (prev->first + prev->second == it->first) {
-        prev->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  uint64_t used() const { return used_; }
-
- private:
-  uint64_t used_ = 0;
-  std::map<uint64_t, uint64_t> free_;
-};
 
 struct Pending {
   uint64_t ticket, tag, count;
@@ -117,13 +75,21 @@ struct phprng_server {
   uint64_t next_ticket = 1;
 
   std::mutex amu;
-  std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> live;  // ticket -> (offset, count)
+  LiveRanges live;
   phprng_server_counters counters{};
   std::atomic<uint64_t> releases{0};     // arena releases so far
   std::atomic<bool> arena_blocked{false};  // the oldest request did not fit
   uint64_t blocked_at = 0;               // releases when that was found (scheduler only)
 
   uint64_t ninst = 0;
+  // scheduler-only scratch, kept across batches so that forming one
+  // allocates nothing in the steady state
+  std::vector<Pending> take;
+  std::vector<phprng_request> reqs;
+  std::vector<phprng_completion> meta;
+  std::vector<uint64_t> pos;        // per instance: position after the batch so far, or kNoPos
+  std::vector<uint32_t> pos_touched;
+  static constexpr uint64_t kNoPos = ~0ull;
   std::atomic<bool> stop{false};
   std::thread thread;
 
@@ -135,6 +101,7 @@ struct phprng_server {
 
 bool phprng_server::retire_finished() {
   bool any = false;
+  int64_t spent = 0;
   for (auto &b : batches) {
     if (!b.active) continue;
     hipError_t q = hipEventQuery(b.done);
@@ -149,14 +116,20 @@ bool phprng_server::retire_finished() {
     b.reqs.clear();
     b.active = false;
     any = true;
+    spent += now_ns() - t;
   }
-  if (any) cv_done.notify_all();
+  if (any) {
+    cv_done.notify_all();
+    std::lock_guard<std::mutex> lk(amu);
+    counters.retire_ns += spent;
+  }
   return any;
 }
 
 bool phprng_server::launch_batch(Batch &b) {
+  const int64_t t_form = now_ns();
   // take the batch's candidates off the queue (batch limits only) ...
-  std::vector<Pending> take;
+  take.clear();
   {
     std::lock_guard<std::mutex> lk(mu);
     uint64_t draws = 0;
@@ -171,8 +144,8 @@ bool phprng_server::launch_batch(Batch &b) {
   }
   if (take.empty()) return false;
   // ... then admit them in FIFO order while the arena has room
-  std::vector<phprng_request> reqs;
-  std::vector<phprng_completion> meta;
+  reqs.clear();
+  meta.clear();
   size_t fit = 0;
   {
     std::lock_guard<std::mutex> lk(amu);
@@ -192,7 +165,7 @@ bool phprng_server::launch_batch(Batch &b) {
       c.count = p.count;
       c.data = arena_ptr + off;
       c.t_submit_ns = p.t_submit;
-      live[p.ticket] = {off, p.count};
+      live.add(p.ticket, off, p.count);
       meta.push_back(c);
     }
     counters.arena_peak = std::max(counters.arena_peak, arena->used());
@@ -207,17 +180,19 @@ bool phprng_server::launch_batch(Batch &b) {
   }
   if (reqs.empty()) return false;
   // positions before the draws of each request (request order = FIFO order)
-  std::unordered_map<uint32_t, uint64_t> pos;
   for (size_t i = 0; i < reqs.size(); ++i) {
-    auto it = pos.find(reqs[i].instance);
-    if (it == pos.end()) {
+    const uint32_t id = reqs[i].instance;
+    if (pos[id] == kNoPos) {
       uint64_t k = 0;
-      phprng_get_position(ctx, reqs[i].instance, &k);
-      it = pos.emplace(reqs[i].instance, k).first;
+      phprng_get_position(ctx, id, &k);
+      pos[id] = k;
+      pos_touched.push_back(id);
     }
-    meta[i].k = it->second;
-    it->second += reqs[i].count;
+    meta[i].k = pos[id];
+    pos[id] += reqs[i].count;
   }
+  for (uint32_t id : pos_touched) pos[id] = kNoPos;
+  pos_touched.clear();
   const int64_t t_admit = now_ns();
   hipStream_t s = streams[next_stream];
   next_stream = (next_stream + 1) % (int)streams.size();
@@ -234,6 +209,7 @@ bool phprng_server::launch_batch(Batch &b) {
     counters.draws += draws;
     counters.launch_ns += dt;
     counters.launch_ns_max = std::max(counters.launch_ns_max, dt);
+    counters.admit_ns += t_admit - t_form;
   }
   for (auto &c : meta) {
     c.t_admit_ns = t_admit;
@@ -246,7 +222,7 @@ bool phprng_server::launch_batch(Batch &b) {
     cv_done.notify_all();
     return true;
   }
-  b.reqs = std::move(meta);
+  b.reqs.swap(meta);  // meta takes the retired batch's emptied buffer
   b.active = true;
   return true;
 }
@@ -295,7 +271,7 @@ extern "C" phprng_status phprng_server_create(phprng_ctx *ctx, const phprng_serv
   if (cfg) c = *cfg;
   if (c.arena_doubles == 0) c.arena_doubles = 1ull << 28;
   if (c.streams <= 0) c.streams = 2;
-  if (c.max_inflight <= 0) c.max_inflight = c.streams;
+  if (c.max_inflight <= 0) c.max_inflight = std::min(c.streams + 1, 6);
   if (c.max_batch_requests == 0) c.max_batch_requests = 8192;
   if (c.max_batch_draws == 0) c.max_batch_draws = 1ull << 28;
   if (c.streams > 8 || c.max_inflight > 6 || c.max_batch_requests > (1u << 24)) return PHPRNG_E_INVALID;
@@ -304,6 +280,7 @@ extern "C" phprng_status phprng_server_create(phprng_ctx *ctx, const phprng_serv
   s->ctx = ctx;
   s->cfg = c;
   s->ninst = phprng_instance_count(ctx);
+  s->pos.assign(s->ninst, phprng_server::kNoPos);
   if (hipMalloc(&s->arena_ptr, c.arena_doubles * sizeof(double)) != hipSuccess) return PHPRNG_E_NOMEM;
   s->arena = new Arena(c.arena_doubles);
   for (int i = 0; i < c.streams; ++i) {
@@ -356,13 +333,12 @@ phprng_status phprng_server::release_many(const uint64_t *tickets, uint64_t n) {
   {
     std::lock_guard<std::mutex> lk(amu);
     for (uint64_t i = 0; i < n; ++i) {
-      auto it = live.find(tickets[i]);
-      if (it == live.end()) {
+      uint64_t off = 0, count = 0;
+      if (!live.take(tickets[i], &off, &count)) {
         st = PHPRNG_E_INVALID;
         continue;
       }
-      arena->release(it->second.first, it->second.second);
-      live.erase(it);
+      arena->release(off, count);
       ++k;
     }
     releases.fetch_add(k);

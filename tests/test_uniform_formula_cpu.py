@@ -1,5 +1,8 @@
 """The width-32 kernels form R = (c+1)/(n+1) from a precomputed reciprocal
-plus one exact correction (for the proof).  This
+plus one exact correction.  It is the IEEE quotient for integers
+1 <= a < b <= 2^33: the residual a - b*q0 is computed exactly by the fma, the
+corrected value lies within 2^-52 ulp of a/b, and a/b with such a denominator
+is never that close to a rounding boundary of binary64.  This
 CPU test checks that form against IEEE division on >= 10^9 seeded pairs,
 near-midpoint pairs, and every a for several b, without touching the GPU.
 The paper's own shortcut (multiply by 1/(n+1), Sec. IV) is shown to differ."""
