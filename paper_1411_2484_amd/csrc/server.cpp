@@ -20,6 +20,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -46,6 +47,7 @@ struct Pending {
 
 struct Batch {
   hipEvent_t done = nullptr;
+  int stream = 0;  // index of the stream it was launched on
   std::vector<phprng_completion> reqs;
   bool active = false;
 };
@@ -97,6 +99,16 @@ struct phprng_server {
   bool retire_finished();
   bool launch_batch(Batch &b);
   phprng_status release_many(const uint64_t *tickets, uint64_t n);
+
+  // Frees what was created, also after a failed create; the scheduler
+  // thread must have been joined.
+  ~phprng_server() {
+    for (auto &b : batches)
+      if (b.done) (void)hipEventDestroy(b.done);
+    for (auto st : streams) (void)hipStreamDestroy(st);
+    if (arena_ptr) (void)hipFree(arena_ptr);
+    delete arena;
+  }
 };
 
 bool phprng_server::retire_finished() {
@@ -194,8 +206,22 @@ bool phprng_server::launch_batch(Batch &b) {
   for (uint32_t id : pos_touched) pos[id] = kNoPos;
   pos_touched.clear();
   const int64_t t_admit = now_ns();
-  hipStream_t s = streams[next_stream];
-  next_stream = (next_stream + 1) % (int)streams.size();
+  // the stream with the fewest batches on it, the rotation breaking ties, so
+  // that a batch queues behind another only when every stream is busy
+  const int ns = (int)streams.size();
+  int pick = -1, best = 0;
+  for (int i = 0; i < ns; ++i) {
+    const int si = (next_stream + i) % ns;
+    int load = 0;
+    for (const auto &o : batches) load += (o.active && o.stream == si) ? 1 : 0;
+    if (pick < 0 || load < best) {
+      pick = si;
+      best = load;
+    }
+  }
+  next_stream = (pick + 1) % ns;
+  b.stream = pick;
+  hipStream_t s = streams[pick];
   phprng_status st = phprng_generate(ctx, reqs.data(), reqs.size(), nullptr, nullptr, arena_ptr,
                                      cfg.arena_doubles, (void *)s, PHPRNG_MODE_PERSISTENT);
   if (st == PHPRNG_OK && hipEventRecord(b.done, s) != hipSuccess) st = PHPRNG_E_DEVICE;
@@ -280,20 +306,35 @@ extern "C" phprng_status phprng_server_create(phprng_ctx *ctx, const phprng_serv
   s->ctx = ctx;
   s->cfg = c;
   s->ninst = phprng_instance_count(ctx);
-  s->pos.assign(s->ninst, phprng_server::kNoPos);
-  if (hipMalloc(&s->arena_ptr, c.arena_doubles * sizeof(double)) != hipSuccess) return PHPRNG_E_NOMEM;
-  s->arena = new Arena(c.arena_doubles);
+  try {
+    s->pos.assign(s->ninst, phprng_server::kNoPos);
+  } catch (...) {
+    return PHPRNG_E_NOMEM;
+  }
+  if (hipMalloc(&s->arena_ptr, c.arena_doubles * sizeof(double)) != hipSuccess) {
+    s->arena_ptr = nullptr;
+    return PHPRNG_E_NOMEM;
+  }
+  s->arena = new (std::nothrow) Arena(c.arena_doubles);
+  if (!s->arena) return PHPRNG_E_NOMEM;
   for (int i = 0; i < c.streams; ++i) {
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return PHPRNG_E_DEVICE;
     s->streams.push_back(st);
   }
   s->batches.resize(c.max_inflight);
-  for (auto &b : s->batches)
-    if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) return PHPRNG_E_DEVICE;
-  phprng_server *raw = s.release();
-  raw->thread = std::thread([raw] { raw->loop(); });
-  *out = raw;
+  for (auto &b : s->batches) {
+    if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) {
+      b.done = nullptr;
+      return PHPRNG_E_DEVICE;
+    }
+  }
+  try {
+    s->thread = std::thread([raw = s.get()] { raw->loop(); });
+  } catch (...) {
+    return PHPRNG_E_NOMEM;  // no thread: nothing runs, the destructor frees the rest
+  }
+  *out = s.release();
   return PHPRNG_OK;
 }
 
@@ -390,11 +431,6 @@ extern "C" phprng_status phprng_server_destroy(phprng_server *s) {
   s->stop.store(true);
   s->cv_work.notify_all();
   if (s->thread.joinable()) s->thread.join();
-  for (auto &b : s->batches)
-    if (b.done) (void)hipEventDestroy(b.done);
-  for (auto st : s->streams) (void)hipStreamDestroy(st);
-  (void)hipFree(s->arena_ptr);
-  delete s->arena;
   delete s;
   return PHPRNG_OK;
 }
