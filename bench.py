@@ -242,7 +242,7 @@ def workload_e(args, torch, ph):
               "batches": cnt["batches"], "requests_per_batch": cnt["requests"] / max(cnt["batches"], 1),
               "launch_us_mean": cnt["launch_ns"] / max(cnt["batches"], 1) / 1e3,
               "launch_us_max": cnt["launch_ns_max"] / 1e3,
-              "form_us_mean": cnt["admit_ns"] / max(cnt["batches"], 1) / 1e3,
+              "form_us_mean": cnt["form_ns"] / max(cnt["batches"], 1) / 1e3,
               "retire_us_mean": cnt["retire_ns"] / max(cnt["batches"], 1) / 1e3,
               "arena_stalls": cnt["arena_stalls"],
               "arena_peak": cnt["arena_peak"]}

@@ -308,7 +308,7 @@ typedef struct {
   int64_t launch_ns_max;
   uint64_t arena_stalls;
   uint64_t arena_peak;
-  int64_t admit_ns;
+  int64_t form_ns;
   int64_t retire_ns;
 } phprng_server_counters;
 phprng_status phprng_server_read_counters(phprng_server *server, phprng_server_counters *out, int reset);

@@ -79,7 +79,7 @@ class phprng_server_counters(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("requests", ctypes.c_uint64), ("draws", ctypes.c_uint64),
                 ("launch_ns", ctypes.c_int64), ("launch_ns_max", ctypes.c_int64),
                 ("arena_stalls", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64),
-                ("admit_ns", ctypes.c_int64), ("retire_ns", ctypes.c_int64)]
+                ("form_ns", ctypes.c_int64), ("retire_ns", ctypes.c_int64)]
 
 
 ARRIVAL_DTYPE = np.dtype([("t_ns", np.int64), ("instance", np.uint32), ("reserved", np.uint32),
@@ -454,7 +454,7 @@ class Server:
 
     def counters(self, reset=False):
         """Launch counters (batches, requests, draws, launch_ns, launch_ns_max,
-        arena_stalls, arena_peak, admit_ns, retire_ns) as a dict; reset clears
+        arena_stalls, arena_peak, form_ns, retire_ns) as a dict; reset clears
         them after the read."""
         c = phprng_server_counters()
         _check(lib().phprng_server_read_counters(self._h, ctypes.byref(c), 1 if reset else 0))

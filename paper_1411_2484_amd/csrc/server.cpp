@@ -235,7 +235,7 @@ bool phprng_server::launch_batch(Batch &b) {
     counters.draws += draws;
     counters.launch_ns += dt;
     counters.launch_ns_max = std::max(counters.launch_ns_max, dt);
-    counters.admit_ns += t_admit - t_form;
+    counters.form_ns += t_admit - t_form;
   }
   for (auto &c : meta) {
     c.t_admit_ns = t_admit;

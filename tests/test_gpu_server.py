@@ -158,7 +158,7 @@ def test_server_open_loop_replay(ph):
     cnt = srv.counters()
     assert cnt["requests"] == n and cnt["draws"] == int(arr["count"].sum())
     assert 1 <= cnt["batches"] <= n and cnt["launch_ns_max"] * cnt["batches"] >= cnt["launch_ns"] > 0
-    assert cnt["admit_ns"] > 0 and cnt["retire_ns"] > 0
+    assert cnt["form_ns"] > 0 and cnt["retire_ns"] > 0
     assert (lat > 0).all()
     assert (adm >= 0).all() and (adm <= lat).all()
     assert np.percentile(lat, 50) < 5e6  # well under 5 ms at this light load
