@@ -3,10 +3,11 @@
 Each mutant below is the oracle's C source with one plausible slip (a
 dropped term, a wrong sign, bit, index or modulus, two steps swapped),
 compiled on its own and loaded as a separate copy of the oracle module.
-The pins of ``test_oracle_pins.py`` that check the affected step against
-something other than the oracle itself must reject it: at least one of the
-listed pins fails on every mutant, and all of them pass on the unmodified
-source built the same way.  Nothing here touches the GPU library.
+The pins (``test_oracle_pins.py``, ``test_pattern_oracle.py``) that check
+the affected step against something other than the oracle itself must
+reject it: at least one of the listed pins fails on every mutant, and all
+of them pass on the unmodified source built the same way.  Nothing here
+touches the GPU library.
 """
 
 import importlib.util
@@ -17,7 +18,9 @@ import subprocess
 
 import pytest
 
-from tests import test_oracle_pins as pins
+from tests import test_oracle_pins, test_pattern_oracle
+
+PIN_MODULES = (test_oracle_pins, test_pattern_oracle)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -84,6 +87,18 @@ MUTANTS = [
      "  for (uint64_t j = i * tab->stride; j < r; j++) {",
      "  for (uint64_t j = i * tab->stride; j <= r; j++) {",
      ["test_full_period_skip_sum", "test_position_equals_stepping_32"]),
+    ("pattern_decrypts_with_e",
+     "    uint64_t m = pho_powmod(c, d, n);",
+     "    uint64_t m = pho_powmod(c, e, n);",
+     ["test_enumeration_equals_full_period_windows"]),
+    ("pattern_advances_skip_before_first_point",
+     "        if (j > 1) {",
+     "        if (j >= 1) {",
+     ["test_enumeration_equals_full_period_windows"]),
+    ("pattern_bins_over_n_plus_one",
+     "((u128)cj * bins) / n)",
+     "((u128)cj * bins) / (n + 1))",
+     ["test_enumeration_equals_full_period_windows"]),
     ("decryption_inverts_e_mod_n",
      "uint64_t pho_decrypt(uint64_t c, uint64_t e, uint64_t n) {\n  uint64_t d = pho_inverse(e, n - 1);",
      "uint64_t pho_decrypt(uint64_t c, uint64_t e, uint64_t n) {\n  uint64_t d = pho_inverse(e, n);",
@@ -106,25 +121,40 @@ def _build(tmp_path, text, tag):
     return mod
 
 
+def _cases(fn):
+    """The argument sets of a pin's parametrize marks (their product)."""
+    cases = [{}]
+    for mark in getattr(fn, "pytestmark", []):
+        if mark.name != "parametrize":
+            continue
+        keys = [k.strip() for k in mark.args[0].split(",")]
+        rows = [dict(zip(keys, v if isinstance(v, (tuple, list)) else (v,))) for v in mark.args[1]]
+        cases = [dict(c, **r) for c in cases for r in rows]
+    return cases
+
+
 def _run_pin(name, mod, paper):
-    """Runs one pin against an oracle variant; returns None if it passes,
-    else a short description of how it failed."""
-    fn = getattr(pins, name)
-    args = {}
-    for a in inspect.signature(fn).parameters:
-        if a == "orc":
-            args[a] = mod
-        elif a == "paper":
-            args[a] = paper
-        elif a == "tab32":
-            p, g = mod.lcg_params(32)
-            args[a] = mod.SkipTab(p, g, 1 << 16, p - 1)
-        else:
-            raise AssertionError("pin %s needs fixture %s" % (name, a))
-    try:
-        fn(**args)
-    except Exception as exc:  # an assertion or an error both reject the variant
-        return "%s: %s" % (type(exc).__name__, str(exc).splitlines()[0] if str(exc) else "")
+    """Runs one pin (every parametrized case) against an oracle variant;
+    returns None if it passes, else a short description of the first failure."""
+    fn = next(getattr(m, name) for m in PIN_MODULES if hasattr(m, name))
+    for case in _cases(fn):
+        args = dict(case)
+        for a in inspect.signature(fn).parameters:
+            if a in args:
+                continue
+            if a == "orc":
+                args[a] = mod
+            elif a == "paper":
+                args[a] = paper
+            elif a == "tab32":
+                p, g = mod.lcg_params(32)
+                args[a] = mod.SkipTab(p, g, 1 << 16, p - 1)
+            else:
+                raise AssertionError("pin %s needs fixture %s" % (name, a))
+        try:
+            fn(**args)
+        except Exception as exc:  # an assertion or an error both reject the variant
+            return "%s %s" % (type(exc).__name__, case)
     return None
 
 
