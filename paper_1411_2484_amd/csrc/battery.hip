@@ -124,12 +124,29 @@ __global__ __launch_bounds__(kHistThreads, 8) void hist_kernel(const double *__r
   }
   if (lane < kPer && wbase + kHistThreads * lane < len) bits[(base_i + wbase + kHistThreads * lane) >> 6] = mine;
   __syncthreads();
+  // poker: a wave counts its hands per category with ballots and adds each
+  // count once (an LDS atomic per hand queued on the seven addresses)
   const uint32_t nhand = len / 5;
-  for (uint32_t j = threadIdx.x; j < nhand; j += kHistThreads) {
-    uint32_t d[5];
+  uint32_t wcount[kPokerCats];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) d[i] = b10[j * 5 + i];
-    atomicAdd(&poker[poker_cat(d)], 1u);
+  for (uint32_t c = 0; c < kPokerCats; ++c) wcount[c] = 0;
+  for (uint32_t j0 = wbase; j0 < nhand; j0 += kHistThreads) {  // wave-uniform bound
+    const uint32_t j = j0 + lane;
+    uint32_t cat = kPokerCats;  // lanes past the last hand count nowhere
+    if (j < nhand) {
+      uint32_t d[5];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) d[i] = b10[j * 5 + i];
+      cat = poker_cat(d);
+    }
+#pragma unroll
+    for (uint32_t c = 0; c < kPokerCats; ++c) wcount[c] += (uint32_t)__popcll(__ballot(cat == c));
+  }
+  if (lane < kPokerCats) {
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < kPokerCats; ++c) v = lane == c ? wcount[c] : v;
+    if (v) atomicAdd(&poker[lane], v);
   }
   // all five tests' keys of the tile in registers, then one scatter over the
   // partition space (its first barrier orders the last reads of the tile
