@@ -60,15 +60,23 @@ def _check_completion(ph, ctx_params, orc, tabs, c, data):
     assert np.array_equal(data.view(np.uint64), wr.view(np.uint64)), (c.instance, c.k, c.count)
 
 
-def test_server_results_match_oracle_alone_and_in_mix(ph, orc, tabs):
-    rng = random.Random(1)
+# (streams, batches in flight, requests per batch): the defaults; one
+# stream with a second batch queued behind the first; six small batches in
+# flight over three streams
+LAYOUTS = [(2, 0, 0), (1, 0, 16), (3, 6, 16)]
+
+
+@pytest.mark.parametrize("streams,inflight,per_batch", LAYOUTS)
+def test_server_results_match_oracle_alone_and_in_mix(ph, orc, tabs, streams, inflight, per_batch):
+    rng = random.Random(1 + streams)
     ctx = ph.Context(0, max_instances=64)
     ids32 = ctx.seed_instances(32, SEED0 + 200, 24, (9, 17), 0, 1 << 40)
     ids64 = ctx.seed_instances(64, SEED0 + 201, 8, (9, 17), 0, 1 << 24)
     ids = [int(i) for i in ids32] + [int(i) for i in ids64]
     params = {i: ctx.get_params(i) for i in ids}
     starts = {i: ctx.get_position(i) for i in ids}
-    srv = ph.Server(ctx, arena_doubles=1 << 22, streams=2)
+    srv = ph.Server(ctx, arena_doubles=1 << 22, streams=streams, max_inflight=inflight,
+                    max_batch_requests=per_batch)
     reqs = [(rng.choice(ids), int(2 ** rng.uniform(4, 14))) for _ in range(300)]
     for j, (i, cnt) in enumerate(reqs):
         srv.submit(i, cnt, tag=j)
@@ -101,7 +109,7 @@ def test_server_results_match_oracle_alone_and_in_mix(ph, orc, tabs):
     srv.close()
     ctx.close()
     # the same ranges requested alone, one request per fresh context, give the same bits
-    for inst, k, cnt, data in checked[:12]:
+    for inst, k, cnt, data in checked[:12 if streams == 2 else 3]:
         n, e, p, a, w = params[inst]
         solo = ph.Context(0, max_instances=1)
         sid = int(solo.add_instances(w, [n], [e], k0=[k])[0])
