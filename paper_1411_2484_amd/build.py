@@ -5,6 +5,7 @@ Usage: python -m paper_1411_2484_amd.build  (or call build()).
 
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -27,23 +28,38 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def _run(cmd, what, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on " + what)
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compiles every source (in parallel, `jobs` at a time; 0: up to 8),
+    links libphprng.so and builds the instruction-rate probe."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
+    cmds = []
+    objs = []
     for src in SOURCES:
         obj = os.path.join(build_dir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *lang, "-c",
-               os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError("hipcc failed on " + src)
+        cmds.append(([hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *lang, "-c",
+                      os.path.join(CSRC, src), "-o", obj], src))
         objs.append(obj)
+    # instruction-rate probe (a standalone executable)
+    probe = os.path.join(HERE, "probe_rates")
+    cmds.append(([hipcc, *HIPCC_FLAGS, "-o", probe + ".tmp", os.path.join(CSRC, "probe_rates.hip")],
+                 "probe_rates.hip"))
+    workers = jobs if jobs > 0 else max(1, min(8, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as pool:
+        for f in [pool.submit(_run, cmd, what, verbose) for cmd, what in cmds]:
+            f.result()
+    os.replace(probe + ".tmp", probe)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -51,14 +67,6 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("link failed")
     os.replace(tmp, LIB)
-    # instruction-rate probe (a standalone executable)
-    probe = os.path.join(HERE, "probe_rates")
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", probe + ".tmp", os.path.join(CSRC, "probe_rates.hip")]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed on probe_rates.hip")
-    os.replace(probe + ".tmp", probe)
     return LIB
 
 
