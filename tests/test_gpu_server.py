@@ -173,3 +173,21 @@ def test_server_open_loop_replay(ph):
     assert wall > 0
     srv.close()
     ctx.close()
+
+
+def test_server_rejected_configs_leave_the_context_usable(ph):
+    ctx = ph.Context(0, max_instances=4)
+    ids = ctx.seed_instances(32, SEED0 + 230, 2, (9, 17), 0, 0)
+    with pytest.raises(ph.PhprngError):
+        ph.Server(ctx, streams=9)            # at most 8 streams
+    with pytest.raises(ph.PhprngError):
+        ph.Server(ctx, max_inflight=7)       # at most 6 batches in flight
+    with pytest.raises(ph.PhprngError):
+        ph.Server(ctx, arena_doubles=1 << 40)  # 8 TiB: the arena allocation fails
+    srv = ph.Server(ctx, arena_doubles=1 << 16, streams=1)
+    t = srv.submit(int(ids[0]), 1000, tag=7)
+    (c,) = _collect(srv, 1)
+    assert c.status == 0 and c.count == 1000 and c.tag == 7
+    srv.release(t)
+    srv.close()
+    ctx.close()
