@@ -26,9 +26,12 @@
  *     binary64(c+1) by binary64(n+1).  For width 32 both conversions are
  *     exact and R lies in (0, 1); for width 64 the conversions round and R
  *     lies in (0, 1] (R = 1.0 occurs for the largest ciphertexts).
- *   - 64-bit positions.  Width-64 instances support positions k with
- *     k + (skip offset) < 2^34; calls that would reach beyond return
- *     PHPRNG_E_RANGE.  Width-32 positions use the whole uint64 range.
+ *   - Positions.  Positions of both widths use the whole uint64 range.  A
+ *     width-64 instance carries its message on the device (the state
+ *     (m, s) of Sec. II): each batch continues it from the instance's own
+ *     skip sums, so generation from any state and any position needs no
+ *     table.  Width-32 tile starts come from eq. (7) and one universal table
+ *     of skip sums over the whole skip period.
  *
  * Threading: a context may be used from one host thread at a time.  Every
  * call validates all of its arguments before it changes any state or
@@ -146,17 +149,26 @@ phprng_status phprng_add_instances_skip(phprng_ctx *ctx, uint64_t count, int wid
  * skip), *b = its constant skip (0 for the pseudorandom skip). */
 phprng_status phprng_get_schedule(phprng_ctx *ctx, uint32_t id, int *sched, uint64_t *b);
 
-/* Same result as phprng_draw_instances followed by phprng_add_instances with
- * m0 = 0, s0 = 1.  For count >= 1024 the primality of the stream outputs is
- * decided on the device (one deterministic Rabin-Miller per output) and the
- * instance records are built there; the draw order is unchanged. */
+/* Seeding of Sec. IV (each process draws its own modulus from a seeded
+ * stream and skips forward from the base state (m_0, s_0) = (0, 1) of
+ * eq. (7)): the same result as phprng_draw_instances followed by
+ * phprng_add_instances with m0 = 0, s0 = 1.  For count >= 1024 the primality
+ * of the stream outputs is decided on the device (one deterministic
+ * Rabin-Miller per output) and the instance records are built there; the
+ * draw order is unchanged.  In that bulk form width-64 starts must lie below
+ * 2^34 (k_hi <= 2^34; the start messages come from the positioning table),
+ * else PHPRNG_E_RANGE; smaller counts accept any start that
+ * phprng_add_instances accepts.  ids: host array of count entries that
+ * receives the new instance ids. */
 phprng_status phprng_seed_instances(phprng_ctx *ctx, uint64_t count, int width, uint64_t seed,
                                     const uint64_t *e_set, int e_len, uint64_t k_lo, uint64_t k_hi, uint32_t *ids);
 
 uint64_t phprng_instance_count(const phprng_ctx *ctx);
 
-/* Generate draws for `nreq` requests (host array) into caller-owned device
- * arrays: out_c32 receives the ciphertexts of width-32 requests, out_c64 those
+/* The hot path: algorithm (9) of Sec. IV, s := a s mod p; m := (m + s) mod n;
+ * c := m^e mod n (eq. (1)); R := (c + 1)/(n + 1), run `count` times per
+ * request from the instance's current state.  Generate draws for `nreq`
+ * requests (host array) into caller-owned device arrays: out_c32 receives the ciphertexts of width-32 requests, out_c64 those
  * of width-64 requests, out_r the uniforms of both; any of them may be NULL
  * (that output is not written).  `capacity` is the element count of every
  * non-NULL output array; each request must satisfy out_offset + count <=
@@ -174,10 +186,18 @@ phprng_status phprng_generate(phprng_ctx *ctx, const phprng_request *reqs, uint6
                               uint64_t *out_c64, double *out_r, uint64_t capacity, void *stream, int mode);
 
 /* Move instance `id` by delta positions (eq. (7); delta < 0 moves backward as
- * in Sec. II).  PHPRNG_E_RANGE if the position would leave its range. */
+ * in Sec. II).  PHPRNG_E_RANGE if the position would leave its range.  A
+ * width-64 move of d = q (p - 1) + r draws adds q whole skip periods
+ * (p(p-1)/2 each, Sec. II) and the skip sum of the remaining r draws, taken
+ * from the positioning table when both ends lie below 2^34 and otherwise
+ * summed on the device (time proportional to min(r, p - 1 - r); either must
+ * stay below 2^42, else PHPRNG_E_RANGE). */
 phprng_status phprng_jump(phprng_ctx *ctx, uint32_t id, int64_t delta);
 
-/* Current state (m_k, s_k, c_k, k) of instance `id`. */
+/* Current state (m_k, s_k, c_k, k) of instance `id`: the mutable integers m,
+ * s and c of Sec. II (c_k = m_k^e mod n, eq. (1)) and the position k of
+ * eq. (7).  Waits for queued width-64 work, whose message is on the device.
+ * out: host struct owned by the caller. */
 phprng_status phprng_get_state(phprng_ctx *ctx, uint32_t id, phprng_state *out);
 
 /* Current position k of instance `id` (cheap: no state is computed). */
@@ -185,27 +205,39 @@ phprng_status phprng_get_position(phprng_ctx *ctx, uint32_t id, uint64_t *k);
 
 /* Restore instance `id` to the state (st->m, st->s) reported at position
  * st->k (st->c is ignored; for a constant-skip instance st->s must equal
- * its b).  Any s in [1, p-1] is accepted: the library finds
- * t with a^t = s mod p by a Pohlig-Hellman discrete logarithm (p - 1 is
- * smooth for both skip moduli).  PHPRNG_E_RANGE for width 64 if t lies beyond
- * the supported position range. */
+ * its b).  Any m in [0, n-1] and any s in [1, p-1] are accepted, for both
+ * widths: the library finds t with a^t = s mod p by a Pohlig-Hellman
+ * discrete logarithm (p - 1 is smooth for both skip moduli), so that the
+ * stream continues by eq. (5)-(6) from exactly that state. */
 phprng_status phprng_set_state(phprng_ctx *ctx, uint32_t id, const phprng_state *st);
 
-/* Fixed parameters of instance `id` (any pointer may be NULL). */
+/* Fixed parameters of instance `id`: the modulus n and exponent e of
+ * eq. (1) and the skip generator's p and a of eq. (5) (the four constant
+ * integers of the state in Sec. II), and its width.  Any pointer may be
+ * NULL. */
 phprng_status phprng_get_params(phprng_ctx *ctx, uint32_t id, uint64_t *n, uint64_t *e, uint64_t *p, uint64_t *a,
                                 int *width);
 
-/* Launch shape used by phprng_generate (persistent mode) and graphs. */
+/* Launch shapes used by phprng_generate (persistent mode) and graphs, one
+ * per class of batch: width-32 requests only, width-64 only, or both.
+ * phprng_set_tuning sets all three classes; phprng_get_tuning reads the
+ * width-32 class. */
+enum { PHPRNG_CLASS_W32 = 0, PHPRNG_CLASS_W64 = 1, PHPRNG_CLASS_MIXED = 2 };
 phprng_status phprng_set_tuning(phprng_ctx *ctx, const phprng_tuning *t);
 phprng_status phprng_get_tuning(phprng_ctx *ctx, phprng_tuning *t);
+phprng_status phprng_set_tuning_class(phprng_ctx *ctx, int cls, const phprng_tuning *t);
+phprng_status phprng_get_tuning_class(phprng_ctx *ctx, int cls, phprng_tuning *t);
 
 /* Time candidate launch shapes (block size, blocks per CU, tiles per chunk,
  * unroll) on a synthetic batch of about `draws` draws spread over the
  * context's first (up to 4096) instances, writing FP64 uniforms only, into a
  * temporary device buffer of 8 bytes per draw.  Each shape is timed by the
  * median of three kernel times after a 300 ms warm-up; the fastest is kept
- * (if it beats the current shape on a re-run) and returned in *best (may be
- * NULL).  Instance positions are restored afterwards. */
+ * (if it beats the current shape on a re-run) for the class of that batch
+ * (the widths among those instances), returned in *best (may be NULL), and
+ * remembered for the process: later contexts on a device of the same
+ * architecture and compute-unit count start from it.  Instance positions
+ * and width-64 messages are restored afterwards. */
 phprng_status phprng_autotune(phprng_ctx *ctx, uint64_t draws, phprng_tuning *best);
 
 /* ---- captured repeat draws -------------------------------------------------*/
@@ -213,10 +245,11 @@ phprng_status phprng_autotune(phprng_ctx *ctx, uint64_t draws, phprng_tuning *be
 typedef struct phprng_graph phprng_graph;
 
 /* Capture one persistent generation of `reqs` into a HIP graph.  Each
- * phprng_graph_launch continues every request's instance by its count (the
- * request positions are advanced on the device by the graph itself) and
- * overwrites the same output ranges.  The instances' host positions advance
- * at each launch.  Requests must name distinct instances. */
+ * phprng_graph_launch draws every request's count from its instance's
+ * current position (whatever moved it since the last launch: generate,
+ * jump, set_state), advances the positions and overwrites the same output
+ * ranges; the planned requests are copied to the device before each
+ * replay.  Requests must name distinct instances. */
 phprng_status phprng_graph_create(phprng_ctx *ctx, const phprng_request *reqs, uint64_t nreq, uint32_t *out_c32,
                                   uint64_t *out_c64, double *out_r, uint64_t capacity, void *stream,
                                   phprng_graph **graph);
@@ -436,7 +469,7 @@ phprng_status phprng_chi2_pvalue(double chi2, double dof, double *p);
 phprng_status phprng_interleave(const double *in, double *out, uint64_t nstreams, uint64_t length, void *stream);
 
 
-/* ---- full-period local pattern (Sec. III) -----------------------------------*/
+/* ---- full-period local pattern (Sec. II, Figs. 3-4) --------------------------*/
 
 /* Over one period n(p-1) of a width-32 instance every state (m_k, s_k)
  * occurs once, so the windows (c_k, c_{k+1}, ..., c_{k+D-1}) whose first

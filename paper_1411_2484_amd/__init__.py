@@ -31,6 +31,10 @@ PHPRNG_E_DEVICE = -6
 PHPRNG_MODE_PERSISTENT = 0
 PHPRNG_MODE_PLAIN = 1
 
+PHPRNG_CLASS_W32 = 0
+PHPRNG_CLASS_W64 = 1
+PHPRNG_CLASS_MIXED = 2
+
 _u64 = ctypes.c_uint64
 _pu64 = ctypes.POINTER(ctypes.c_uint64)
 _pu32 = ctypes.POINTER(ctypes.c_uint32)
@@ -113,6 +117,8 @@ SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_int)]),
     "phprng_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(phprng_tuning)]),
     "phprng_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(phprng_tuning)]),
+    "phprng_set_tuning_class": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(phprng_tuning)]),
+    "phprng_get_tuning_class": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(phprng_tuning)]),
     "phprng_autotune": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(phprng_tuning)]),
     "phprng_graph_create": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp, ctypes.POINTER(_vp)]),
     "phprng_graph_launch": (ctypes.c_int, [_vp, _vp]),
@@ -219,8 +225,44 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
-def _dptr(t):
-    return None if t is None else t.data_ptr()
+# element types each device array may have (the library writes 4-byte
+# ciphertexts, 8-byte ciphertexts and binary64 uniforms)
+_C32_DTYPES = ("int32", "uint32")
+_C64_DTYPES = ("int64", "uint64")
+_R_DTYPES = ("float64",)
+
+
+def _device_array(t, dtypes, device, what):
+    """Device address of tensor `t` after checking that it is a contiguous
+    tensor on HIP device `device` with one of `dtypes`; None for None.
+    Raises before anything is launched."""
+    if t is None:
+        return None
+    dt = str(getattr(t, "dtype", "")).replace("torch.", "")
+    if dt not in dtypes:
+        raise TypeError("%s must have dtype %s, got %s" % (what, " or ".join(dtypes), dt or type(t).__name__))
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("%s must be a device (cuda) tensor" % what)
+    idx = getattr(getattr(t, "device", None), "index", None)
+    if device is not None and idx is not None and idx != device:
+        raise ValueError("%s is on device %s, the context on device %s" % (what, idx, device))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    return t.data_ptr()
+
+
+def _outputs(out_c32, out_c64, out_r, device, capacity):
+    """Checked device addresses of the three output arrays and the capacity
+    (the smallest element count among the given arrays when not stated)."""
+    p32 = _device_array(out_c32, _C32_DTYPES, device, "out_c32")
+    p64 = _device_array(out_c64, _C64_DTYPES, device, "out_c64")
+    pr = _device_array(out_r, _R_DTYPES, device, "out_r")
+    caps = [t.numel() for t in (out_c32, out_c64, out_r) if t is not None]
+    if capacity is None:
+        capacity = min(caps) if caps else 0
+    elif caps and int(capacity) > min(caps):
+        raise ValueError("capacity %d exceeds an output array of %d elements" % (capacity, min(caps)))
+    return p32, p64, pr, int(capacity)
 
 
 def make_requests(instances, counts, offsets):
@@ -319,14 +361,14 @@ class Context:
 
     def generate(self, requests, out_c32=None, out_c64=None, out_r=None, capacity=None, stream=None,
                  mode=PHPRNG_MODE_PERSISTENT):
-        """requests: numpy array of REQUEST_DTYPE.  Outputs are device tensors
-        (uint32 / int64 viewed as uint64 / float64) or None."""
+        """requests: numpy array of REQUEST_DTYPE.  Outputs are contiguous
+        device tensors on this context's device (int32/uint32, int64/uint64,
+        float64) or None."""
         reqs = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
-        if capacity is None:
-            caps = [t.numel() for t in (out_c32, out_c64, out_r) if t is not None]
-            capacity = min(caps) if caps else 0
-        self._chk(lib().phprng_generate(self._h, reqs.ctypes.data, reqs.size, _dptr(out_c32), _dptr(out_c64),
-                                        _dptr(out_r), int(capacity), _stream_handle(stream), int(mode)))
+        p32, p64, pr, cap = _outputs(out_c32, out_c64, out_r, self.device, capacity)
+        self._chk(lib().phprng_generate(self._h, reqs.ctypes.data, reqs.size, p32, p64, pr, cap,
+                                        _stream_handle(stream), int(mode)))
+
 
     def last_kernel_ms(self):
         v = ctypes.c_double()
@@ -376,6 +418,16 @@ class Context:
         return dict(block_threads=t.block_threads, blocks_per_cu=t.blocks_per_cu,
                     tiles_per_chunk=t.tiles_per_chunk, unroll=t.unroll)
 
+    def set_tuning_class(self, cls, block_threads=0, blocks_per_cu=0, tiles_per_chunk=0, unroll=0):
+        t = phprng_tuning(block_threads, blocks_per_cu, tiles_per_chunk, unroll)
+        self._chk(lib().phprng_set_tuning_class(self._h, int(cls), ctypes.byref(t)))
+
+    def get_tuning_class(self, cls):
+        t = phprng_tuning()
+        self._chk(lib().phprng_get_tuning_class(self._h, int(cls), ctypes.byref(t)))
+        return dict(block_threads=t.block_threads, blocks_per_cu=t.blocks_per_cu,
+                    tiles_per_chunk=t.tiles_per_chunk, unroll=t.unroll)
+
     def autotune(self, draws=1 << 26):
         t = phprng_tuning()
         self._chk(lib().phprng_autotune(self._h, int(draws), ctypes.byref(t)))
@@ -391,12 +443,10 @@ class Graph:
 
     def __init__(self, ctx, requests, out_c32, out_c64, out_r, capacity, stream):
         reqs = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
-        if capacity is None:
-            caps = [t.numel() for t in (out_c32, out_c64, out_r) if t is not None]
-            capacity = min(caps) if caps else 0
+        p32, p64, pr, cap = _outputs(out_c32, out_c64, out_r, ctx.device, capacity)
         h = _vp()
-        _check(lib().phprng_graph_create(ctx.handle, reqs.ctypes.data, reqs.size, _dptr(out_c32), _dptr(out_c64),
-                                         _dptr(out_r), int(capacity), _stream_handle(stream), ctypes.byref(h)),
+        _check(lib().phprng_graph_create(ctx.handle, reqs.ctypes.data, reqs.size, p32, p64, pr, cap,
+                                         _stream_handle(stream), ctypes.byref(h)),
                ctx.handle)
         self._h = h
         self._ctx = ctx
@@ -510,7 +560,11 @@ def battery_probabilities(test):
 
 def interleave(src, dst, nstreams, length, stream=None):
     """dst[t * nstreams + i] = src[i * length + t] (device float64 tensors)."""
-    _check(lib().phprng_interleave(_dptr(src), _dptr(dst), int(nstreams), int(length), _stream_handle(stream)))
+    ps = _device_array(src, _R_DTYPES, None, "src")
+    pd = _device_array(dst, _R_DTYPES, None, "dst")
+    if src.numel() < nstreams * length or dst.numel() < nstreams * length:
+        raise ValueError("interleave: arrays shorter than nstreams * length")
+    _check(lib().phprng_interleave(ps, pd, int(nstreams), int(length), _stream_handle(stream)))
 
 
 class Battery:
@@ -531,7 +585,10 @@ class Battery:
     def accumulate(self, r, count=None, stream=None):
         """Add the uniforms of device tensor `r` (float64; count a multiple of 2^20)."""
         n = r.numel() if count is None else int(count)
-        self._chk(lib().phprng_battery_accumulate(self._h, _dptr(r), n, _stream_handle(stream)))
+        pr = _device_array(r, _R_DTYPES, None, "r")
+        if n > r.numel():
+            raise ValueError("count beyond the array")
+        self._chk(lib().phprng_battery_accumulate(self._h, pr, n, _stream_handle(stream)))
 
     def report(self, stream=None):
         """{test name: (chi2, dof, p_value, samples)}."""
@@ -550,7 +607,11 @@ class Battery:
 
     def fourier(self, r, coef, count=None, stream=None):
         n = r.numel() if count is None else int(count)
-        self._chk(lib().phprng_battery_fourier(self._h, _dptr(r), n, _dptr(coef), _stream_handle(stream)))
+        pr = _device_array(r, _R_DTYPES, None, "r")
+        pc = _device_array(coef, _R_DTYPES, None, "coef")
+        if n > r.numel() or coef.numel() < n:
+            raise ValueError("fourier: arrays shorter than count")
+        self._chk(lib().phprng_battery_fourier(self._h, pr, n, pc, _stream_handle(stream)))
 
     def timing(self):
         """{kernel class: (ms, launches)} since the last reset."""
@@ -582,12 +643,19 @@ def pattern_spec(n, e, x0, l0, dim, bins, s_lo=1, s_hi=None):
 
 def pattern_histogram(spec, hist, stream=None):
     """Add the counts of `spec` to `hist` (device int64 tensor of bins^(dim-1))."""
-    _check(lib().phprng_pattern_histogram(ctypes.byref(spec), _dptr(hist), _stream_handle(stream)))
+    ph = _device_array(hist, _C64_DTYPES, None, "hist")
+    # the library refuses a bad shape itself; for a shape it accepts, the
+    # caller's array must hold every cell
+    dim, bins = int(spec.dim), int(spec.bins)
+    if 2 <= dim <= 5 and bins >= 1 and bins ** (dim - 1) <= (1 << 24) and hist.numel() < bins ** (dim - 1):
+        raise ValueError("hist must hold bins^(dim-1) counts")
+    _check(lib().phprng_pattern_histogram(ctypes.byref(spec), ph, _stream_handle(stream)))
 
 
 def pattern_chi2(spec, hist, stream=None):
     """(chi2, p_value, total) of a pattern histogram."""
     c, p, t = ctypes.c_double(), ctypes.c_double(), _u64()
-    _check(lib().phprng_pattern_chi2(ctypes.byref(spec), _dptr(hist), ctypes.byref(c), ctypes.byref(p),
+    ph = _device_array(hist, _C64_DTYPES, None, "hist")
+    _check(lib().phprng_pattern_chi2(ctypes.byref(spec), ph, ctypes.byref(c), ctypes.byref(p),
                                      ctypes.byref(t), _stream_handle(stream)))
     return c.value, p.value, t.value

@@ -221,6 +221,21 @@ __device__ __forceinline__ uint64_t powmod_p61(uint64_t b, uint64_t e) {
   return r;
 }
 
+// a^t mod (2^61 - 1) computed by the whole wave: lane b contributes
+// pow2[b] = a^{2^b} when bit b of t is set, and the 64 factors are multiplied
+// in a butterfly (six products per lane instead of up to 61 in sequence).
+// Every lane receives the result.
+__device__ __forceinline__ uint64_t wave_pow_p61(const uint64_t *pow2, uint64_t t, uint32_t lane) {
+  uint64_t f = (lane < 61 && ((t >> lane) & 1)) ? pow2[lane] : 1ull;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t lo = __shfl_xor((int)(uint32_t)f, d, 64);
+    const uint32_t hi = __shfl_xor((int)(uint32_t)(f >> 32), d, 64);
+    f = mulmod_p61(f, ((uint64_t)hi << 32) | lo);
+  }
+  return f;
+}
+
 // binary64(c + 1) / binary64(n + 1) correctly rounded, with den = RN(n + 1)
 // and rcp = RN(1/den); c + 1 < 2^63 converts with one rounding.  The first
 // correction makes the quotient faithful (within 1 ulp); from a faithful
@@ -379,6 +394,37 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
   uint32_t lo = __shfl((int)(uint32_t)v, src, 64);
   uint32_t hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
   return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+  uint32_t lo = __shfl_xor((int)(uint32_t)v, mask, 64);
+  uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), mask, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Sum of v over the 64 lanes of the wave, mod n (v < n < 2^63); every lane
+// receives it.
+__device__ __forceinline__ uint64_t wave_sum_mod(uint64_t v, uint64_t n) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t t = v + shfl_xor_u64(v, d);
+    v = t >= n ? t - n : t;
+  }
+  return v;
+}
+
+// Exclusive prefix sum of v over the lanes of the wave, mod n (v < n < 2^63).
+__device__ __forceinline__ uint64_t wave_exclusive_mod(uint64_t v, uint64_t n, uint32_t lane) {
+  uint64_t incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t u = shfl_up_u64(incl, d);
+    if ((int)lane >= d) {
+      const uint64_t t = incl + u;
+      incl = t >= n ? t - n : t;
+    }
+  }
+  return incl >= v ? incl - v : incl + (n - v);
 }
 
 // Orders this wave's LDS accesses across lanes (all lanes of one wave).

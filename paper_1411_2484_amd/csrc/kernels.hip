@@ -1,15 +1,18 @@
 // gfx950 kernels for the Pohlig-Hellman parameter-split generator:
 //   - skip-prefix table segments (eq. (7b) building blocks),
-//   - the request planner (tile/chunk bookkeeping for a batch),
+//   - width-64 tile starts from the requests' own skip sums (reduce, then a
+//     scan per instance that also commits the instance's message),
 //   - batched generation (algorithm (9)) as a persistent work-stealing grid
 //     or as one plain grid per request,
-//   - the position advance used by captured repeat draws.
+//   - width-64 positioning and jumps (eq. (7) sums on the device).
 //
-// Work decomposition.  A tile is 2048 consecutive draws of one instance whose
-// starting state index is a multiple of 2048 within the skip period (the
-// universal table holds the skip-prefix sum U and the skip a^r there).  One
-// wave computes a tile in three passes over its LDS row block:
-//   A. lane l steps the skip generator over its run of 32 draws, keeps the
+// Width-32 tiles are 2048 consecutive draws of one instance whose starting
+// state index is a multiple of 2048 within the skip period: the universal
+// table holds the skip-prefix sum U and the skip a^r there.  Width-64 tiles
+// are 1024 draws counted from the first draw of their request; their start
+// states come from the reduce and scan kernels.  One wave computes a tile in
+// three passes over its LDS row block:
+//   A. lane l steps the skip generator over its run of draws, keeps the
 //      skips in LDS and sums them;
 //   B. a wave scan of the run sums gives each lane its starting message; the
 //      lane accumulates its run's messages into LDS (eq. (3a));
@@ -19,6 +22,7 @@
 // state from one tile to the next within a chunk.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "arith.hpp"
@@ -27,10 +31,14 @@
 
 namespace phprng {
 
-constexpr int kRow = kRun + 1;  // padded LDS row (conflict-free for both access orders)
+constexpr int kRow32 = kRun32 + 1;  // padded LDS rows (conflict-free for both access orders)
+constexpr int kRow64 = kRun64 + 1;
 static_assert((kTilesPerPeriod32 & (kTilesPerPeriod32 - 1)) == 0, "tiles per period is a power of two");
 constexpr int kTileShift32 = 20;
 static_assert((1ull << kTileShift32) == kTilesPerPeriod32, "tile shift");
+// LDS words (64-bit) per wave: the width-32 block, or the larger width-64 one.
+constexpr int kLdsWords32 = (64 * kRow32 + 1) / 2;  // 1056
+constexpr int kLdsWords64 = 64 * kRow64;            // 1088
 
 // ---------------------------------------------------------------------------
 // skip-prefix table segments
@@ -140,112 +148,214 @@ __global__ void __launch_bounds__(256) build_records(const uint64_t *n_arr, cons
 }
 
 // ---------------------------------------------------------------------------
-// planner
+// width-64 skip sums from the positioning table (eq. (7b))
 // ---------------------------------------------------------------------------
 
-// Global tile index of the tile whose draws include the draw made from state
-// index x.
-__device__ __forceinline__ uint64_t tile_of(uint64_t x, bool w64) {
-  if (w64) return x / kTile;
-  uint64_t q = x / ((uint64_t)kP32 - 1);
-  uint64_t r = x - q * ((uint64_t)kP32 - 1);
-  return (q << kTileShift32) | (r / kTile);
+// U(t) mod n for t < kTab64Range: the table entry at or below t plus at most
+// 2047 steps of the skip generator, then the 128-bit sum reduced mod n.
+__device__ uint64_t table_prefix64(const uint64_t *u_lo, const uint64_t *u_hi, const uint64_t *u_s, uint64_t t,
+                                   uint64_t n, uint64_t ninv, uint64_t r2) {
+  const uint64_t i = t / kTableStride;
+  uint64_t lo = u_lo[i], hi = u_hi[i], s = u_s[i];
+  for (uint64_t x = i * kTableStride; x < t; ++x) {
+    s = dev::mulmod_p61(kA64, s);
+    const uint64_t v = lo + s;
+    hi += v < lo ? 1 : 0;
+    lo = v;
+  }
+  // hi < 2^30 < n, so REDC applies; times R^2 undoes the 2^-64
+  dev::W128 w;
+  w.lo = lo;
+  w.hi = hi;
+  return dev::mont64(dev::redc64(w, n, ninv), r2, n, ninv);
 }
 
-// Inclusive scan of v over a workgroup of kPlanGroup threads; *total gets the
-// sum.  ws: LDS scratch of kPlanGroup / 64 words.  Starts and ends with a barrier.
-__device__ __forceinline__ uint64_t plan_scan(uint64_t v, uint64_t *ws, uint64_t *total) {
-  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  uint64_t incl = v;
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint64_t u = dev::shfl_up_u64(incl, d);
-    if ((int)lane >= d) incl += u;
-  }
-  if (lane == 63) ws[w] = incl;
-  __syncthreads();
-  uint64_t before = 0, all = 0;
-#pragma unroll
-  for (uint32_t j = 0; j < kPlanGroup / 64; ++j) {
-    before += j < w ? ws[j] : 0;
-    all += ws[j];
-  }
-  *total = all;
-  __syncthreads();
-  return before + incl;
+// m64[ids[i]] = m0[i] + U(ta[i]) - U(tb[i]) mod n, for skip logarithms
+// ta, tb < kTab64Range (one thread per instance).  With ta = t0 + k0 and
+// tb = t0 this is the message at position k0 of an instance whose state at
+// position 0 is (m0, a^t0) (eq. (7b)); a jump by d from skip log t takes
+// ta = t + d, tb = t (backward: ta = t - d).
+__global__ void __launch_bounds__(256) position64_kernel(const InstRec *inst, const uint32_t *ids, const uint64_t *m0,
+                                                         const uint64_t *ta, const uint64_t *tb, uint64_t count,
+                                                         const uint64_t *u_lo, const uint64_t *u_hi,
+                                                         const uint64_t *u_s, uint64_t *m64) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const InstRec &I = inst[ids[i]];
+  const uint64_t n = I.n, ninv = I.ninv, r2 = I.r2;
+  const uint64_t a = ta ? ta[i] : 0, b = tb ? tb[i] : 0;
+  const uint64_t ua = a ? table_prefix64(u_lo, u_hi, u_s, a, n, ninv, r2) : 0;
+  const uint64_t ub = b ? table_prefix64(u_lo, u_hi, u_s, b, n, ninv, r2) : 0;
+  const uint64_t m = dev::addmod64(m0 ? m0[i] : 0, ua, n);
+  m64[ids[i]] = m >= ub ? m - ub : m + (n - ub);
 }
 
-// One workgroup per kPlanGroup requests.  The host-written requests are read
-// with system-scope loads (src is pinned host memory, or device memory for
-// graph replays); per request the first tile, tile count and chunk count are
-// found, scanned inside the group, and the group's total goes to gbase.  The
-// last workgroup to finish turns gbase into exclusive prefixes, stores the
-// batch total, and clears the work counter and its own completion counter.
-__global__ void __launch_bounds__(kPlanGroup) plan_kernel(const InstRec *inst, const HostReq *src, ReqRec *req,
-                                                          uint64_t nreq, uint64_t *gbase, PlanHdr *hdr,
-                                                          uint32_t tiles_per_chunk) {
-  constexpr uint32_t kWords = sizeof(HostReq) / 8;
-  __shared__ uint64_t words[kPlanGroup * kWords];
-  __shared__ uint64_t ws[kPlanGroup / 64];
-  __shared__ uint32_t last;
-  const uint32_t tid = threadIdx.x;
-  const uint64_t r0 = (uint64_t)blockIdx.x * kPlanGroup;
-  const uint32_t nin = (uint32_t)min((uint64_t)kPlanGroup, nreq - r0);
-  // consecutive lanes read consecutive words: whole lines over the bus
-  const uint64_t *sw = reinterpret_cast<const uint64_t *>(src + r0);
-  for (uint32_t i = tid; i < nin * kWords; i += kPlanGroup)
-    words[i] = __hip_atomic_load(sw + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __syncthreads();
-  ReqRec R{};
-  if (tid < nin) {
-    R.k = words[tid * kWords];
-    R.count = words[tid * kWords + 1];
-    R.out_off = words[tid * kWords + 2];
-    R.inst = (uint32_t)words[tid * kWords + 3];
-    const InstRec &I = inst[R.inst];
-    const bool w64 = I.width == 64 || I.sched == kSchedConstant;  // no skip period to respect
-    if (R.count > 0) {
-      R.g1 = tile_of(R.k, w64);
-      R.ntiles = tile_of(R.k + R.count - 1, w64) - R.g1 + 1;
+// ---------------------------------------------------------------------------
+// width-64 tile starts: reduce, then scan per instance
+// ---------------------------------------------------------------------------
+
+// Wave-cooperative search over a sorted key: the last index r in [0, nreq)
+// with key(r) <= c (the last such r when empty requests share a key).
+template <typename Key>
+__device__ __forceinline__ uint64_t wave_search(uint64_t nreq, uint64_t c, uint32_t lane, Key key) {
+  uint64_t lo = 0, hi = nreq;
+  while (hi - lo > 1) {
+    const uint64_t step = (hi - lo + 63) / 64;
+    const uint64_t idx = lo + (uint64_t)lane * step;
+    const bool le = idx < hi && key(idx) <= c;
+    const uint64_t mask = __ballot(le);
+    const uint64_t k = (uint64_t)__popcll(mask);
+    lo = lo + (k - 1) * step;
+    hi = min(lo + step, hi);
+  }
+  return lo;
+}
+
+// Sum, mod n, of the skips of lane `lane`'s run of kRun64 draws in a tile
+// that starts with skip s_tile and holds `len` draws; every lane gets the
+// tile total.
+__device__ __forceinline__ uint64_t tile_skip_sum64(uint64_t s_tile, uint64_t lane_mul, uint32_t len, uint64_t n,
+                                                    uint32_t lane) {
+  uint64_t s = dev::mulmod_p61(s_tile, lane_mul);
+  uint64_t sum = 0;
+  const uint32_t first = lane * kRun64;
+#pragma unroll 4
+  for (int i = 0; i < kRun64; ++i) {
+    s = dev::mulmod_p61(kA64, s);
+    if (first + (uint32_t)i < len) sum = dev::addmod64(sum, s, n);
+  }
+  return dev::wave_sum_mod(sum, n);
+}
+
+// Draws in tile j of a width-64 request: 1024, or what is left in its last
+// tile.  Written with a 32-bit test of the tile index: a wave-uniform 64-bit
+// "rem < 1024 ? rem : 1024" has been compiled for gfx950 into a select that
+// reads a stale SCC after the branch on the same comparison, which gave 1024
+// for every last tile.
+__device__ __forceinline__ uint32_t tile_len64(const ReqRec &R, uint32_t j) {
+  const uint32_t last = (uint32_t)(R.count - (uint64_t)(R.ntiles - 1) * kTile64);
+  return j + 1 == R.ntiles ? last : (uint32_t)kTile64;
+}
+
+// One wave per width-64 tile (grid-stride): the skip before the tile,
+// a^{t + 1024 j} mod p for tile j of a request starting at skip log t, and
+// the sum of the tile's skips mod n.
+__global__ void __launch_bounds__(256) reduce64_kernel(GenArgs A) {
+  const uint32_t lane = dev::lane_id();
+  const uint32_t wave = dev::uniform_u32(threadIdx.x / 64);
+  const uint64_t tiles = dev::uniform_u64(dev::const_load(&A.hdr->tiles64));
+  const uint64_t nreq64 = dev::uniform_u64(dev::const_load(&A.hdr->nreq64));
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / 64);
+  const uint64_t lane_mul = A.lanemul->m64[lane];
+  const uint64_t pm1 = kP64 - 1;
+  for (uint64_t t = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave; t < tiles; t += nwaves) {
+    const uint64_t r =
+        dev::uniform_u64(wave_search(nreq64, t, lane, [&](uint64_t i) { return A.req[i].g1; }));
+    const ReqRec R = dev::const_load(A.req + r);
+    const uint64_t n = dev::const_load(&A.inst[R.inst].n);
+    const uint32_t j = (uint32_t)(t - R.g1);
+    uint64_t lg = R.x + (uint64_t)j * kTile64;  // x < p - 1 and j * 1024 < 2^42: one subtraction wraps it
+    if (lg >= pm1) lg -= pm1;
+    const uint64_t s_tile = dev::wave_pow_p61(A.lanemul->pow64, lg, lane);
+    const uint32_t len = tile_len64(R, j);
+    const uint64_t sum = tile_skip_sum64(s_tile, lane_mul, len, n, lane);
+    if (lane == 0) {
+      A.t64.s[t] = s_tile;
+      A.t64.sum[t] = sum;
     }
-    R.nchunks = (uint32_t)((R.ntiles + tiles_per_chunk - 1) / tiles_per_chunk);
-  }
-  uint64_t gtotal;
-  const uint64_t incl = plan_scan(R.nchunks, ws, &gtotal);
-  if (tid < nin) {
-    R.chunk_base = incl - R.nchunks;
-    req[r0 + tid] = R;
-  }
-  if (tid == 0) {
-    gbase[blockIdx.x] = gtotal;
-    __threadfence();
-    last = atomicAdd(&hdr->done, 1u) == gridDim.x - 1 ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // last workgroup: exclusive scan of the group totals, in place
-  const uint32_t ng = gridDim.x;
-  uint64_t carry = 0;
-  for (uint32_t base = 0; base < ng; base += kPlanGroup) {
-    const uint32_t j = base + tid;
-    const uint64_t v = j < ng ? __hip_atomic_load(gbase + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-    uint64_t rtotal;
-    const uint64_t in = plan_scan(v, ws, &rtotal);
-    if (j < ng) gbase[j] = carry + in - v;
-    carry += rtotal;
-  }
-  if (tid == 0) {
-    hdr->total_chunks = carry;
-    hdr->counter = 0;
-    hdr->done = 0;
   }
 }
 
-// Graph replays: every request continues where it ended.
-__global__ void __launch_bounds__(256) advance_kernel(HostReq *req, uint64_t nreq) {
-  uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nreq) req[r].k += req[r].count;
+// Scan per instance: one workgroup per width-64 request; the first request
+// of each instance in the batch (seg > 0) turns the tile sums of all of that
+// instance's requests into tile-start messages, starting from the
+// instance's committed message, and commits the message after the last
+// draw.  The instance's requests hold consecutive tiles.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+
+__global__ void __launch_bounds__(kScanThreads) scan64_kernel(GenArgs A) {
+  __shared__ uint64_t wtot[kScanThreads / 64];
+  const uint64_t r = blockIdx.x;
+  const ReqRec R = dev::const_load(A.req + r);
+  if (R.seg == 0) return;
+  const ReqRec L = dev::const_load(A.req + r + R.seg - 1);
+  const uint64_t n = dev::const_load(&A.inst[R.inst].n);
+  const uint64_t t0 = R.g1, t1 = L.g1 + L.ntiles;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint64_t carry = A.m64[R.inst];
+  for (uint64_t base = t0; base < t1; base += (uint64_t)kScanThreads * kScanPer) {
+    const uint64_t first = base + (uint64_t)tid * kScanPer;
+    uint64_t v[kScanPer];
+    uint64_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+      v[q] = first + q < t1 ? A.t64.sum[first + q] : 0;
+      tot = dev::addmod64(tot, v[q], n);
+    }
+    // exclusive prefix of the thread totals over the workgroup
+    const uint64_t ex = dev::wave_exclusive_mod(tot, n, lane);
+    if (lane == 63) wtot[w] = dev::addmod64(ex, tot, n);
+    __syncthreads();
+    uint64_t before = carry, all = carry;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+      if (k < (int)w) before = dev::addmod64(before, wtot[k], n);
+      all = dev::addmod64(all, wtot[k], n);
+    }
+    __syncthreads();
+    uint64_t m = dev::addmod64(before, ex, n);
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+      if (first + q < t1) A.t64.m[first + q] = m;
+      m = dev::addmod64(m, v[q], n);
+    }
+    carry = all;
+  }
+  if (tid == 0) A.m64[R.inst] = carry;
+}
+
+// ---------------------------------------------------------------------------
+// width-64 jumps off the table: sum of `count` consecutive skips
+// ---------------------------------------------------------------------------
+
+// partial[w] = sum, mod n, of the skips a^{t+1+i} mod p for the blocks of
+// 1024 draws i in [1024 b, 1024 (b + 1)) ∩ [0, count) that wave w takes
+// (b = w, w + nwaves, ...).
+__global__ void __launch_bounds__(256) skip_total64_kernel(uint64_t t, uint64_t count, uint64_t n,
+                                                           const LaneMul *lm, uint64_t *partial) {
+  const uint32_t lane = dev::lane_id();
+  const uint32_t wave = dev::uniform_u32(threadIdx.x / 64);
+  const uint64_t w = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / 64);
+  const uint64_t pm1 = kP64 - 1;
+  const uint64_t lane_mul = lm->m64[lane];
+  const uint64_t nblk = (count + kTile64 - 1) / kTile64;
+  uint64_t acc = 0;
+  for (uint64_t b = w; b < nblk; b += nwaves) {
+    const uint64_t off = (b * kTile64) % pm1;
+    uint64_t lg = t + off;
+    if (lg >= pm1) lg -= pm1;
+    const uint64_t s0 = dev::wave_pow_p61(lm->pow64, lg, lane);
+    // the last block holds what is left (an equality test: see tile_len64)
+    const uint32_t len = b + 1 == nblk ? (uint32_t)(count - (nblk - 1) * kTile64) : (uint32_t)kTile64;
+    acc = dev::addmod64(acc, tile_skip_sum64(s0, lane_mul, len, n, lane), n);
+  }
+  if (lane == 0) partial[w] = acc;
+}
+
+// *m = *m + sign * (sum of the partials + extra) mod n (one wave).
+__global__ void __launch_bounds__(64) skip_total64_apply(const uint64_t *partial, uint64_t nparts, uint64_t n,
+                                                         uint64_t extra, int sign, uint64_t *m) {
+  const uint32_t lane = threadIdx.x;
+  uint64_t acc = 0;
+  for (uint64_t i = lane; i < nparts; i += 64) acc = dev::addmod64(acc, partial[i], n);
+  acc = dev::wave_sum_mod(acc, n);
+  acc = dev::addmod64(acc, extra, n);
+  if (lane == 0) {
+    const uint64_t v = *m;
+    *m = sign > 0 ? dev::addmod64(v, acc, n) : (v >= acc ? v - acc : v + (n - acc));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -267,11 +377,11 @@ struct Enc32 {
 template <int UNROLL, int EK, int OUT, bool MASKED>
 __device__ __forceinline__ void passC32(const uint32_t *L, uint32_t lane, const Enc32 &K, uint32_t *c32, double *rr,
                                         uint32_t t_lo, uint32_t t_hi) {
-  const uint32_t *src = L + (lane >> 5) * kRow + (lane & 31);
+  const uint32_t *src = L + (lane >> 5) * kRow32 + (lane & 31);
   const uint32_t span = t_hi - t_lo;
 #pragma unroll UNROLL
-  for (int i = 0; i < kRun; ++i) {
-    const uint32_t m = src[i * 2 * kRow];
+  for (int i = 0; i < kRun32; ++i) {
+    const uint32_t m = src[i * 2 * kRow32];
     if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
       const uint32_t c = dev::encrypt32<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
       if (OUT & kOutC) c32[i * 64] = c;
@@ -319,7 +429,7 @@ __device__ void run_chunk32(const GenArgs &A, const InstRec &I, const ReqRec &R,
   for (uint64_t g = g_begin; g < g_end; ++g) {
     const uint64_t q = g >> kTileShift32;
     const uint32_t j = (uint32_t)(g & (kTilesPerPeriod32 - 1));
-    const uint64_t x0 = q * pm1 + (uint64_t)j * kTile;
+    const uint64_t x0 = q * pm1 + (uint64_t)j * kTile32;
     if (!carried || j == 0) {
       // state at x0 from the universal table (eq. (7)):
       // m = mbase + q p(p-1)/2 + U(j*2048) mod n,  s = a^{j*2048} mod p
@@ -330,11 +440,11 @@ __device__ void run_chunk32(const GenArgs &A, const InstRec &I, const ReqRec &R,
       m_t = dev::addmod32(mu, mq, n);
     }
     // ---- pass A: skips of this lane's run, their sum
-    uint32_t *row = L + lane * kRow;
+    uint32_t *row = L + lane * kRow32;
     uint32_t s = dev::mulmod_p31(s_t, lane_mul);
     uint64_t sum = 0;
 #pragma unroll 8
-    for (int i = 0; i < kRun; ++i) {
+    for (int i = 0; i < kRun32; ++i) {
       s = dev::mulmod_p31(kA32, s);
       row[i] = s;
       sum = dev::acc_u32(sum, s, one);
@@ -348,7 +458,7 @@ __device__ void run_chunk32(const GenArgs &A, const InstRec &I, const ReqRec &R,
     }
     uint32_t m = dev::mont32(dev::redc32(incl - sum + m_t, n, ninv), r2, n, ninv);
 #pragma unroll 8
-    for (int i = 0; i < kRun; ++i) {
+    for (int i = 0; i < kRun32; ++i) {
       m = dev::addmod32(m, row[i], n);
       row[i] = m;
     }
@@ -359,17 +469,17 @@ __device__ void run_chunk32(const GenArgs &A, const InstRec &I, const ReqRec &R,
     dev::wave_lds_sync();
     // ---- pass C: encrypt in draw order
     const uint64_t tile_first = x0;  // draw t of this tile comes from state index x0 + t
-    const uint64_t req_end = R.k + R.count;  // one past the last state index used
-    uint32_t t_lo = R.k > tile_first ? (uint32_t)(R.k - tile_first) : 0u;
+    const uint64_t req_end = R.x + R.count;  // one past the last state index used
+    uint32_t t_lo = R.x > tile_first ? (uint32_t)(R.x - tile_first) : 0u;
     uint64_t hi1 = req_end - tile_first;
-    uint64_t hi2 = pm1 - (uint64_t)j * kTile;
-    uint64_t hi = min(min(hi1, hi2), (uint64_t)kTile);
+    uint64_t hi2 = pm1 - (uint64_t)j * kTile32;
+    uint64_t hi = min(min(hi1, hi2), (uint64_t)kTile32);
     uint32_t t_hi = (uint32_t)hi;
-    const int64_t base = (int64_t)R.out_off + (int64_t)(tile_first - R.k) + (int64_t)lane;
+    const int64_t base = (int64_t)R.out_off + (int64_t)(tile_first - R.x) + (int64_t)lane;
     uint32_t *c32 = A.out_c32 ? A.out_c32 + base : nullptr;
     double *rr = A.out_r ? A.out_r + base : nullptr;
     const Enc32 K{n, ninv, kc, e, ebits, den, rcp};
-    if (t_lo == 0 && t_hi == (uint32_t)kTile)
+    if (t_lo == 0 && t_hi == (uint32_t)kTile32)
       passC32_e<UNROLL, false>(ekind, L, lane, K, c32, rr, t_lo, t_hi);
     else
       passC32_e<1, true>(ekind, L, lane, K, c32, rr, t_lo, t_hi);
@@ -383,15 +493,16 @@ struct Enc64 {
   double den, rcp;
 };
 
+// Pass C, width 64: draw t = i*64 + lane lives at LDS row t / 16, column
+// t % 16, i.e. row 4 i + lane / 16.  MASKED tiles write only t < t_hi.
 template <int UNROLL, int EK, int OUT, bool MASKED>
 __device__ __forceinline__ void passC64(const uint64_t *L, uint32_t lane, const Enc64 &K, uint64_t *c64, double *rr,
-                                        uint32_t t_lo, uint32_t t_hi) {
-  const uint64_t *src = L + (lane >> 5) * kRow + (lane & 31);
-  const uint32_t span = t_hi - t_lo;
+                                        uint32_t t_hi) {
+  const uint64_t *src = L + (lane >> 4) * kRow64 + (lane & 15);
 #pragma unroll UNROLL
-  for (int i = 0; i < kRun; ++i) {
-    const uint64_t m = src[i * 2 * kRow];
-    if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
+  for (int i = 0; i < kRun64; ++i) {
+    const uint64_t m = src[i * 4 * kRow64];
+    if (!MASKED || ((uint32_t)i * 64u + lane < t_hi)) {
       const uint64_t c = dev::encrypt64<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
       if (OUT & kOutC) c64[i * 64] = c;
       if (OUT & kOutR) rr[i * 64] = dev::uniform64(c, K.den, K.rcp);
@@ -401,86 +512,71 @@ __device__ __forceinline__ void passC64(const uint64_t *L, uint32_t lane, const 
 
 template <int UNROLL, int EK, bool MASKED>
 __device__ __forceinline__ void passC64_out(const uint64_t *L, uint32_t lane, const Enc64 &K, uint64_t *c64,
-                                            double *rr, uint32_t t_lo, uint32_t t_hi) {
-  if (c64 && rr) passC64<UNROLL, EK, kOutC | kOutR, MASKED>(L, lane, K, c64, rr, t_lo, t_hi);
-  else if (rr) passC64<UNROLL, EK, kOutR, MASKED>(L, lane, K, c64, rr, t_lo, t_hi);
-  else if (c64) passC64<UNROLL, EK, kOutC, MASKED>(L, lane, K, c64, rr, t_lo, t_hi);
+                                            double *rr, uint32_t t_hi) {
+  if (c64 && rr) passC64<UNROLL, EK, kOutC | kOutR, MASKED>(L, lane, K, c64, rr, t_hi);
+  else if (rr) passC64<UNROLL, EK, kOutR, MASKED>(L, lane, K, c64, rr, t_hi);
+  else if (c64) passC64<UNROLL, EK, kOutC, MASKED>(L, lane, K, c64, rr, t_hi);
 }
 
 template <int UNROLL, bool MASKED>
 __device__ __forceinline__ void passC64_e(int ekind, const uint64_t *L, uint32_t lane, const Enc64 &K, uint64_t *c64,
-                                          double *rr, uint32_t t_lo, uint32_t t_hi) {
+                                          double *rr, uint32_t t_hi) {
   switch (ekind) {
-    case 9: passC64_out<UNROLL, 9, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
-    case 17: passC64_out<UNROLL, 17, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
-    case 3: passC64_out<UNROLL, 3, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
-    case 5: passC64_out<UNROLL, 5, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
-    default: passC64_out<UNROLL, 0, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
+    case 9: passC64_out<UNROLL, 9, MASKED>(L, lane, K, c64, rr, t_hi); break;
+    case 17: passC64_out<UNROLL, 17, MASKED>(L, lane, K, c64, rr, t_hi); break;
+    case 3: passC64_out<UNROLL, 3, MASKED>(L, lane, K, c64, rr, t_hi); break;
+    case 5: passC64_out<UNROLL, 5, MASKED>(L, lane, K, c64, rr, t_hi); break;
+    default: passC64_out<UNROLL, 0, MASKED>(L, lane, K, c64, rr, t_hi); break;
   }
 }
 
+// Width 64: tile j of the request covers its draws [1024 j, 1024 (j + 1));
+// the state before the chunk's first tile comes from the scan, later tiles
+// continue from lane 63's last state.
 template <int UNROLL>
 __device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R, uint64_t chunk, uint64_t *L,
                             uint32_t lane) {
-  const uint64_t n = I.n, ninv = I.ninv, kc = I.kcorr, r2 = I.r2;
+  const uint64_t n = I.n, ninv = I.ninv, kc = I.kcorr;
   const uint64_t e = I.e;
   const int ebits = (int)I.ebits, ekind = (int)I.ekind;
   const double den = I.den;
   const uint64_t lane_mul = A.lanemul->m64[lane];
 
-  const uint64_t g_begin = R.g1 + chunk * A.tiles_per_chunk;
-  const uint64_t g_end = min(g_begin + A.tiles_per_chunk, R.g1 + R.ntiles);
-  uint64_t m_t = 0, s_t = 0;
-  bool carried = false;
-  for (uint64_t g = g_begin; g < g_end; ++g) {
-    const uint64_t x0 = g * kTile;  // width-64 indices never reach the end of the skip period
-    if (!carried) {
-      dev::W128 u;
-      u.lo = A.tab.u64_lo[g];
-      u.hi = A.tab.u64_hi[g];
-      s_t = A.tab.s64[g];
-      uint64_t mu = dev::mont64(dev::redc64(u, n, ninv), r2, n, ninv);
-      m_t = dev::addmod64(mu, I.mbase, n);
-    }
-    uint64_t *row = L + lane * kRow;
+  const uint32_t j_begin = (uint32_t)chunk * A.tiles_per_chunk;
+  const uint32_t j_end = min(j_begin + A.tiles_per_chunk, R.ntiles);
+  uint64_t m_t = dev::uniform_u64(dev::const_load(A.t64.m + R.g1 + j_begin));
+  uint64_t s_t = dev::uniform_u64(dev::const_load(A.t64.s + R.g1 + j_begin));
+  for (uint32_t j = j_begin; j < j_end; ++j) {
+    // ---- pass A
+    uint64_t *row = L + lane * kRow64;
     uint64_t s = dev::mulmod_p61(s_t, lane_mul);
     uint64_t sum = 0;
 #pragma unroll 4
-    for (int i = 0; i < kRun; ++i) {
+    for (int i = 0; i < kRun64; ++i) {
       s = dev::mulmod_p61(kA64, s);
       row[i] = s;
       sum = dev::addmod64(sum, s, n);
     }
-    uint64_t incl = sum;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      uint64_t v = dev::shfl_up_u64(incl, d);
-      if ((int)lane >= d) incl = dev::addmod64(incl, v, n);
-    }
-    // exclusive prefix = incl - sum (mod n)
-    uint64_t pre = incl >= sum ? incl - sum : incl + (n - sum);
-    uint64_t m = dev::addmod64(m_t, pre, n);
+    // ---- pass B
+    uint64_t m = dev::addmod64(m_t, dev::wave_exclusive_mod(sum, n, lane), n);
 #pragma unroll 4
-    for (int i = 0; i < kRun; ++i) {
+    for (int i = 0; i < kRun64; ++i) {
       m = dev::addmod64(m, row[i], n);
       row[i] = m;
     }
     m_t = dev::shfl_u64(m, 63);
     s_t = dev::shfl_u64(s, 63);
-    carried = true;
     dev::wave_lds_sync();
-    const uint64_t req_end = R.k + R.count;
-    uint32_t t_lo = R.k > x0 ? (uint32_t)(R.k - x0) : 0u;
-    uint64_t hi = min(req_end - x0, (uint64_t)kTile);
-    uint32_t t_hi = (uint32_t)hi;
-    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.k) + (int64_t)lane;
+    // ---- pass C
+    const uint32_t t_hi = tile_len64(R, j);
+    const uint64_t base = R.out_off + (uint64_t)j * kTile64 + lane;
     uint64_t *c64 = A.out_c64 ? A.out_c64 + base : nullptr;
     double *rr = A.out_r ? A.out_r + base : nullptr;
     const Enc64 K{n, ninv, kc, e, ebits, den, I.rcp};
-    if (t_lo == 0 && t_hi == (uint32_t)kTile)
-      passC64_e<UNROLL, false>(ekind, L, lane, K, c64, rr, t_lo, t_hi);
+    if (t_hi == (uint32_t)kTile64)
+      passC64_e<UNROLL, false>(ekind, L, lane, K, c64, rr, t_hi);
     else
-      passC64_e<1, true>(ekind, L, lane, K, c64, rr, t_lo, t_hi);
+      passC64_e<1, true>(ekind, L, lane, K, c64, rr, t_hi);
     dev::wave_lds_sync();
   }
 }
@@ -496,7 +592,7 @@ __device__ __forceinline__ void passCS32(uint32_t m, uint32_t step, uint32_t lan
                                          double *rr, uint32_t t_lo, uint32_t t_hi) {
   const uint32_t span = t_hi - t_lo;
 #pragma unroll UNROLL
-  for (int i = 0; i < kRun; ++i) {
+  for (int i = 0; i < kTileCS / 64; ++i) {
     if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
       const uint32_t c = dev::encrypt32<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
       if (OUT & kOutC) c32[i * 64] = c;
@@ -534,7 +630,7 @@ __device__ void run_chunk32_cs(const GenArgs &A, const InstRec &I, const ReqRec 
   const uint64_t g_begin = R.g1 + chunk * A.tiles_per_chunk;
   const uint64_t g_end = min(g_begin + A.tiles_per_chunk, R.g1 + R.ntiles);
   for (uint64_t g = g_begin; g < g_end; ++g) {
-    const uint64_t x0 = g * kTile;
+    const uint64_t x0 = g * kTileCS;
     // lane's first state index v = x0 + 1 + lane; v b mod n by Montgomery:
     // bring hi(v) below n, then REDC(v) times b R^2
     const uint64_t v = x0 + 1 + lane;
@@ -542,13 +638,13 @@ __device__ void run_chunk32_cs(const GenArgs &A, const InstRec &I, const ReqRec 
     vh = vh >= n ? vh - n : vh;
     const uint64_t vr = ((uint64_t)vh << 32) | (uint32_t)v;
     const uint32_t m = dev::addmod32(mbase, dev::mont32(dev::redc32(vr, n, ninv), bR2, n, ninv), n);
-    const uint64_t req_end = R.k + R.count;
-    const uint32_t t_lo = R.k > x0 ? (uint32_t)(R.k - x0) : 0u;
-    const uint32_t t_hi = (uint32_t)min(req_end - x0, (uint64_t)kTile);
-    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.k) + (int64_t)lane;
+    const uint64_t req_end = R.x + R.count;
+    const uint32_t t_lo = R.x > x0 ? (uint32_t)(R.x - x0) : 0u;
+    const uint32_t t_hi = (uint32_t)min(req_end - x0, (uint64_t)kTileCS);
+    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.x) + (int64_t)lane;
     uint32_t *c32 = A.out_c32 ? A.out_c32 + base : nullptr;
     double *rr = A.out_r ? A.out_r + base : nullptr;
-    if (t_lo == 0 && t_hi == (uint32_t)kTile)
+    if (t_lo == 0 && t_hi == (uint32_t)kTileCS)
       passCS32_e<UNROLL, false>((int)I.ekind, m, step, lane, K, c32, rr, t_lo, t_hi);
     else
       passCS32_e<1, true>((int)I.ekind, m, step, lane, K, c32, rr, t_lo, t_hi);
@@ -560,7 +656,7 @@ __device__ __forceinline__ void passCS64(uint64_t m, uint64_t step, uint32_t lan
                                          double *rr, uint32_t t_lo, uint32_t t_hi) {
   const uint32_t span = t_hi - t_lo;
 #pragma unroll UNROLL
-  for (int i = 0; i < kRun; ++i) {
+  for (int i = 0; i < kTileCS / 64; ++i) {
     if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
       const uint64_t c = dev::encrypt64<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
       if (OUT & kOutC) c64[i * 64] = c;
@@ -597,59 +693,46 @@ __device__ void run_chunk64_cs(const GenArgs &A, const InstRec &I, const ReqRec 
   const uint64_t g_begin = R.g1 + chunk * A.tiles_per_chunk;
   const uint64_t g_end = min(g_begin + A.tiles_per_chunk, R.g1 + R.ntiles);
   for (uint64_t g = g_begin; g < g_end; ++g) {
-    const uint64_t x0 = g * kTile;
+    const uint64_t x0 = g * kTileCS;
     dev::W128 v;
     v.lo = x0 + 1 + lane;  // hi word 0 < n, so REDC applies
     v.hi = 0;
     const uint64_t m = dev::addmod64(I.mbase, dev::mont64(dev::redc64(v, n, ninv), I.bR2, n, ninv), n);
-    const uint64_t req_end = R.k + R.count;
-    const uint32_t t_lo = R.k > x0 ? (uint32_t)(R.k - x0) : 0u;
-    const uint32_t t_hi = (uint32_t)min(req_end - x0, (uint64_t)kTile);
-    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.k) + (int64_t)lane;
+    const uint64_t req_end = R.x + R.count;
+    const uint32_t t_lo = R.x > x0 ? (uint32_t)(R.x - x0) : 0u;
+    const uint32_t t_hi = (uint32_t)min(req_end - x0, (uint64_t)kTileCS);
+    const int64_t base = (int64_t)R.out_off + (int64_t)(x0 - R.x) + (int64_t)lane;
     uint64_t *c64 = A.out_c64 ? A.out_c64 + base : nullptr;
     double *rr = A.out_r ? A.out_r + base : nullptr;
-    if (t_lo == 0 && t_hi == (uint32_t)kTile)
+    if (t_lo == 0 && t_hi == (uint32_t)kTileCS)
       passCS64_e<UNROLL, false>((int)I.ekind, m, I.b64, lane, K, c64, rr, t_lo, t_hi);
     else
       passCS64_e<1, true>((int)I.ekind, m, I.b64, lane, K, c64, rr, t_lo, t_hi);
   }
 }
 
-// First chunk of request r in the batch.
-__device__ __forceinline__ uint64_t chunk_base_of(const GenArgs &A, uint64_t r) {
-  return A.gbase[r / kPlanGroup] + A.req[r].chunk_base;
-}
-
-// Wave-cooperative search: the request r whose first chunk is <= c < the next
-// request's (the last such r when empty requests share a first chunk).
-__device__ __forceinline__ uint64_t find_request(const GenArgs &A, uint64_t c, uint32_t lane) {
-  uint64_t lo = 0, hi = A.nreq;
-  while (hi - lo > 1) {
-    uint64_t step = (hi - lo + 63) / 64;
-    uint64_t idx = lo + (uint64_t)lane * step;
-    bool le = idx < hi && chunk_base_of(A, idx) <= c;
-    uint64_t mask = __ballot(le);
-    uint64_t k = (uint64_t)__popcll(mask);
-    lo = lo + (k - 1) * step;
-    hi = min(lo + step, hi);
+// One chunk of request r.
+template <int UNROLL, bool HAS64>
+__device__ __forceinline__ void run_chunk(const GenArgs &A, const ReqRec &R, uint64_t chunk, uint64_t *L,
+                                          uint32_t lane) {
+  const InstRec I = dev::const_load(A.inst + R.inst);
+  if (I.sched == kSchedConstant) {
+    if (HAS64 && I.width == 64) run_chunk64_cs<UNROLL>(A, I, R, chunk, lane);
+    else run_chunk32_cs<UNROLL>(A, I, R, chunk, lane);
+  } else if (HAS64 && I.width == 64) {
+    run_chunk64<UNROLL>(A, I, R, chunk, L, lane);
+  } else {
+    run_chunk32<UNROLL>(A, I, R, chunk, reinterpret_cast<uint32_t *>(L), lane);
   }
-  return lo;
 }
-
-template <bool HAS64>
-struct WaveLds {
-  using T = typename std::conditional<HAS64, uint64_t, uint32_t>::type;
-  static constexpr int kWords = 64 * kRow;
-};
 
 template <int BLOCK, int UNROLL, bool HAS64>
 __global__ void __launch_bounds__(BLOCK) gen_persistent(GenArgs A) {
-  using LT = typename WaveLds<HAS64>::T;
-  __shared__ LT lds[BLOCK / 64][WaveLds<HAS64>::kWords];
+  __shared__ uint64_t lds[BLOCK / 64][HAS64 ? kLdsWords64 : kLdsWords32];
   const uint32_t lane = dev::lane_id();
   const uint32_t wave = dev::uniform_u32(threadIdx.x / 64);  // wave-uniform: keeps chunk math scalar
-  LT *L = lds[wave];
-  const uint64_t total = dev::uniform_u64(A.hdr->total_chunks);
+  uint64_t *L = lds[wave];
+  const uint64_t total = dev::uniform_u64(dev::const_load(&A.hdr->total_chunks));
   // The first chunk of every wave is its global wave index; later chunks come
   // from the shared counter, offset by the number of waves.  Small batches
   // therefore need no atomics, and large ones avoid the start-up burst.
@@ -657,41 +740,33 @@ __global__ void __launch_bounds__(BLOCK) gen_persistent(GenArgs A) {
   uint64_t c = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
   for (;;) {
     if (c >= total) break;
-    const uint64_t r = dev::uniform_u64(find_request(A, c, lane));
+    const uint64_t r =
+        dev::uniform_u64(wave_search(A.nreq, c, lane, [&](uint64_t i) { return A.req[i].chunk_base; }));
     const ReqRec R = dev::const_load(A.req + r);
-    const InstRec I = dev::const_load(A.inst + R.inst);
-    const uint64_t chunk = c - (dev::const_load(A.gbase + r / kPlanGroup) + R.chunk_base);
-    if (I.sched == kSchedConstant) {
-      if (HAS64 && I.width == 64) run_chunk64_cs<UNROLL>(A, I, R, chunk, lane);
-      else run_chunk32_cs<UNROLL>(A, I, R, chunk, lane);
-    } else if (HAS64 && I.width == 64) {
-      run_chunk64<UNROLL>(A, I, R, chunk, reinterpret_cast<uint64_t *>(L), lane);
-    } else {
-      run_chunk32<UNROLL>(A, I, R, chunk, reinterpret_cast<uint32_t *>(L), lane);
-    }
+    run_chunk<UNROLL, HAS64>(A, R, c - R.chunk_base, L, lane);
     uint32_t next = 0;
-    if (lane == 0) next = atomicAdd(&A.hdr->counter, 1u);
+    if (lane == 0) next = atomicAdd(&A.ctr->counter, 1u);
     c = (uint64_t)nwaves + dev::uniform_u32((uint32_t)__shfl((int)next, 0, 64));
+  }
+  // Every wave counts itself out; the last one leaves the counter at zero
+  // for the next launch (every other wave has made its last grab by then).
+  if (lane == 0) {
+    const uint32_t prev = atomicAdd(&A.ctr->done, 1u);
+    if (prev == nwaves - 1) {
+      __hip_atomic_store(&A.ctr->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&A.ctr->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
 // One grid per request: block b (one wave) takes chunk b of request `r`.
 template <int UNROLL, bool HAS64>
 __global__ void __launch_bounds__(64) gen_plain(GenArgs A, uint64_t r) {
-  using LT = typename WaveLds<HAS64>::T;
-  __shared__ LT lds[WaveLds<HAS64>::kWords];
+  __shared__ uint64_t lds[HAS64 ? kLdsWords64 : kLdsWords32];
   const uint32_t lane = dev::lane_id();
   const ReqRec R = dev::const_load(A.req + r);
   if ((uint64_t)blockIdx.x >= R.nchunks) return;
-  const InstRec I = dev::const_load(A.inst + R.inst);
-  if (I.sched == kSchedConstant) {
-    if (HAS64 && I.width == 64) run_chunk64_cs<UNROLL>(A, I, R, blockIdx.x, lane);
-    else run_chunk32_cs<UNROLL>(A, I, R, blockIdx.x, lane);
-  } else if (HAS64 && I.width == 64) {
-    run_chunk64<UNROLL>(A, I, R, blockIdx.x, reinterpret_cast<uint64_t *>(lds), lane);
-  } else {
-    run_chunk32<UNROLL>(A, I, R, blockIdx.x, reinterpret_cast<uint32_t *>(lds), lane);
-  }
+  run_chunk<UNROLL, HAS64>(A, R, blockIdx.x, lds, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -725,20 +800,41 @@ hipError_t launch_build_records(const uint64_t *n, const uint64_t *e, uint64_t c
   return hipGetLastError();
 }
 
-hipError_t launch_plan(const InstRec *inst, const HostReq *src, ReqRec *req, uint64_t nreq, uint64_t *gbase,
-                       PlanHdr *hdr, uint32_t tiles_per_chunk, hipStream_t st) {
-  if (nreq == 0) return hipErrorInvalidValue;
-  const uint64_t groups = (nreq + kPlanGroup - 1) / kPlanGroup;
-  if (groups > 0x7fffffffull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(plan_kernel, dim3((unsigned)groups), dim3(kPlanGroup), 0, st, inst, src, req, nreq, gbase, hdr,
-                     tiles_per_chunk);
+hipError_t launch_position64(const InstRec *inst, const uint32_t *ids, const uint64_t *m0, const uint64_t *ta,
+                             const uint64_t *tb, uint64_t count, const uint64_t *u_lo, const uint64_t *u_hi,
+                             const uint64_t *u_s, uint64_t *m64, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  unsigned blocks = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(position64_kernel, dim3(blocks), dim3(256), 0, st, inst, ids, m0, ta, tb, count, u_lo, u_hi, u_s,
+                     m64);
   return hipGetLastError();
 }
 
-hipError_t launch_advance(HostReq *req, uint64_t nreq, hipStream_t st) {
-  if (nreq == 0) return hipSuccess;
-  unsigned blocks = (unsigned)((nreq + 255) / 256);
-  hipLaunchKernelGGL(advance_kernel, dim3(blocks), dim3(256), 0, st, req, nreq);
+hipError_t launch_tiles64_reduce(const GenArgs &A, uint64_t tiles64, unsigned max_blocks, hipStream_t st) {
+  if (tiles64 == 0) return hipSuccess;
+  const uint64_t want = (tiles64 + 3) / 4;
+  const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, max_blocks));
+  hipLaunchKernelGGL(reduce64_kernel, dim3(blocks), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_tiles64_scan(const GenArgs &A, uint64_t nreq64, hipStream_t st) {
+  if (nreq64 == 0) return hipSuccess;
+  if (nreq64 > 0x7fffffffull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scan64_kernel, dim3((unsigned)nreq64), dim3(kScanThreads), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_skip_total64(uint64_t t, uint64_t count, uint64_t n, const LaneMul *lm, uint64_t *partial,
+                               unsigned blocks, uint64_t extra, int sign, uint64_t *m, hipStream_t st) {
+  if (blocks == 0) return hipErrorInvalidValue;
+  if (count > 0) {
+    hipLaunchKernelGGL(skip_total64_kernel, dim3(blocks), dim3(256), 0, st, t, count, n, lm, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(skip_total64_apply, dim3(1), dim3(64), 0, st, partial, count > 0 ? (uint64_t)blocks * 4 : 0, n,
+                     extra, sign, m);
   return hipGetLastError();
 }
 

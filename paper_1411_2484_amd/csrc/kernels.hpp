@@ -14,12 +14,23 @@ hipError_t launch_seed_prime_flags(uint64_t seed, uint64_t j0, uint64_t count, i
                                    hipStream_t st);
 hipError_t launch_build_records(const uint64_t *n, const uint64_t *e, uint64_t count, int width, InstRec *out,
                                 hipStream_t st);
-// src: nreq host-written requests, device-accessible (pinned host memory or
-// device memory); req: nreq device records; gbase: ceil(nreq / kPlanGroup)
-// words; hdr->done must be 0 (every plan leaves it so).
-hipError_t launch_plan(const InstRec *inst, const HostReq *src, ReqRec *req, uint64_t nreq, uint64_t *gbase,
-                       PlanHdr *hdr, uint32_t tiles_per_chunk, hipStream_t st);
-hipError_t launch_advance(HostReq *req, uint64_t nreq, hipStream_t st);
+// m64[ids[i]] = m0[i] + U(ta[i]) - U(tb[i]) mod n[ids[i]] from the width-64
+// positioning table (ta, tb < kTab64Range; U(t) = sum_{j<=t} (a^j mod p));
+// m0, ta, tb may be NULL (zeros).  All arrays are device arrays of `count`
+// entries.
+hipError_t launch_position64(const InstRec *inst, const uint32_t *ids, const uint64_t *m0, const uint64_t *ta,
+                             const uint64_t *tb, uint64_t count, const uint64_t *u_lo, const uint64_t *u_hi,
+                             const uint64_t *u_s, uint64_t *m64, hipStream_t st);
+// Width-64 tile starts of a batch: the reduce writes each tile's start skip
+// and skip sum (hdr->tiles64 tiles, grid-stride with at most max_blocks
+// blocks); the scan turns the sums into tile-start messages per instance and
+// commits the instances' messages (one workgroup per width-64 request).
+hipError_t launch_tiles64_reduce(const GenArgs &A, uint64_t tiles64, unsigned max_blocks, hipStream_t st);
+hipError_t launch_tiles64_scan(const GenArgs &A, uint64_t nreq64, hipStream_t st);
+// *m = *m + sign * (sum_{i=1}^{count} (a^{t+i} mod p) + extra) mod n, with
+// `blocks` 256-thread blocks writing blocks * 4 partial sums to `partial`.
+hipError_t launch_skip_total64(uint64_t t, uint64_t count, uint64_t n, const LaneMul *lm, uint64_t *partial,
+                               unsigned blocks, uint64_t extra, int sign, uint64_t *m, hipStream_t st);
 // grid: number of blocks; block: 64/128/256/512 threads; unroll: 1/2/4.
 hipError_t launch_persistent(const GenArgs &A, unsigned grid, int block, int unroll, bool has64, hipStream_t st);
 // One plain grid of `grid` one-wave blocks for request r.

@@ -1,6 +1,6 @@
-// Host runtime behind include/phprng.h: instance tables, seeding, the
-// universal skip-prefix tables, request planning and kernel launches,
-// jumps and state restore, captured repeat draws.
+// Host runtime behind include/phprng.h: instance tables, seeding, the skip
+// tables, request planning and kernel launches, jumps and state restore and
+// captured repeat draws.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,9 +8,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <unordered_set>
 #include <vector>
 
@@ -26,12 +29,15 @@ namespace {
 struct HostInst {
   uint64_t n, e;
   int width;
-  uint64_t mbase;  // m at internal index x = mbase + q p(p-1)/2 + U(r) mod n (constant skip: mbase + x b)
-  uint64_t x;      // internal index of the current state
-  int64_t kofs;    // reported position k = x - kofs
   uint32_t sched = kSchedSkipLcg;
-  uint64_t b = 0;  // constant skip
+  uint64_t b = 0;      // constant skip
+  uint64_t mbase = 0;  // width 32: m at internal index x is mbase + q p(p-1)/2 + U(r) mod n; constant skip: m_0
+  uint64_t x = 0;      // width 32 / constant skip: internal index of the current state;
+                       // width 64 pseudorandom skip: skip log t of the current state (s = a^t mod p), < p - 1
+  uint64_t k = 0;      // position reported to the caller
 };
+
+bool lcg64(const HostInst &h) { return h.width == 64 && h.sched == kSchedSkipLcg; }
 
 const SkipGroup &group(int width) {
   static const SkipGroup g32(kP32, kA32);
@@ -61,46 +67,107 @@ int bit_length(uint64_t v) {
   return b;
 }
 
+// Requests the planning scratch holds before it grows.
+constexpr uint64_t kPlanReserve = 16384;
+
+// Width-64 draws per request: tiles are counted in 32 bits.
+constexpr uint64_t kMaxCount64 = (uint64_t)kTile64 << 32;
+// Width-64 jumps off the positioning table sum the skips on the device; the
+// remainder of a jump modulo the skip period (or its complement) must stay
+// below this many draws.
+constexpr uint64_t kJumpMax = 1ull << 42;
+constexpr unsigned kJumpBlocks = 2048;
+
+// Launch-shape classes: batches of width-32 requests only, width-64 only, or
+// both.
+enum { kMix32 = 0, kMix64 = 1, kMixBoth = 2 };
+
+// Process-wide cache of autotuned shapes, keyed by (architecture, compute
+// units, class): a new context on the same kind of device starts from it.
+struct TuneKey {
+  std::string arch;
+  int cus;
+  int cls;
+  bool operator<(const TuneKey &o) const { return std::tie(arch, cus, cls) < std::tie(o.arch, o.cus, o.cls); }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, phprng_tuning> g_tune_cache;
+
+uint64_t add_u64_mod(uint64_t x, uint64_t y, uint64_t m) {  // (x + y) mod m, x, y < m
+  const uint64_t s = x + y;
+  return (s < x || s >= m) ? s - m : s;
+}
+
 }  // namespace
 
 struct phprng_graph {
   phprng_ctx *ctx = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  HostReq *d_src = nullptr;  // requests; the graph's last node advances them
-  ReqRec *d_req = nullptr;
-  uint64_t *d_gbase = nullptr;
-  PlanHdr *d_hdr = nullptr;
-  std::vector<uint32_t> inst;
-  std::vector<uint64_t> count;
+  uint8_t *d_blk = nullptr;  // batch header + requests, refreshed before every launch
+  WorkCtr *d_ctr = nullptr;
+  uint64_t *d_t64 = nullptr;  // width-64 tile state
+  hipEvent_t done = nullptr;  // after the previous launch
+  bool launched = false;
+  std::vector<phprng_request> reqs;
+  uint64_t nreq64 = 0, tiles64 = 0;
+  uint32_t tpc = 1;
+  bool has64 = false;
+  ~phprng_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (d_blk) (void)hipFree(d_blk);
+    if (d_ctr) (void)hipFree(d_ctr);
+    if (d_t64) (void)hipFree(d_t64);
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
+// Result of planning a request list.
+struct Plan {
+  uint64_t nreq = 0;
+  uint64_t nreq64 = 0;   // width-64 pseudorandom-skip requests (first in the staging order)
+  uint64_t tiles64 = 0;  // their tiles
+  uint64_t tiles = 0;    // all tiles
+  uint64_t total_chunks = 0;
+  uint32_t tpc = 1;
+  bool has32 = false, has64 = false;
+  int cls = kMix32;
 };
 
 struct phprng_ctx {
   int device = 0;
   int num_cus = 0;
+  std::string arch;
   uint64_t max_instances = 0;
   std::vector<HostInst> inst;
   InstRec *d_inst = nullptr;
   LaneMul *d_lanemul = nullptr;
-  // universal skip-prefix tables: host mirrors and device copies
+  uint64_t *d_m64 = nullptr;  // width-64 message at each instance's committed position
+  // universal width-32 skip-prefix table: host mirror and device copy
   std::vector<uint64_t> u32;
   std::vector<uint32_t> s32;
-  std::vector<u128> u64;
-  std::vector<uint64_t> s64;
   uint64_t *d_u32 = nullptr;
   uint32_t *d_s32 = nullptr;
+  // width-64 positioning table (device only), built with the first width-64 instance
   uint64_t *d_u64lo = nullptr, *d_u64hi = nullptr, *d_s64 = nullptr;
   bool have64 = false;
+  uint64_t *d_partial = nullptr;  // jump partial sums
+  // Width-64 messages live on the device: each batch's scan reads and
+  // commits them.  Scans of successive calls are ordered by this event, so
+  // that calls on different streams still continue each stream in call order.
+  hipEvent_t chain_ev = nullptr;
+  bool chain_pending = false;
   // Request staging: a ring of slots so that consecutive calls (possibly on
-  // different streams) never overwrite a request list still in use.  A slot
+  // different streams) never overwrite a request block still in use.  A slot
   // is reused only after the event recorded behind its last kernel.
   struct Slot {
-    HostReq *h_req = nullptr;            // pinned, mapped
-    const HostReq *h_req_dev = nullptr;  // h_req's address for kernels
-    ReqRec *d_req = nullptr;
-    uint64_t *d_gbase = nullptr;         // ceil(cap / kPlanGroup) words
+    uint8_t *h_blk = nullptr;  // pinned: BatchHdr + ReqRec[cap]
+    uint8_t *d_blk = nullptr;  // device copy
     uint64_t cap = 0;
-    PlanHdr *d_hdr = nullptr;
+    WorkCtr *d_ctr = nullptr;
+    uint64_t *d_t64 = nullptr;  // 3 * cap64 words
+    uint64_t cap64 = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
     bool busy = false;
   };
@@ -109,14 +176,42 @@ struct phprng_ctx {
   Slot slots[kSlots];
   int cur_slot = 0;
   int last_timed = -1;
-  double acc_ms = 0;        // cumulative kernel time of recycled slots
+  double acc_ms = 0;  // cumulative kernel time of recycled slots
   uint64_t acc_calls = 0;
-  HostReq *h_req = nullptr;  // staging array of the slot being prepared
-  // Per instance: its index in the touched list of the batch being prepared;
-  // -1 between calls, so that a batch costs O(requests), not O(instances).
-  std::vector<int64_t> where;
-  phprng_tuning tuning{256, 4, 8, 4};
+  // Planning scratch kept across calls, so that a batch costs O(requests).
+  std::vector<int64_t> where;  // per instance: index in `touched` during a plan, -1 otherwise
+  std::vector<uint32_t> touched;
+  std::vector<uint64_t> cur_x, cur_k;
+  std::vector<uint32_t> seg_count, seg_start;
+  std::vector<uint64_t> req_x;
+  std::vector<uint32_t> req_pos;
+  std::vector<uint32_t> order;
+  phprng_tuning tuning[3] = {{256, 4, 8, 4}, {256, 4, 8, 4}, {256, 4, 8, 4}};
   std::string err;
+
+  ~phprng_ctx() {
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(d_inst);
+    (void)hipFree(d_lanemul);
+    (void)hipFree(d_m64);
+    (void)hipFree(d_u32);
+    (void)hipFree(d_s32);
+    (void)hipFree(d_u64lo);
+    (void)hipFree(d_u64hi);
+    (void)hipFree(d_s64);
+    (void)hipFree(d_partial);
+    if (chain_ev) (void)hipEventDestroy(chain_ev);
+    for (auto &s : slots) {
+      (void)hipFree(s.d_blk);
+      if (s.h_blk) (void)hipHostFree(s.h_blk);
+      (void)hipFree(s.d_ctr);
+      (void)hipFree(s.d_t64);
+      if (s.ev0) (void)hipEventDestroy(s.ev0);
+      if (s.ev1) (void)hipEventDestroy(s.ev1);
+      if (s.done) (void)hipEventDestroy(s.done);
+    }
+  }
 
   phprng_status fail(phprng_status st, const char *fmt, ...) {
     char buf[512];
@@ -131,13 +226,13 @@ struct phprng_ctx {
     return fail(PHPRNG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
   }
 
-  // U(r) = sum_{j=1}^{r} (a^j mod p) and a^r mod p, from the table entry at or
-  // below r plus at most stride-1 host steps.
-  void prefix(int width, uint64_t r, u128 *U, uint64_t *S) const {
-    const SkipGroup &G = group(width);
+  // U(r) = sum_{j=1}^{r} (a^j mod p) and a^r mod p (width 32), from the table
+  // entry at or below r plus at most stride-1 host steps.
+  void prefix32(uint64_t r, u128 *U, uint64_t *S) const {
+    const SkipGroup &G = group(32);
     const uint64_t i = r / kTableStride;
-    u128 u = width == 32 ? (u128)u32[i] : u64[i];
-    uint64_t s = width == 32 ? (uint64_t)s32[i] : s64[i];
+    u128 u = (u128)u32[i];
+    uint64_t s = (uint64_t)s32[i];
     for (uint64_t x = i * kTableStride; x < r; ++x) {
       s = G.mulmod(G.a, s);
       u += s;
@@ -146,29 +241,24 @@ struct phprng_ctx {
     *S = s;
   }
 
-  // State (m, s) at internal index x of instance h (eq. (7); constant skip:
-  // m = m_0 + x b, s = b).
+  // State (m, s) at internal index x of a width-32 pseudorandom-skip or a
+  // constant-skip instance (eq. (7); constant skip: m = m_0 + x b, s = b).
   void state_at(const HostInst &h, uint64_t x, uint64_t *m, uint64_t *s) const {
+    Mont64 M(h.n);
     if (h.sched == kSchedConstant) {
-      Mont64 M(h.n);
       *m = M.add(h.mbase % h.n, M.mulmod(x % h.n, h.b));
       *s = h.b;
       return;
     }
-    const SkipGroup &G = group(h.width);
+    const SkipGroup &G = group(32);
     const uint64_t pm1 = G.p - 1;
     const uint64_t q = x / pm1, r = x % pm1;
     u128 U;
-    prefix(h.width, r, &U, s);
-    Mont64 M(h.n);
+    prefix32(r, &U, s);
     const u128 full = ((u128)G.p * (G.p - 1)) / 2;
     uint64_t b = M.reduce128(full);
     uint64_t qb = M.mulmod(q % h.n, b);
     *m = M.add(M.add(h.mbase % h.n, M.reduce128(U)), qb);
-  }
-
-  uint64_t max_index(const HostInst &h) const {
-    return (h.width == 32 || h.sched == kSchedConstant) ? ~0ull : kMaxPos64;
   }
 
   InstRec make_record(const HostInst &h) const {
@@ -241,41 +331,56 @@ struct phprng_ctx {
       if ((e = hipEventCreate(&s.ev0)) != hipSuccess) return hip_fail(e, "event");
       if ((e = hipEventCreate(&s.ev1)) != hipSuccess) return hip_fail(e, "event");
       if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-      if ((e = hipMalloc(&s.d_hdr, sizeof(PlanHdr))) != hipSuccess) return fail(PHPRNG_E_NOMEM, "plan header");
-      // the plan kernel expects a zero completion counter and leaves it so
-      if ((e = hipMemset(s.d_hdr, 0, sizeof(PlanHdr))) != hipSuccess) return hip_fail(e, "plan header");
+      if ((e = hipMalloc(&s.d_ctr, sizeof(WorkCtr))) != hipSuccess) return fail(PHPRNG_E_NOMEM, "work counter");
+      // the generation kernel expects a zero counter and leaves it so
+      if ((e = hipMemset(s.d_ctr, 0, sizeof(WorkCtr))) != hipSuccess) return hip_fail(e, "work counter");
     }
     if (nreq > s.cap) {
       // room for typical batches from the start: growing frees buffers,
       // which waits for the device
       uint64_t cap = std::max<uint64_t>({nreq, 2 * s.cap, kMinSlotRequests});
-      if (s.d_req) (void)hipFree(s.d_req);
-      if (s.d_gbase) (void)hipFree(s.d_gbase);
-      if (s.h_req) (void)hipHostFree(s.h_req);
-      s.d_req = nullptr;
-      s.d_gbase = nullptr;
-      s.h_req = nullptr;
-      s.h_req_dev = nullptr;
+      if (s.d_blk) (void)hipFree(s.d_blk);
+      if (s.h_blk) (void)hipHostFree(s.h_blk);
+      s.d_blk = nullptr;
+      s.h_blk = nullptr;
       s.cap = 0;
-      if ((e = hipMalloc(&s.d_req, cap * sizeof(ReqRec))) != hipSuccess)
+      const uint64_t bytes = sizeof(BatchHdr) + cap * sizeof(ReqRec);
+      if ((e = hipMalloc(&s.d_blk, bytes)) != hipSuccess)
         return fail(PHPRNG_E_NOMEM, "request buffer: %s", hipGetErrorString(e));
-      if ((e = hipMalloc(&s.d_gbase, (cap + kPlanGroup - 1) / kPlanGroup * sizeof(uint64_t))) != hipSuccess)
-        return fail(PHPRNG_E_NOMEM, "plan buffer: %s", hipGetErrorString(e));
-      if ((e = hipHostMalloc(&s.h_req, cap * sizeof(HostReq), hipHostMallocMapped)) != hipSuccess)
+      if ((e = hipHostMalloc(&s.h_blk, bytes, hipHostMallocDefault)) != hipSuccess) {
+        s.h_blk = nullptr;
         return fail(PHPRNG_E_NOMEM, "pinned request buffer: %s", hipGetErrorString(e));
-      void *dp = nullptr;
-      if ((e = hipHostGetDevicePointer(&dp, s.h_req, 0)) != hipSuccess || !dp)
-        return hip_fail(e != hipSuccess ? e : hipErrorInvalidValue, "pinned request buffer address");
-      s.h_req_dev = static_cast<const HostReq *>(dp);
+      }
       s.cap = cap;
     }
-    h_req = s.h_req;
     *out = &s;
+    return PHPRNG_OK;
+  }
+
+  phprng_status ensure_tiles(Slot &s, uint64_t tiles64) {
+    if (tiles64 <= s.cap64) return PHPRNG_OK;
+    const uint64_t cap = std::max<uint64_t>({tiles64, 2 * s.cap64, 1ull << 16});
+    if (s.d_t64) (void)hipFree(s.d_t64);
+    s.d_t64 = nullptr;
+    s.cap64 = 0;
+    hipError_t e = hipMalloc(&s.d_t64, 3 * cap * sizeof(uint64_t));
+    if (e != hipSuccess) return fail(PHPRNG_E_NOMEM, "tile state: %s", hipGetErrorString(e));
+    s.cap64 = cap;
     return PHPRNG_OK;
   }
 
   phprng_status build_table32();
   phprng_status build_table64();
+  phprng_status plan(const phprng_request *reqs, uint64_t nreq, uint64_t capacity, int mode, const uint32_t *tpc_fix,
+                     uint64_t stage_cap, uint8_t *stage, Plan *P);
+  void commit_plan();
+  GenArgs args(const uint8_t *d_blk, WorkCtr *ctr, uint64_t *t64, uint64_t t64cap, uint64_t nreq, uint32_t *c32,
+               uint64_t *c64, double *r, uint32_t tpc) const;
+  phprng_status launch(const Plan &P, const GenArgs &A, const ReqRec *hreq, hipStream_t s, int mode);
+  phprng_status sync_chain();
+  phprng_status read_m64(uint32_t id, uint64_t *m);
+  phprng_status write_m64(uint32_t id, uint64_t m);
+  phprng_status move64(uint32_t id, uint64_t d, bool forward, bool dry_run);
 };
 
 phprng_status phprng_ctx::build_table32() {
@@ -306,7 +411,7 @@ phprng_status phprng_ctx::build_table32() {
   // Self-check: the full-period skip sum is p(p-1)/2 and the skip returns to 1.
   u128 U;
   uint64_t S;
-  prefix(32, pm1, &U, &S);
+  prefix32(pm1, &U, &S);
   if (U != ((u128)kP32 * pm1) / 2 || S != 1) {
     (void)hipFree(d_start);
     return fail(PHPRNG_E_DEVICE, "32-bit skip-prefix table failed its full-period check");
@@ -320,46 +425,394 @@ phprng_status phprng_ctx::build_table32() {
 
 phprng_status phprng_ctx::build_table64() {
   if (have64) return PHPRNG_OK;
-  const uint64_t ne = kMaxPos64 / kTableStride;
+  const uint64_t ne = kTab64Range / kTableStride;
   uint64_t *d_lo = nullptr, *d_hi = nullptr, *d_start = nullptr;
   hipError_t e;
   if ((e = hipMalloc(&d_lo, ne * 8)) != hipSuccess) return hip_fail(e, "table64 alloc");
-  if ((e = hipMalloc(&d_hi, ne * 8)) != hipSuccess) return hip_fail(e, "table64 alloc");
-  if ((e = hipMalloc(&d_start, ne * 8)) != hipSuccess) return hip_fail(e, "table64 alloc");
+  if ((e = hipMalloc(&d_hi, ne * 8)) != hipSuccess) {
+    (void)hipFree(d_lo);
+    return hip_fail(e, "table64 alloc");
+  }
+  if ((e = hipMalloc(&d_start, ne * 8)) != hipSuccess) {
+    (void)hipFree(d_lo);
+    (void)hipFree(d_hi);
+    return hip_fail(e, "table64 alloc");
+  }
+  auto give_up = [&](phprng_status st) {
+    (void)hipFree(d_lo);
+    (void)hipFree(d_hi);
+    (void)hipFree(d_start);
+    return st;
+  };
   if ((e = launch_table_segments64(ne, d_lo, d_hi, d_start, nullptr)) != hipSuccess)
-    return hip_fail(e, "table64 launch");
-  std::vector<uint64_t> lo(ne), hi(ne);
-  s64.resize(ne);
-  if ((e = hipMemcpy(lo.data(), d_lo, ne * 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "copy");
-  if ((e = hipMemcpy(hi.data(), d_hi, ne * 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "copy");
-  if ((e = hipMemcpy(s64.data(), d_start, ne * 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "copy");
-  u64.resize(ne);
+    return give_up(hip_fail(e, "table64 launch"));
+  std::vector<uint64_t> lo(ne), hi(ne), s64(ne);
+  if ((e = hipMemcpy(lo.data(), d_lo, ne * 8, hipMemcpyDeviceToHost)) != hipSuccess) return give_up(hip_fail(e, "copy"));
+  if ((e = hipMemcpy(hi.data(), d_hi, ne * 8, hipMemcpyDeviceToHost)) != hipSuccess) return give_up(hip_fail(e, "copy"));
+  if ((e = hipMemcpy(s64.data(), d_start, ne * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+    return give_up(hip_fail(e, "copy"));
+  std::vector<u128> u(ne);
   u128 acc = 0;
   for (uint64_t i = 0; i < ne; ++i) {
-    u64[i] = acc;
+    u[i] = acc;
     acc += ((u128)hi[i] << 64) | lo[i];
-    lo[i] = (uint64_t)u64[i];
-    hi[i] = (uint64_t)(u64[i] >> 64);
+    lo[i] = (uint64_t)u[i];
+    hi[i] = (uint64_t)(u[i] >> 64);
   }
   // Spot-check a few entries against host stepping from the previous entry.
   const SkipGroup &G = group(64);
   for (uint64_t i : {(uint64_t)1, ne / 3, ne - 1}) {
-    u128 u = u64[i - 1];
+    u128 v = u[i - 1];
     uint64_t s = s64[i - 1];
     for (uint64_t x = 0; x < kTableStride; ++x) {
       s = G.mulmod(G.a, s);
-      u += s;
+      v += s;
     }
-    if (u != u64[i] || s != s64[i] || s != G.powmod(G.a, i * kTableStride))
-      return fail(PHPRNG_E_DEVICE, "64-bit skip-prefix table failed its check at entry %llu", (unsigned long long)i);
+    if (v != u[i] || s != s64[i] || s != G.powmod(G.a, i * kTableStride))
+      return give_up(fail(PHPRNG_E_DEVICE, "64-bit skip-prefix table failed its check at entry %llu",
+                          (unsigned long long)i));
   }
-  if ((e = hipMemcpy(d_lo, lo.data(), ne * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "upload");
-  if ((e = hipMemcpy(d_hi, hi.data(), ne * 8, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "upload");
+  if ((e = hipMemcpy(d_lo, lo.data(), ne * 8, hipMemcpyHostToDevice)) != hipSuccess)
+    return give_up(hip_fail(e, "upload"));
+  if ((e = hipMemcpy(d_hi, hi.data(), ne * 8, hipMemcpyHostToDevice)) != hipSuccess)
+    return give_up(hip_fail(e, "upload"));
   d_u64lo = d_lo;
   d_u64hi = d_hi;
   d_s64 = d_start;
   have64 = true;
   return PHPRNG_OK;
+}
+
+// Global tile index of the width-32 tile whose draws include the draw made
+// from internal index x.
+static inline uint64_t tile_of32(uint64_t x) {
+  const uint64_t pm1 = (uint64_t)kP32 - 1;
+  const uint64_t q = x / pm1, r = x - q * pm1;
+  return (q << 20) | (r / kTile32);
+}
+
+// Validate a request list, reserve positions (in request order) and write
+// the planned batch into `stage` (BatchHdr followed by nreq ReqRec): the
+// width-64 pseudorandom-skip requests first, grouped by instance in call
+// order, then the other width-64 requests, then the width-32 ones.  The new
+// positions are kept in cur_x / cur_k for commit_plan once every launch has
+// been issued.  tpc_fix: tiles per chunk to use as is (graphs), else the
+// tuned value, halved for batches too small to give every wave 4 chunks.
+phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64_t capacity, int mode,
+                               const uint32_t *tpc_fix, uint64_t stage_cap, uint8_t *stage, Plan *P) {
+  if (nreq > 0 && !reqs) return fail(PHPRNG_E_INVALID, "null request array");
+  if (nreq > stage_cap) return fail(PHPRNG_E_RANGE, "too many requests for the staging buffer");
+  if (nreq >= (1ull << 31)) return fail(PHPRNG_E_RANGE, "too many requests");
+  const uint64_t pm1_64 = kP64 - 1;
+  for (uint64_t i = 0; i < nreq; ++i) {
+    const phprng_request &r = reqs[i];
+    if (r.instance >= inst.size() || r.reserved != 0)
+      return fail(PHPRNG_E_INVALID, "request %llu: bad instance", (unsigned long long)i);
+    if (r.count > capacity || r.out_offset > capacity - r.count)
+      return fail(PHPRNG_E_RANGE, "request %llu: output range beyond capacity", (unsigned long long)i);
+  }
+  if (where.size() < inst.size()) where.resize(inst.size(), -1);
+  touched.clear();
+  cur_x.clear();
+  cur_k.clear();
+  seg_count.clear();
+  req_x.resize(nreq);
+  req_pos.resize(nreq);
+  struct Reset {  // `where` back to -1 on every way out
+    std::vector<int64_t> &w;
+    const std::vector<uint32_t> &t;
+    ~Reset() {
+      for (uint32_t i : t) w[i] = -1;
+    }
+  } reset{where, touched};
+  // positions in request order
+  uint64_t c64l = 0, c64c = 0, c32 = 0;
+  for (uint64_t i = 0; i < nreq; ++i) {
+    const phprng_request &r = reqs[i];
+    const HostInst &h = inst[r.instance];
+    if (where[r.instance] < 0) {
+      where[r.instance] = (int64_t)touched.size();
+      touched.push_back(r.instance);
+      cur_x.push_back(h.x);
+      cur_k.push_back(h.k);
+      seg_count.push_back(0);
+    }
+    const size_t t = (size_t)where[r.instance];
+    if (r.count > ~0ull - cur_k[t])
+      return fail(PHPRNG_E_RANGE, "request %llu: position beyond range", (unsigned long long)i);
+    req_x[i] = cur_x[t];
+    if (lcg64(h)) {
+      if (r.count >= kMaxCount64)
+        return fail(PHPRNG_E_RANGE, "request %llu: more than 2^42 width-64 draws", (unsigned long long)i);
+      cur_x[t] = add_u64_mod(cur_x[t], r.count % pm1_64, pm1_64);
+      seg_count[t] += 1;
+      ++c64l;
+    } else {
+      if (r.count > ~0ull - cur_x[t])
+        return fail(PHPRNG_E_RANGE, "request %llu: position beyond range", (unsigned long long)i);
+      cur_x[t] += r.count;
+      if (h.width == 64) ++c64c;
+      else ++c32;
+    }
+    cur_k[t] += r.count;
+  }
+  // staging order
+  seg_start.resize(touched.size());
+  uint32_t run = 0;
+  for (size_t t = 0; t < touched.size(); ++t) {
+    seg_start[t] = run;
+    if (lcg64(inst[touched[t]])) run += seg_count[t];
+  }
+  {
+    uint64_t f64c = c64l, f32 = c64l + c64c;
+    // seg_count doubles as the fill count of each instance's group
+    std::vector<uint32_t> &fill = seg_count;
+    for (size_t t = 0; t < touched.size(); ++t) fill[t] = 0;
+    for (uint64_t i = 0; i < nreq; ++i) {
+      const HostInst &h = inst[reqs[i].instance];
+      const size_t t = (size_t)where[reqs[i].instance];
+      if (lcg64(h)) req_pos[i] = seg_start[t] + fill[t]++;
+      else if (h.width == 64) req_pos[i] = (uint32_t)f64c++;
+      else req_pos[i] = (uint32_t)f32++;
+    }
+  }
+  order.resize(nreq);
+  for (uint64_t i = 0; i < nreq; ++i) order[req_pos[i]] = (uint32_t)i;
+  // records
+  BatchHdr *H = reinterpret_cast<BatchHdr *>(stage);
+  ReqRec *R = reinterpret_cast<ReqRec *>(stage + sizeof(BatchHdr));
+  uint64_t tiles = 0, tiles64 = 0;
+  for (uint64_t p = 0; p < nreq; ++p) {
+    const uint64_t i = order[p];
+    const phprng_request &q = reqs[i];
+    const HostInst &h = inst[q.instance];
+    ReqRec &rr = R[p];
+    memset(&rr, 0, sizeof rr);
+    rr.x = req_x[i];
+    rr.count = q.count;
+    rr.out_off = q.out_offset;
+    rr.inst = q.instance;
+    uint64_t nt = 0;
+    if (lcg64(h)) {
+      const size_t t = (size_t)where[q.instance];
+      nt = (q.count + kTile64 - 1) / kTile64;
+      rr.g1 = tiles64;
+      tiles64 += nt;
+      rr.seg = p == seg_start[t] ? seg_count[t] : 0;
+    } else if (h.sched == kSchedConstant) {
+      rr.g1 = rr.x / kTileCS;
+      nt = q.count ? (rr.x + q.count - 1) / kTileCS - rr.g1 + 1 : 0;
+    } else {
+      rr.g1 = tile_of32(rr.x);
+      nt = q.count ? tile_of32(rr.x + q.count - 1) - rr.g1 + 1 : 0;
+    }
+    if (nt >= (1ull << 32)) return fail(PHPRNG_E_RANGE, "request %llu: too many tiles", (unsigned long long)i);
+    rr.ntiles = (uint32_t)nt;
+    tiles += nt;
+  }
+  // chunks
+  Plan out;
+  out.nreq = nreq;
+  out.nreq64 = c64l;
+  out.tiles64 = tiles64;
+  out.tiles = tiles;
+  out.has64 = c64l + c64c > 0;
+  out.has32 = c32 > 0;
+  out.cls = out.has64 ? (out.has32 ? kMixBoth : kMix64) : kMix32;
+  const phprng_tuning &T = tuning[out.cls];
+  uint32_t tpc;
+  if (mode == PHPRNG_MODE_PLAIN) {
+    tpc = 1;
+  } else if (tpc_fix) {
+    tpc = *tpc_fix;
+  } else {
+    tpc = (uint32_t)T.tiles_per_chunk;
+    const uint64_t waves = (uint64_t)num_cus * T.blocks_per_cu * (T.block_threads / 64);
+    while (tpc > 1 && tiles < 4 * waves * tpc) tpc >>= 1;
+  }
+  out.tpc = tpc;
+  uint64_t chunks = 0;
+  for (uint64_t p = 0; p < nreq; ++p) {
+    ReqRec &rr = R[p];
+    const uint64_t nc = ((uint64_t)rr.ntiles + tpc - 1) / tpc;
+    rr.chunk_base = chunks;
+    rr.nchunks = (uint32_t)nc;
+    chunks += nc;
+  }
+  out.total_chunks = chunks;
+  memset(H, 0, sizeof *H);
+  H->total_chunks = chunks;
+  H->nreq = nreq;
+  H->nreq64 = c64l;
+  H->tiles64 = tiles64;
+  *P = out;
+  return PHPRNG_OK;
+}
+
+void phprng_ctx::commit_plan() {
+  for (size_t t = 0; t < touched.size(); ++t) {
+    HostInst &h = inst[touched[t]];
+    h.x = cur_x[t];
+    h.k = cur_k[t];
+  }
+}
+
+GenArgs phprng_ctx::args(const uint8_t *d_blk, WorkCtr *ctr, uint64_t *t64, uint64_t t64cap, uint64_t nreq,
+                         uint32_t *c32, uint64_t *c64, double *r, uint32_t tpc) const {
+  GenArgs A;
+  memset(&A, 0, sizeof A);
+  A.inst = d_inst;
+  A.hdr = reinterpret_cast<const BatchHdr *>(d_blk);
+  A.req = reinterpret_cast<const ReqRec *>(d_blk + sizeof(BatchHdr));
+  A.nreq = nreq;
+  A.ctr = ctr;
+  A.tab = SkipTables{d_u32, d_s32, (uint64_t)u32.size()};
+  A.lanemul = d_lanemul;
+  A.t64.s = t64;
+  A.t64.sum = t64 ? t64 + t64cap : nullptr;
+  A.t64.m = t64 ? t64 + 2 * t64cap : nullptr;
+  A.m64 = d_m64;
+  A.out_c32 = c32;
+  A.out_c64 = c64;
+  A.out_r = r;
+  A.tiles_per_chunk = tpc;
+  return A;
+}
+
+// Width-64 tile starts (ordered after the previous call's scan), then the
+// generation kernel(s).  The batch block must already be on the device.
+phprng_status phprng_ctx::launch(const Plan &P, const GenArgs &A, const ReqRec *hreq, hipStream_t s, int mode) {
+  hipError_t e;
+  if (P.nreq64 > 0) {
+    if ((e = launch_tiles64_reduce(A, P.tiles64, (unsigned)num_cus * 8, s)) != hipSuccess)
+      return hip_fail(e, "tile reduce");
+    if (chain_pending && (e = hipStreamWaitEvent(s, chain_ev, 0)) != hipSuccess) return hip_fail(e, "chain wait");
+    if ((e = launch_tiles64_scan(A, P.nreq64, s)) != hipSuccess) return hip_fail(e, "tile scan");
+    if ((e = hipEventRecord(chain_ev, s)) != hipSuccess) return hip_fail(e, "chain record");
+    chain_pending = true;
+  }
+  const phprng_tuning &T = tuning[P.cls];
+  if (mode == PHPRNG_MODE_PERSISTENT) {
+    if (P.total_chunks == 0) return PHPRNG_OK;
+    // no more blocks than the batch can keep busy
+    const uint64_t wpb = (uint64_t)T.block_threads / 64;
+    const unsigned grid = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)num_cus * T.blocks_per_cu, (P.total_chunks + wpb - 1) / wpb));
+    if ((e = launch_persistent(A, grid, T.block_threads, T.unroll, P.has64, s)) != hipSuccess)
+      return hip_fail(e, "persistent launch");
+  } else {
+    // one grid per request, from the host copy of the planned requests
+    for (uint64_t p = 0; p < P.nreq; ++p) {
+      if ((e = launch_plain(A, p, hreq[p].nchunks, T.unroll, P.has64, s)) != hipSuccess)
+        return hip_fail(e, "plain launch");
+    }
+  }
+  return PHPRNG_OK;
+}
+
+phprng_status phprng_ctx::sync_chain() {
+  if (!chain_pending) return PHPRNG_OK;
+  hipError_t e = hipEventSynchronize(chain_ev);
+  if (e != hipSuccess) return hip_fail(e, "chain wait");
+  chain_pending = false;
+  return PHPRNG_OK;
+}
+
+phprng_status phprng_ctx::read_m64(uint32_t id, uint64_t *m) {
+  phprng_status st = sync_chain();
+  if (st != PHPRNG_OK) return st;
+  hipError_t e = hipMemcpy(m, d_m64 + id, sizeof(uint64_t), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? PHPRNG_OK : hip_fail(e, "message read");
+}
+
+phprng_status phprng_ctx::write_m64(uint32_t id, uint64_t m) {
+  phprng_status st = sync_chain();
+  if (st != PHPRNG_OK) return st;
+  hipError_t e = hipMemcpy(d_m64 + id, &m, sizeof(uint64_t), hipMemcpyHostToDevice);
+  return e == hipSuccess ? PHPRNG_OK : hip_fail(e, "message write");
+}
+
+namespace {
+
+// Runs position64_kernel on host arrays (one entry per instance) and waits.
+phprng_status apply_table64(phprng_ctx *c, const std::vector<uint32_t> &ids, const std::vector<uint64_t> &m0,
+                            const std::vector<uint64_t> &ta, const std::vector<uint64_t> &tb) {
+  const uint64_t n = ids.size();
+  if (n == 0) return PHPRNG_OK;
+  uint8_t *d = nullptr;
+  const uint64_t bytes = n * (4 + 3 * 8) + 64;
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return c->fail(PHPRNG_E_NOMEM, "positioning buffer");
+  uint64_t *dm = reinterpret_cast<uint64_t *>(d), *da = dm + n, *db = da + n;
+  uint32_t *di = reinterpret_cast<uint32_t *>(db + n);
+  if (e == hipSuccess) e = hipMemcpy(dm, m0.data(), n * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(da, ta.data(), n * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(db, tb.data(), n * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(di, ids.data(), n * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_position64(c->d_inst, di, dm, da, db, n, c->d_u64lo, c->d_u64hi, c->d_s64, c->d_m64, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  (void)hipFree(d);
+  return e == hipSuccess ? PHPRNG_OK : c->hip_fail(e, "positioning");
+}
+
+}  // namespace
+
+// Moves the device message of width-64 instance `id` by d draws from skip
+// log h.x (forward or backward) and reports the new skip log.  d = q (p - 1)
+// + r: each whole skip period adds p(p-1)/2 (Sec. II), and the r remaining
+// skips come from the positioning table when both ends lie on it, else are
+// summed on the device (or, when r is within kJumpMax of a whole period,
+// the complement is).  dry_run only checks that the move is supported.
+phprng_status phprng_ctx::move64(uint32_t id, uint64_t d, bool forward, bool dry_run) {
+  const HostInst &h = inst[id];
+  const uint64_t pm1 = kP64 - 1, x = h.x;
+  const uint64_t q = d / pm1, r = d % pm1;
+  enum { kTable, kSum, kComplement } path;
+  if (forward ? (x + r < kTab64Range) : (x >= r && x < kTab64Range)) path = kTable;
+  else if (r <= kJumpMax) path = kSum;
+  else if (pm1 - r <= kJumpMax) path = kComplement;
+  else return fail(PHPRNG_E_RANGE, "width-64 move of %llu draws: off the table and too far from a whole skip period",
+                   (unsigned long long)d);
+  if (dry_run) return PHPRNG_OK;
+  if (path == kTable && !have64) {
+    phprng_status bs = build_table64();
+    if (bs != PHPRNG_OK) return bs;
+  }
+  Mont64 M(h.n);
+  const uint64_t b = M.reduce128(((u128)kP64 * pm1) / 2);
+  const uint64_t qb = M.mulmod(q % h.n, b);
+  phprng_status st;
+  if (path == kTable) {
+    uint64_t m = 0;
+    if ((st = read_m64(id, &m)) != PHPRNG_OK) return st;
+    m = forward ? M.add(m, qb) : M.sub(m, qb);
+    std::vector<uint32_t> ids{id};
+    std::vector<uint64_t> m0{m}, ta{forward ? x + r : x - r}, tb{x};
+    st = apply_table64(this, ids, m0, ta, tb);
+  } else {
+    if ((st = sync_chain()) != PHPRNG_OK) return st;
+    uint64_t t, cnt, extra;
+    int sign;
+    if (path == kSum) {
+      // forward: + (q b + skips of logs x+1 .. x+r); backward: - (q b + logs x-r+1 .. x)
+      t = forward ? x : (x >= r ? x - r : x + (pm1 - r));
+      cnt = r;
+      extra = qb;
+      sign = forward ? 1 : -1;
+    } else {
+      // the r skips are a whole period less the pm1 - r skips that complete it
+      const uint64_t e1 = M.mulmod((q + 1) % h.n, b);
+      t = forward ? add_u64_mod(x, r, pm1) : x;
+      cnt = pm1 - r;
+      extra = e1 ? h.n - e1 : 0;
+      sign = forward ? -1 : 1;
+    }
+    hipError_t e = launch_skip_total64(t, cnt, h.n, d_lanemul, d_partial, kJumpBlocks, extra, sign, d_m64 + id, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    st = e == hipSuccess ? PHPRNG_OK : hip_fail(e, "skip sum");
+  }
+  return st;
 }
 
 // ---------------------------------------------------------------------------
@@ -436,27 +889,51 @@ extern "C" phprng_status phprng_draw_instances(int width, uint64_t seed, uint64_
 extern "C" phprng_status phprng_create(phprng_ctx **out, int device, uint64_t max_instances) {
   if (!out || max_instances == 0 || max_instances > (1ull << 31)) return PHPRNG_E_INVALID;
   *out = nullptr;
-  std::unique_ptr<phprng_ctx> c(new (std::nothrow) phprng_ctx);
-  if (!c) return PHPRNG_E_NOMEM;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PHPRNG_E_INVALID;
-  hipError_t e = hipSetDevice(device);
-  if (e != hipSuccess) return PHPRNG_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return PHPRNG_E_DEVICE;
+  std::unique_ptr<phprng_ctx> c(new (std::nothrow) phprng_ctx);
+  if (!c) return PHPRNG_E_NOMEM;
   c->device = device;
   hipDeviceProp_t prop;
-  if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return PHPRNG_E_DEVICE;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PHPRNG_E_DEVICE;
   c->num_cus = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
   c->max_instances = max_instances;
+  try {
+    for (auto *v : {&c->touched, &c->seg_count, &c->seg_start, &c->req_pos, &c->order})
+      v->reserve(kPlanReserve);
+    for (auto *v : {&c->cur_x, &c->cur_k, &c->req_x}) v->reserve(kPlanReserve);
+  } catch (...) {
+    return PHPRNG_E_NOMEM;
+  }
   if (hipMalloc(&c->d_inst, max_instances * sizeof(InstRec)) != hipSuccess) return PHPRNG_E_NOMEM;
-  // lane start multipliers a^{l * run} mod p
+  if (hipMalloc(&c->d_m64, max_instances * sizeof(uint64_t)) != hipSuccess) return PHPRNG_E_NOMEM;
+  if (hipMemset(c->d_m64, 0, max_instances * sizeof(uint64_t)) != hipSuccess) return PHPRNG_E_DEVICE;
+  if (hipMalloc(&c->d_partial, (uint64_t)kJumpBlocks * 4 * sizeof(uint64_t)) != hipSuccess) return PHPRNG_E_NOMEM;
+  // lane start multipliers a^{l * run} and the powers a^{2^b} of the 64-bit skip
   LaneMul lm;
+  memset(&lm, 0, sizeof lm);
   const SkipGroup &g32 = group(32), &g64 = group(64);
   for (int l = 0; l < 64; ++l) {
-    lm.m32[l] = (uint32_t)g32.powmod(g32.a, (uint64_t)l * kRun);
-    lm.m64[l] = g64.powmod(g64.a, (uint64_t)l * kRun);
+    lm.m32[l] = (uint32_t)g32.powmod(g32.a, (uint64_t)l * kRun32);
+    lm.m64[l] = g64.powmod(g64.a, (uint64_t)l * kRun64);
+  }
+  uint64_t pw = g64.a;
+  for (int bexp = 0; bexp < 61; ++bexp) {
+    lm.pow64[bexp] = pw;
+    pw = g64.mulmod(pw, pw);
   }
   if (hipMalloc(&c->d_lanemul, sizeof(LaneMul)) != hipSuccess) return PHPRNG_E_NOMEM;
   if (hipMemcpy(c->d_lanemul, &lm, sizeof lm, hipMemcpyHostToDevice) != hipSuccess) return PHPRNG_E_DEVICE;
+  if (hipEventCreateWithFlags(&c->chain_ev, hipEventDisableTiming) != hipSuccess) return PHPRNG_E_DEVICE;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int cls = 0; cls < 3; ++cls) {
+      auto it = g_tune_cache.find(TuneKey{c->arch, c->num_cus, cls});
+      if (it != g_tune_cache.end()) c->tuning[cls] = it->second;
+    }
+  }
   phprng_status st = c->build_table32();
   if (st != PHPRNG_OK) return st;
   *out = c.release();
@@ -465,24 +942,6 @@ extern "C" phprng_status phprng_create(phprng_ctx **out, int device, uint64_t ma
 
 extern "C" phprng_status phprng_destroy(phprng_ctx *c) {
   if (!c) return PHPRNG_E_INVALID;
-  (void)hipSetDevice(c->device);
-  (void)hipDeviceSynchronize();
-  (void)hipFree(c->d_inst);
-  (void)hipFree(c->d_lanemul);
-  (void)hipFree(c->d_u32);
-  (void)hipFree(c->d_s32);
-  (void)hipFree(c->d_u64lo);
-  (void)hipFree(c->d_u64hi);
-  (void)hipFree(c->d_s64);
-  for (auto &s : c->slots) {
-    (void)hipFree(s.d_req);
-    (void)hipFree(s.d_gbase);
-    if (s.h_req) (void)hipHostFree(s.h_req);
-    (void)hipFree(s.d_hdr);
-    if (s.ev0) (void)hipEventDestroy(s.ev0);
-    if (s.ev1) (void)hipEventDestroy(s.ev1);
-    if (s.done) (void)hipEventDestroy(s.done);
-  }
   delete c;
   return PHPRNG_OK;
 }
@@ -499,32 +958,51 @@ extern "C" phprng_status phprng_add_instances(phprng_ctx *c, uint64_t count, int
   if (!n || !e || !ids) return c->fail(PHPRNG_E_INVALID, "null array");
   if (c->inst.size() + count > c->max_instances) return c->fail(PHPRNG_E_RANGE, "instance table full");
   (void)hipSetDevice(c->device);
-  for (uint64_t i = 0; i < count; ++i) {
-    phprng_status st = check_instance_impl(width, n[i], e[i]);
-    if (st != PHPRNG_OK) return c->fail(st, "instance %llu rejected", (unsigned long long)i);
-  }
-  if (width == 64 && !c->have64) {
-    phprng_status bs = c->build_table64();
-    if (bs != PHPRNG_OK) return bs;
-  }
   const SkipGroup &G = group(width);
+  const uint64_t pm1 = G.p - 1;
   std::vector<HostInst> add(count);
+  std::vector<uint64_t> t0s(count, 0);
+  std::vector<uint8_t> on_table(count, 0);
+  // validate everything first
   for (uint64_t i = 0; i < count; ++i) {
     phprng_status st = check_instance_impl(width, n[i], e[i]);
     if (st != PHPRNG_OK) return c->fail(st, "instance %llu rejected", (unsigned long long)i);
     const uint64_t mm0 = m0 ? m0[i] : 0, ss0 = s0 ? s0[i] : 1, kk = k0 ? k0[i] : 0;
     if (mm0 >= n[i] || ss0 == 0 || ss0 >= G.p) return c->fail(PHPRNG_E_INVALID, "bad m0/s0 at %llu", (unsigned long long)i);
     const uint64_t t0 = ss0 == 1 ? 0 : G.dlog(ss0);
-    if (width == 64 && (t0 >= kMaxPos64 || kk >= kMaxPos64 - t0))
-      return c->fail(PHPRNG_E_RANGE, "width-64 start beyond the supported range");
-    if (width == 32 && kk > ~0ull - t0) return c->fail(PHPRNG_E_RANGE, "start index overflows");
-    add[i] = HostInst{n[i], e[i], width, 0, t0 + kk, (int64_t)t0};
+    t0s[i] = t0;
+    HostInst h{n[i], e[i], width};
+    h.k = kk;
+    if (width == 32) {
+      if (kk > ~0ull - t0) return c->fail(PHPRNG_E_RANGE, "start index overflows");
+      h.x = t0 + kk;
+    } else {
+      h.x = t0;  // moved to kk below
+      if (kk < kTab64Range && t0 + kk < kTab64Range) {
+        on_table[i] = 1;
+      } else {
+        // off the table: the start is reached by summing skips on the device
+        c->inst.push_back(h);
+        phprng_status ms = c->move64((uint32_t)(c->inst.size() - 1), kk, true, true);
+        c->inst.pop_back();
+        if (ms != PHPRNG_OK) return ms;
+      }
+    }
+    add[i] = h;
+  }
+  if (width == 64 && !c->have64) {
+    phprng_status bs = c->build_table64();
+    if (bs != PHPRNG_OK) return bs;
+  }
+  for (uint64_t i = 0; i < count; ++i) {
+    if (width != 32) continue;
     // mbase such that the state at internal index t0 is (m0, s0): m0 - U(t0)
-    if (t0 != 0 || mm0 != 0) {
+    const uint64_t mm0 = m0 ? m0[i] : 0;
+    if (t0s[i] != 0 || mm0 != 0) {
       HostInst tmp = add[i];
       tmp.mbase = 0;
       uint64_t mu, su;
-      c->state_at(tmp, t0, &mu, &su);
+      c->state_at(tmp, t0s[i], &mu, &su);
       Mont64 M(n[i]);
       add[i].mbase = M.sub(mm0, mu);
     }
@@ -537,6 +1015,34 @@ extern "C" phprng_status phprng_add_instances(phprng_ctx *c, uint64_t count, int
   for (uint64_t i = 0; i < count; ++i) {
     c->inst.push_back(add[i]);
     ids[i] = (uint32_t)(base + i);
+  }
+  if (c->where.size() < c->inst.size()) c->where.resize(c->inst.size(), -1);
+  if (width == 64) {
+    // messages at the start positions: from the table where it reaches,
+    // else m0 moved forward on the device
+    std::vector<uint32_t> tid;
+    std::vector<uint64_t> tm, ta, tb;
+    phprng_status st = PHPRNG_OK;
+    for (uint64_t i = 0; i < count; ++i) {
+      const uint64_t mm0 = m0 ? m0[i] : 0, kk = k0 ? k0[i] : 0;
+      const uint32_t id = (uint32_t)(base + i);
+      if (on_table[i]) {
+        tid.push_back(id);
+        tm.push_back(mm0);
+        ta.push_back(t0s[i] + kk);
+        tb.push_back(t0s[i]);
+        c->inst[id].x = t0s[i] + kk;
+      } else {
+        if (st == PHPRNG_OK) st = c->write_m64(id, mm0);
+        if (st == PHPRNG_OK) st = c->move64(id, kk, true, false);
+        c->inst[id].x = add_u64_mod(t0s[i], kk % pm1, pm1);
+      }
+    }
+    if (st == PHPRNG_OK) st = apply_table64(c, tid, tm, ta, tb);
+    if (st != PHPRNG_OK) {
+      c->inst.resize(base);  // nothing added
+      return st;
+    }
   }
   return PHPRNG_OK;
 }
@@ -635,7 +1141,8 @@ extern "C" phprng_status phprng_seed_instances(phprng_ctx *c, uint64_t count, in
   for (int i = 0; i < e_len; ++i) any = any || e_set[i] >= 3;
   if (!any) return c->fail(PHPRNG_E_EXPONENT, "no admissible exponent in the set");
   if (c->inst.size() + count > c->max_instances) return c->fail(PHPRNG_E_RANGE, "instance table full");
-  if (width == 64 && k_hi > kMaxPos64) return c->fail(PHPRNG_E_RANGE, "width-64 start beyond the supported range");
+  if (width == 64 && k_hi > kTab64Range)
+    return c->fail(PHPRNG_E_RANGE, "bulk width-64 starts must lie below 2^34 (the positioning table)");
   (void)hipSetDevice(c->device);
   std::vector<uint64_t> n(count), e(count), k(count);
   phprng_status st = draw_on_device(c, width, seed, count, e_set, e_len, k_lo, k_hi, n.data(), e.data(), k.data());
@@ -645,19 +1152,34 @@ extern "C" phprng_status phprng_seed_instances(phprng_ctx *c, uint64_t count, in
     if (st != PHPRNG_OK) return st;
   }
   uint64_t *d_ne = nullptr;
-  hipError_t he = hipMalloc(&d_ne, 2 * count * sizeof(uint64_t));
+  hipError_t he = hipMalloc(&d_ne, 3 * count * sizeof(uint64_t) + count * sizeof(uint32_t));
   if (he != hipSuccess) return c->hip_fail(he, "seed records");
   const uint64_t base = c->inst.size();
+  uint32_t *d_ids = reinterpret_cast<uint32_t *>(d_ne + 3 * count);
+  std::vector<uint32_t> hid(count);
+  for (uint64_t i = 0; i < count; ++i) hid[i] = (uint32_t)(base + i);
   he = hipMemcpy(d_ne, n.data(), count * 8, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(d_ne + count, e.data(), count * 8, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = launch_build_records(d_ne, d_ne + count, count, width, c->d_inst + base, nullptr);
+  if (he == hipSuccess && width == 64) {
+    // messages at the start positions from the base state (0, 1): U(k) mod n
+    he = hipMemcpy(d_ne + 2 * count, k.data(), count * 8, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(d_ids, hid.data(), count * 4, hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+      he = launch_position64(c->d_inst, d_ids, nullptr, d_ne + 2 * count, nullptr, count, c->d_u64lo, c->d_u64hi,
+                             c->d_s64, c->d_m64, nullptr);
+  }
   if (he == hipSuccess) he = hipDeviceSynchronize();
   (void)hipFree(d_ne);
   if (he != hipSuccess) return c->hip_fail(he, "seed records");
   for (uint64_t i = 0; i < count; ++i) {
-    c->inst.push_back(HostInst{n[i], e[i], width, 0, k[i], 0});
+    HostInst h{n[i], e[i], width};
+    h.x = k[i];
+    h.k = k[i];
+    c->inst.push_back(h);
     ids[i] = (uint32_t)(base + i);
   }
+  if (c->where.size() < c->inst.size()) c->where.resize(c->inst.size(), -1);
   return PHPRNG_OK;
 }
 
@@ -677,9 +1199,11 @@ extern "C" phprng_status phprng_add_instances_skip(phprng_ctx *c, uint64_t count
     const uint64_t mm0 = m0 ? m0[i] : 0;
     if (b[i] == 0 || b[i] >= n[i] || mm0 >= n[i])
       return c->fail(PHPRNG_E_INVALID, "bad skip or m0 at %llu", (unsigned long long)i);
-    HostInst h{n[i], e[i], width, mm0, k0 ? k0[i] : 0, 0};
+    HostInst h{n[i], e[i], width};
     h.sched = kSchedConstant;
     h.b = b[i];
+    h.mbase = mm0;
+    h.x = h.k = k0 ? k0[i] : 0;
     add[i] = h;
     recs[i] = c->make_record(h);
   }
@@ -690,6 +1214,7 @@ extern "C" phprng_status phprng_add_instances_skip(phprng_ctx *c, uint64_t count
     c->inst.push_back(add[i]);
     ids[i] = (uint32_t)(base + i);
   }
+  if (c->where.size() < c->inst.size()) c->where.resize(c->inst.size(), -1);
   return PHPRNG_OK;
 }
 
@@ -701,91 +1226,9 @@ extern "C" phprng_status phprng_get_schedule(phprng_ctx *c, uint32_t id, int *sc
   return PHPRNG_OK;
 }
 
-namespace {
-
-// Validate a request list and reserve positions.  Fills the slot's staging
-// array (width-64 requests first, for load balance) and returns the new
-// internal positions through `moves`; the caller applies them once every
-// launch has been issued.
-phprng_status prepare_requests(phprng_ctx *c, const phprng_request *reqs, uint64_t nreq, uint64_t capacity,
-                               phprng_ctx::Slot **slot, bool *has64,
-                               std::vector<std::pair<uint32_t, uint64_t>> *moves) {
-  if (nreq > 0 && !reqs) return c->fail(PHPRNG_E_INVALID, "null request array");
-  uint64_t n64 = 0;
-  for (uint64_t i = 0; i < nreq; ++i) {
-    const phprng_request &r = reqs[i];
-    if (r.instance >= c->inst.size() || r.reserved != 0)
-      return c->fail(PHPRNG_E_INVALID, "request %llu: bad instance", (unsigned long long)i);
-    if (r.count > capacity || r.out_offset > capacity - r.count)
-      return c->fail(PHPRNG_E_RANGE, "request %llu: output range beyond capacity", (unsigned long long)i);
-    if (c->inst[r.instance].width == 64) ++n64;
-  }
-  *has64 = n64 > 0;
-  // tentative positions, in request order
-  std::vector<uint32_t> touched;
-  std::vector<uint64_t> cur;
-  if (c->where.size() < c->inst.size()) c->where.resize(c->inst.size(), -1);
-  std::vector<int64_t> &where = c->where;
-  struct Reset {  // back to -1 on every way out
-    std::vector<int64_t> &w;
-    const std::vector<uint32_t> &t;
-    ~Reset() {
-      for (uint32_t i : t) w[i] = -1;
-    }
-  } reset{where, touched};
-  for (uint64_t i = 0; i < nreq; ++i) {
-    const phprng_request &r = reqs[i];
-    const HostInst &h = c->inst[r.instance];
-    if (where[r.instance] < 0) {
-      where[r.instance] = (int64_t)touched.size();
-      touched.push_back(r.instance);
-      cur.push_back(h.x);
-    }
-    uint64_t &x = cur[(size_t)where[r.instance]];
-    if (r.count > c->max_index(h) - x)
-      return c->fail(PHPRNG_E_RANGE, "request %llu: position beyond range", (unsigned long long)i);
-    x += r.count;
-  }
-  phprng_status st = c->take_slot(std::max<uint64_t>(nreq, 1), slot);
-  if (st != PHPRNG_OK) return st;
-  for (size_t t = 0; t < touched.size(); ++t) cur[t] = c->inst[touched[t]].x;
-  uint64_t w64 = 0, w32 = n64;
-  for (uint64_t i = 0; i < nreq; ++i) {
-    const phprng_request &r = reqs[i];
-    const HostInst &h = c->inst[r.instance];
-    uint64_t &x = cur[(size_t)where[r.instance]];
-    HostReq rec;
-    memset(&rec, 0, sizeof rec);
-    rec.k = x;
-    rec.count = r.count;
-    rec.out_off = r.out_offset;
-    rec.inst = r.instance;
-    c->h_req[h.width == 64 ? w64++ : w32++] = rec;
-    x += r.count;
-  }
-  moves->clear();
-  for (size_t t = 0; t < touched.size(); ++t) moves->push_back({touched[t], cur[t]});
-  return PHPRNG_OK;
-}
-
-}  // namespace
-
-static GenArgs make_args(phprng_ctx *c, ReqRec *d_req, const uint64_t *d_gbase, PlanHdr *d_hdr, uint64_t nreq,
-                         uint32_t *out_c32, uint64_t *out_c64, double *out_r, uint32_t tpc) {
-  GenArgs A;
-  A.inst = c->d_inst;
-  A.req = d_req;
-  A.gbase = d_gbase;
-  A.hdr = d_hdr;
-  A.nreq = nreq;
-  A.tab = SkipTables{c->d_u32, c->d_s32, c->d_u64lo, c->d_u64hi, c->d_s64, c->u32.size(), c->s64.size()};
-  A.lanemul = c->d_lanemul;
-  A.out_c32 = out_c32;
-  A.out_c64 = out_c64;
-  A.out_r = out_r;
-  A.tiles_per_chunk = tpc;
-  return A;
-}
+// ---------------------------------------------------------------------------
+// generation
+// ---------------------------------------------------------------------------
 
 extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *reqs, uint64_t nreq, uint32_t *out_c32,
                                          uint64_t *out_c64, double *out_r, uint64_t capacity, void *stream,
@@ -794,48 +1237,27 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
   if (mode != PHPRNG_MODE_PERSISTENT && mode != PHPRNG_MODE_PLAIN) return c->fail(PHPRNG_E_INVALID, "bad mode");
   if (nreq == 0) return PHPRNG_OK;
   (void)hipSetDevice(c->device);
-  bool has64 = false;
-  std::vector<std::pair<uint32_t, uint64_t>> moves;
   phprng_ctx::Slot *slot = nullptr;
-  phprng_status st = prepare_requests(c, reqs, nreq, capacity, &slot, &has64, &moves);
+  phprng_status st = c->take_slot(nreq, &slot);
   if (st != PHPRNG_OK) return st;
+  Plan P;
+  st = c->plan(reqs, nreq, capacity, mode, nullptr, slot->cap, slot->h_blk, &P);
+  if (st != PHPRNG_OK) return st;
+  if ((st = c->ensure_tiles(*slot, P.tiles64)) != PHPRNG_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const phprng_tuning &T = c->tuning;
-  uint32_t tpc = mode == PHPRNG_MODE_PLAIN ? 1u : (uint32_t)T.tiles_per_chunk;
-  // Upper bound on the tiles of the batch (a request touches at most
-  // count / 2048 + 2 tiles, one more at a skip-period boundary).
-  uint64_t tiles = 0;
-  for (uint64_t i = 0; i < nreq; ++i)
-    tiles += slot->h_req[i].count ? slot->h_req[i].count / kTile + 3 : 0;
-  const uint64_t waves = (uint64_t)c->num_cus * T.blocks_per_cu * (T.block_threads / 64);
-  // Small batches: shrink the chunk so that every resident wave gets work.
-  while (tpc > 1 && tiles < 4 * waves * tpc) tpc >>= 1;
-  // the plan reads the request list from the slot's pinned buffer directly
-  hipError_t e = launch_plan(c->d_inst, slot->h_req_dev, slot->d_req, nreq, slot->d_gbase, slot->d_hdr, tpc, s);
-  if (e != hipSuccess) return c->hip_fail(e, "plan");
-  GenArgs A = make_args(c, slot->d_req, slot->d_gbase, slot->d_hdr, nreq, out_c32, out_c64, out_r, tpc);
+  hipError_t e;
+  const uint64_t bytes = sizeof(BatchHdr) + nreq * sizeof(ReqRec);
+  if ((e = hipMemcpyAsync(slot->d_blk, slot->h_blk, bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return c->hip_fail(e, "request copy");
+  GenArgs A = c->args(slot->d_blk, slot->d_ctr, slot->d_t64, slot->cap64, nreq, out_c32, out_c64, out_r, P.tpc);
   if ((e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
-  if (mode == PHPRNG_MODE_PERSISTENT) {
-    // no more blocks than the batch can keep busy
-    const uint64_t wpb = (uint64_t)T.block_threads / 64;
-    const uint64_t need = (tiles + tpc - 1) / tpc;
-    const unsigned grid = (unsigned)std::max<uint64_t>(
-        1, std::min<uint64_t>((uint64_t)c->num_cus * T.blocks_per_cu, (need + wpb - 1) / wpb));
-    e = launch_persistent(A, grid, T.block_threads, T.unroll, has64, s);
-    if (e != hipSuccess) return c->hip_fail(e, "persistent launch");
-  } else {
-    for (uint64_t i = 0; i < nreq; ++i) {
-      const HostReq &r = slot->h_req[i];
-      const unsigned grid = r.count ? (unsigned)(r.count / kTile + 3) : 0u;
-      e = launch_plain(A, i, grid, T.unroll, c->inst[r.inst].width == 64, s);
-      if (e != hipSuccess) return c->hip_fail(e, "plain launch");
-    }
-  }
+  st = c->launch(P, A, reinterpret_cast<const ReqRec *>(slot->h_blk + sizeof(BatchHdr)), s, mode);
+  if (st != PHPRNG_OK) return st;
   if ((e = hipEventRecord(slot->ev1, s)) != hipSuccess) return c->hip_fail(e, "event");
   if ((e = hipEventRecord(slot->done, s)) != hipSuccess) return c->hip_fail(e, "event");
   slot->busy = true;
   c->last_timed = c->cur_slot;
-  for (auto &mv : moves) c->inst[mv.first].x = mv.second;
+  c->commit_plan();
   return PHPRNG_OK;
 }
 
@@ -877,6 +1299,10 @@ extern "C" phprng_status phprng_timing_read(phprng_ctx *c, double *total_ms, uin
   return PHPRNG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// state
+// ---------------------------------------------------------------------------
+
 extern "C" phprng_status phprng_get_params(phprng_ctx *c, uint32_t id, uint64_t *n, uint64_t *e, uint64_t *p,
                                            uint64_t *a, int *width) {
   if (!c || id >= c->inst.size()) return PHPRNG_E_INVALID;
@@ -891,42 +1317,53 @@ extern "C" phprng_status phprng_get_params(phprng_ctx *c, uint32_t id, uint64_t 
 
 extern "C" phprng_status phprng_get_state(phprng_ctx *c, uint32_t id, phprng_state *out) {
   if (!c || !out || id >= c->inst.size()) return PHPRNG_E_INVALID;
+  (void)hipSetDevice(c->device);
   const HostInst &h = c->inst[id];
   uint64_t m, s;
-  c->state_at(h, h.x, &m, &s);
+  if (lcg64(h)) {
+    phprng_status st = c->read_m64(id, &m);
+    if (st != PHPRNG_OK) return st;
+    s = group(64).powmod(kA64, h.x);
+  } else {
+    c->state_at(h, h.x, &m, &s);
+  }
   Mont64 M(h.n);
   out->m = m;
   out->s = s;
   out->c = M.powmod(m, h.e);
-  out->k = (uint64_t)((int64_t)h.x - h.kofs);
+  out->k = h.k;
   return PHPRNG_OK;
 }
 
 extern "C" phprng_status phprng_get_position(phprng_ctx *c, uint32_t id, uint64_t *k) {
   if (!c || !k || id >= c->inst.size()) return PHPRNG_E_INVALID;
-  const HostInst &h = c->inst[id];
-  *k = (uint64_t)((int64_t)h.x - h.kofs);
+  *k = c->inst[id].k;
   return PHPRNG_OK;
 }
 
 extern "C" phprng_status phprng_jump(phprng_ctx *c, uint32_t id, int64_t delta) {
   if (!c || id >= c->inst.size()) return PHPRNG_E_INVALID;
+  (void)hipSetDevice(c->device);
   HostInst &h = c->inst[id];
-  const uint64_t k = (uint64_t)((int64_t)h.x - h.kofs);
-  if (delta < 0) {
-    const uint64_t d = (uint64_t)(-(delta + 1)) + 1;
-    if (d > k || d > h.x) return c->fail(PHPRNG_E_RANGE, "jump before position 0");
-    h.x -= d;
+  const bool forward = delta >= 0;
+  const uint64_t d = forward ? (uint64_t)delta : (uint64_t)(-(delta + 1)) + 1;
+  if (forward ? d > ~0ull - h.k : d > h.k) return c->fail(PHPRNG_E_RANGE, "jump beyond the position range");
+  if (lcg64(h)) {
+    phprng_status st = c->move64(id, d, forward, false);
+    if (st != PHPRNG_OK) return st;
+    const uint64_t pm1 = kP64 - 1, r = d % pm1;
+    h.x = forward ? add_u64_mod(h.x, r, pm1) : (h.x >= r ? h.x - r : h.x + (pm1 - r));
   } else {
-    const uint64_t d = (uint64_t)delta;
-    if (d > c->max_index(h) - h.x) return c->fail(PHPRNG_E_RANGE, "jump beyond range");
-    h.x += d;
+    if (forward ? d > ~0ull - h.x : d > h.x) return c->fail(PHPRNG_E_RANGE, "jump beyond the position range");
+    h.x = forward ? h.x + d : h.x - d;
   }
+  h.k = forward ? h.k + d : h.k - d;
   return PHPRNG_OK;
 }
 
 extern "C" phprng_status phprng_set_state(phprng_ctx *c, uint32_t id, const phprng_state *st) {
   if (!c || !st || id >= c->inst.size()) return PHPRNG_E_INVALID;
+  (void)hipSetDevice(c->device);
   HostInst &h = c->inst[id];
   if (h.sched == kSchedConstant) {
     if (st->m >= h.n || st->s != h.b) return c->fail(PHPRNG_E_INVALID, "bad state for a constant skip");
@@ -934,26 +1371,25 @@ extern "C" phprng_status phprng_set_state(phprng_ctx *c, uint32_t id, const phpr
     HostInst tmp = h;
     tmp.mbase = M.sub(st->m, M.mulmod(st->k % h.n, h.b));
     InstRec rec = c->make_record(tmp);
-    (void)hipSetDevice(c->device);
     hipError_t e = hipMemcpy(c->d_inst + id, &rec, sizeof rec, hipMemcpyHostToDevice);
     if (e != hipSuccess) return c->hip_fail(e, "instance upload");
     h.mbase = tmp.mbase;
-    h.x = st->k;
-    h.kofs = 0;
+    h.x = h.k = st->k;
     return PHPRNG_OK;
   }
   const SkipGroup &G = group(h.width);
   if (st->m >= h.n || st->s == 0 || st->s >= G.p) return c->fail(PHPRNG_E_INVALID, "bad state");
   const uint64_t pm1 = G.p - 1;
   const uint64_t t = G.dlog(st->s);
-  uint64_t x;
-  if (h.width == 32) {
-    const uint64_t q = st->k / pm1;
-    x = q * pm1 + t;
-  } else {
-    x = t;
-    if (x >= kMaxPos64) return c->fail(PHPRNG_E_RANGE, "skip state beyond the width-64 index range");
+  if (h.width == 64) {
+    phprng_status ws = c->write_m64(id, st->m);
+    if (ws != PHPRNG_OK) return ws;
+    h.x = t;
+    h.k = st->k;
+    return PHPRNG_OK;
   }
+  const uint64_t q = st->k / pm1;
+  const uint64_t x = q * pm1 + t;
   HostInst tmp = h;
   tmp.mbase = 0;
   uint64_t mu, su;
@@ -962,35 +1398,65 @@ extern "C" phprng_status phprng_set_state(phprng_ctx *c, uint32_t id, const phpr
   const uint64_t mbase = M.sub(st->m, mu);
   tmp.mbase = mbase;
   InstRec rec = c->make_record(tmp);
-  (void)hipSetDevice(c->device);
   hipError_t e = hipMemcpy(c->d_inst + id, &rec, sizeof rec, hipMemcpyHostToDevice);
   if (e != hipSuccess) return c->hip_fail(e, "instance upload");
   h.mbase = mbase;
   h.x = x;
-  h.kofs = (int64_t)(x - st->k);
+  h.k = st->k;
   return PHPRNG_OK;
 }
 
-extern "C" phprng_status phprng_set_tuning(phprng_ctx *c, const phprng_tuning *t) {
-  if (!c || !t) return PHPRNG_E_INVALID;
-  phprng_tuning v = c->tuning;
-  if (t->block_threads) v.block_threads = t->block_threads;
-  if (t->blocks_per_cu) v.blocks_per_cu = t->blocks_per_cu;
-  if (t->tiles_per_chunk) v.tiles_per_chunk = t->tiles_per_chunk;
-  if (t->unroll) v.unroll = t->unroll;
+// ---------------------------------------------------------------------------
+// launch shapes
+// ---------------------------------------------------------------------------
+
+static phprng_status check_tuning(phprng_ctx *c, const phprng_tuning &v) {
   if (v.block_threads != 64 && v.block_threads != 128 && v.block_threads != 256 && v.block_threads != 512)
     return c->fail(PHPRNG_E_INVALID, "block_threads");
   if (v.blocks_per_cu < 1 || v.blocks_per_cu > 64) return c->fail(PHPRNG_E_INVALID, "blocks_per_cu");
   if (v.tiles_per_chunk < 1 || v.tiles_per_chunk > 64) return c->fail(PHPRNG_E_INVALID, "tiles_per_chunk");
   if (v.unroll != 1 && v.unroll != 2 && v.unroll != 4) return c->fail(PHPRNG_E_INVALID, "unroll");
-  c->tuning = v;
+  return PHPRNG_OK;
+}
+
+static phprng_tuning merge_tuning(const phprng_tuning &base, const phprng_tuning *t) {
+  phprng_tuning v = base;
+  if (t->block_threads) v.block_threads = t->block_threads;
+  if (t->blocks_per_cu) v.blocks_per_cu = t->blocks_per_cu;
+  if (t->tiles_per_chunk) v.tiles_per_chunk = t->tiles_per_chunk;
+  if (t->unroll) v.unroll = t->unroll;
+  return v;
+}
+
+extern "C" phprng_status phprng_set_tuning_class(phprng_ctx *c, int cls, const phprng_tuning *t) {
+  if (!c || !t || cls < 0 || cls > 2) return PHPRNG_E_INVALID;
+  const phprng_tuning v = merge_tuning(c->tuning[cls], t);
+  phprng_status st = check_tuning(c, v);
+  if (st != PHPRNG_OK) return st;
+  c->tuning[cls] = v;
+  return PHPRNG_OK;
+}
+
+extern "C" phprng_status phprng_get_tuning_class(phprng_ctx *c, int cls, phprng_tuning *t) {
+  if (!c || !t || cls < 0 || cls > 2) return PHPRNG_E_INVALID;
+  *t = c->tuning[cls];
+  return PHPRNG_OK;
+}
+
+extern "C" phprng_status phprng_set_tuning(phprng_ctx *c, const phprng_tuning *t) {
+  if (!c || !t) return PHPRNG_E_INVALID;
+  phprng_tuning v[3];
+  for (int cls = 0; cls < 3; ++cls) {
+    v[cls] = merge_tuning(c->tuning[cls], t);
+    phprng_status st = check_tuning(c, v[cls]);
+    if (st != PHPRNG_OK) return st;
+  }
+  for (int cls = 0; cls < 3; ++cls) c->tuning[cls] = v[cls];
   return PHPRNG_OK;
 }
 
 extern "C" phprng_status phprng_get_tuning(phprng_ctx *c, phprng_tuning *t) {
-  if (!c || !t) return PHPRNG_E_INVALID;
-  *t = c->tuning;
-  return PHPRNG_OK;
+  return phprng_get_tuning_class(c, PHPRNG_CLASS_W32, t);
 }
 
 extern "C" phprng_status phprng_autotune(phprng_ctx *c, uint64_t draws, phprng_tuning *best) {
@@ -1004,25 +1470,31 @@ extern "C" phprng_status phprng_autotune(phprng_ctx *c, uint64_t draws, phprng_t
   const uint64_t cap = ninst * per;
   bool any64 = false, any32 = false;
   for (uint64_t i = 0; i < ninst; ++i) (c->inst[i].width == 64 ? any64 : any32) = true;
-  uint32_t *d_c32 = nullptr;
-  uint64_t *d_c64 = nullptr;
+  const int cls = any64 ? (any32 ? kMixBoth : kMix64) : kMix32;
   double *d_r = nullptr;
   hipError_t e;
   if ((e = hipMalloc(&d_r, cap * 8)) != hipSuccess) return c->hip_fail(e, "autotune alloc");
-  (void)any32;
-  (void)any64;
-  std::vector<uint64_t> saved(ninst);
-  for (uint64_t i = 0; i < ninst; ++i) saved[i] = c->inst[i].x;
-  const phprng_tuning orig = c->tuning;
+  // positions and (width 64) device messages are restored afterwards
+  std::vector<std::pair<uint64_t, uint64_t>> saved(ninst);
+  for (uint64_t i = 0; i < ninst; ++i) saved[i] = {c->inst[i].x, c->inst[i].k};
+  std::vector<uint64_t> m64;
   phprng_status result = PHPRNG_OK;
+  if (any64) {
+    if ((result = c->sync_chain()) == PHPRNG_OK) {
+      m64.resize(ninst);
+      if ((e = hipMemcpy(m64.data(), c->d_m64, ninst * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        result = c->hip_fail(e, "autotune save");
+    }
+  }
+  const phprng_tuning orig = c->tuning[cls];
   // one timed call: median kernel time of `reps` calls of shape t
   auto run = [&](const phprng_tuning &t, int reps) -> double {
-    c->tuning = t;
+    c->tuning[cls] = t;
     std::vector<double> v;
     for (int rep = 0; rep < reps && result == PHPRNG_OK; ++rep) {
-      for (uint64_t i = 0; i < ninst; ++i) c->inst[i].x = saved[i];
-      phprng_status st =
-          phprng_generate(c, reqs.data(), ninst, d_c32, d_c64, d_r, cap, nullptr, PHPRNG_MODE_PERSISTENT);
+      for (uint64_t i = 0; i < ninst; ++i) std::tie(c->inst[i].x, c->inst[i].k) = saved[i];
+      phprng_status st = phprng_generate(c, reqs.data(), ninst, nullptr, nullptr, d_r, cap, nullptr,
+                                         PHPRNG_MODE_PERSISTENT);
       double ms = 0;
       if (st == PHPRNG_OK) st = phprng_last_kernel_ms(c, &ms);
       if (st != PHPRNG_OK) result = st;
@@ -1032,33 +1504,46 @@ extern "C" phprng_status phprng_autotune(phprng_ctx *c, uint64_t draws, phprng_t
     std::sort(v.begin(), v.end());
     return v[v.size() / 2];
   };
-  // bring the clocks up before timing anything
-  auto t0 = std::chrono::steady_clock::now();
-  while (result == PHPRNG_OK && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(300)) run(orig, 1);
   phprng_tuning bestT = orig;
-  double best_ms = run(orig, 5);
-  const int blocks[] = {256, 512, 128, 64};
-  const int bpcs[] = {1, 2, 4, 8};
-  const int tpcs[] = {1, 2, 4, 8, 16};
-  const int unrolls[] = {1, 2, 4};
-  for (int b : blocks)
-    for (int bpc : bpcs)
-      for (int tpc : tpcs)
-        for (int u : unrolls) {
-          if (b * bpc > 2048 || result != PHPRNG_OK) continue;
-          const phprng_tuning t{b, bpc, tpc, u};
-          const double ms = run(t, 3);
-          if (ms < best_ms) {
-            best_ms = ms;
-            bestT = t;
+  if (result == PHPRNG_OK) {
+    // bring the clocks up before timing anything
+    auto t0 = std::chrono::steady_clock::now();
+    while (result == PHPRNG_OK && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(300)) run(orig, 1);
+    double best_ms = run(orig, 5);
+    const int blocks[] = {256, 512, 128, 64};
+    const int bpcs[] = {1, 2, 4, 8};
+    const int tpcs[] = {1, 2, 4, 8, 16};
+    const int unrolls[] = {1, 2, 4};
+    for (int b : blocks)
+      for (int bpc : bpcs)
+        for (int tpc : tpcs)
+          for (int u : unrolls) {
+            if (b * bpc > 2048 || result != PHPRNG_OK) continue;
+            const phprng_tuning t{b, bpc, tpc, u};
+            const double ms = run(t, 3);
+            if (ms < best_ms) {
+              best_ms = ms;
+              bestT = t;
+            }
           }
-        }
-  // confirm the winner against the starting shape with more repetitions
-  if (result == PHPRNG_OK && run(bestT, 7) > run(orig, 7)) bestT = orig;
-  for (uint64_t i = 0; i < ninst; ++i) c->inst[i].x = saved[i];
+    // confirm the winner against the starting shape with more repetitions
+    if (result == PHPRNG_OK && run(bestT, 7) > run(orig, 7)) bestT = orig;
+  }
+  for (uint64_t i = 0; i < ninst; ++i) std::tie(c->inst[i].x, c->inst[i].k) = saved[i];
+  if (any64 && !m64.empty()) {
+    phprng_status s2 = c->sync_chain();
+    if (s2 == PHPRNG_OK && (e = hipMemcpy(c->d_m64, m64.data(), ninst * 8, hipMemcpyHostToDevice)) != hipSuccess)
+      s2 = c->hip_fail(e, "autotune restore");
+    if (result == PHPRNG_OK) result = s2;
+  }
+  (void)hipDeviceSynchronize();
   (void)hipFree(d_r);
-  c->tuning = result == PHPRNG_OK ? bestT : orig;
-  if (best) *best = c->tuning;
+  c->tuning[cls] = result == PHPRNG_OK ? bestT : orig;
+  if (result == PHPRNG_OK) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[TuneKey{c->arch, c->num_cus, cls}] = bestT;
+  }
+  if (best) *best = c->tuning[cls];
   return result;
 }
 
@@ -1069,8 +1554,9 @@ extern "C" phprng_status phprng_autotune(phprng_ctx *c, uint64_t draws, phprng_t
 extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request *reqs, uint64_t nreq,
                                              uint32_t *out_c32, uint64_t *out_c64, double *out_r, uint64_t capacity,
                                              void *stream, phprng_graph **graph) {
-  if (!c || !graph || nreq == 0) return PHPRNG_E_INVALID;
+  if (!c || !graph || nreq == 0 || !reqs) return PHPRNG_E_INVALID;
   *graph = nullptr;
+  (void)stream;
   (void)hipSetDevice(c->device);
   {
     std::vector<uint8_t> used(c->inst.size(), 0);
@@ -1081,46 +1567,43 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
       }
     }
   }
-  bool has64 = false;
-  std::vector<std::pair<uint32_t, uint64_t>> moves;
+  // plan once from the current positions (not reserved: every launch plans again)
   phprng_ctx::Slot *slot = nullptr;
-  phprng_status st = prepare_requests(c, reqs, nreq, capacity, &slot, &has64, &moves);
+  phprng_status st = c->take_slot(nreq, &slot);
   if (st != PHPRNG_OK) return st;
-  // every launch advances each instance by its count: the first launch starts
-  // at the current positions (prepare_requests recorded them in h_req)
+  Plan P;
+  st = c->plan(reqs, nreq, capacity, PHPRNG_MODE_PERSISTENT, nullptr, slot->cap, slot->h_blk, &P);
+  if (st != PHPRNG_OK) return st;
   std::unique_ptr<phprng_graph> g(new (std::nothrow) phprng_graph);
   if (!g) return PHPRNG_E_NOMEM;
   g->ctx = c;
+  g->reqs.assign(reqs, reqs + nreq);
+  g->nreq64 = P.nreq64;
+  g->tiles64 = P.tiles64;
+  g->tpc = P.tpc;
+  g->has64 = P.has64;
   hipError_t e;
-  if ((e = hipMalloc(&g->d_src, nreq * sizeof(HostReq))) != hipSuccess) return c->hip_fail(e, "graph alloc");
-  if ((e = hipMalloc(&g->d_req, nreq * sizeof(ReqRec))) != hipSuccess) return c->hip_fail(e, "graph alloc");
-  if ((e = hipMalloc(&g->d_gbase, (nreq + kPlanGroup - 1) / kPlanGroup * sizeof(uint64_t))) != hipSuccess)
-    return c->hip_fail(e, "graph alloc");
-  if ((e = hipMalloc(&g->d_hdr, sizeof(PlanHdr))) != hipSuccess) return c->hip_fail(e, "graph alloc");
-  if ((e = hipMemset(g->d_hdr, 0, sizeof(PlanHdr))) != hipSuccess) return c->hip_fail(e, "graph alloc");
-  if ((e = hipMemcpy(g->d_src, c->h_req, nreq * sizeof(HostReq), hipMemcpyHostToDevice)) != hipSuccess)
-    return c->hip_fail(e, "graph upload");
-  for (uint64_t i = 0; i < nreq; ++i) {
-    g->inst.push_back(c->h_req[i].inst);
-    g->count.push_back(c->h_req[i].count);
-  }
+  const uint64_t bytes = sizeof(BatchHdr) + nreq * sizeof(ReqRec);
+  const uint64_t cap64 = std::max<uint64_t>(P.tiles64, 1);
+  if ((e = hipMalloc(&g->d_blk, bytes)) != hipSuccess) return c->hip_fail(e, "graph alloc");
+  if ((e = hipMalloc(&g->d_ctr, sizeof(WorkCtr))) != hipSuccess) return c->hip_fail(e, "graph alloc");
+  if ((e = hipMemset(g->d_ctr, 0, sizeof(WorkCtr))) != hipSuccess) return c->hip_fail(e, "graph alloc");
+  if ((e = hipMalloc(&g->d_t64, 3 * cap64 * sizeof(uint64_t))) != hipSuccess) return c->hip_fail(e, "graph alloc");
+  if ((e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming)) != hipSuccess) return c->hip_fail(e, "event");
+  const phprng_tuning &T = c->tuning[P.cls];
+  GenArgs A = c->args(g->d_blk, g->d_ctr, g->d_t64, cap64, nreq, out_c32, out_c64, out_r, P.tpc);
   hipStream_t cap_stream;
   if ((e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking)) != hipSuccess) return c->hip_fail(e, "stream");
-  const phprng_tuning &T = c->tuning;
-  GenArgs A = make_args(c, g->d_req, g->d_gbase, g->d_hdr, nreq, out_c32, out_c64, out_r,
-                        (uint32_t)T.tiles_per_chunk);
   e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess && P.nreq64 > 0) e = launch_tiles64_reduce(A, P.tiles64, (unsigned)c->num_cus * 8, cap_stream);
+  if (e == hipSuccess && P.nreq64 > 0) e = launch_tiles64_scan(A, P.nreq64, cap_stream);
   if (e == hipSuccess)
-    e = launch_plan(c->d_inst, g->d_src, g->d_req, nreq, g->d_gbase, g->d_hdr, A.tiles_per_chunk, cap_stream);
-  if (e == hipSuccess)
-    e = launch_persistent(A, (unsigned)(c->num_cus * T.blocks_per_cu), T.block_threads, T.unroll, has64, cap_stream);
-  if (e == hipSuccess) e = launch_advance(g->d_src, nreq, cap_stream);
+    e = launch_persistent(A, (unsigned)(c->num_cus * T.blocks_per_cu), T.block_threads, T.unroll, P.has64, cap_stream);
   hipError_t e2 = hipStreamEndCapture(cap_stream, &g->graph);
   (void)hipStreamDestroy(cap_stream);
   if (e != hipSuccess || e2 != hipSuccess) return c->hip_fail(e != hipSuccess ? e : e2, "graph capture");
   if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
     return c->hip_fail(e, "graph instantiate");
-  (void)stream;
   *graph = g.release();
   return PHPRNG_OK;
 }
@@ -1129,23 +1612,40 @@ extern "C" phprng_status phprng_graph_launch(phprng_graph *g, void *stream) {
   if (!g || !g->ctx) return PHPRNG_E_INVALID;
   phprng_ctx *c = g->ctx;
   (void)hipSetDevice(c->device);
-  // range check before launching: each instance advances by its count
-  for (size_t i = 0; i < g->inst.size(); ++i) {
-    const HostInst &h = c->inst[g->inst[i]];
-    if (g->count[i] > c->max_index(h) - h.x) return c->fail(PHPRNG_E_RANGE, "graph launch beyond range");
-  }
-  hipStream_t s = (hipStream_t)stream;
+  const uint64_t nreq = g->reqs.size();
   phprng_ctx::Slot *slot = nullptr;
-  phprng_status st = c->take_slot(1, &slot);
+  phprng_status st = c->take_slot(nreq, &slot);
   if (st != PHPRNG_OK) return st;
+  // plan from the instances' current positions, whatever moved them since
+  // the last launch (generate, jump, set_state)
+  Plan P;
+  uint64_t capacity = ~0ull;
+  st = c->plan(g->reqs.data(), nreq, capacity, PHPRNG_MODE_PERSISTENT, &g->tpc, slot->cap, slot->h_blk, &P);
+  if (st != PHPRNG_OK) return st;
+  if (P.nreq64 != g->nreq64 || P.tiles64 != g->tiles64)
+    return c->fail(PHPRNG_E_INVALID, "graph requests no longer match their instances");
+  hipStream_t s = (hipStream_t)stream;
   hipError_t e;
+  // the previous launch must be done with the request block before it is rewritten
+  if (g->launched && (e = hipStreamWaitEvent(s, g->done, 0)) != hipSuccess) return c->hip_fail(e, "graph wait");
+  const uint64_t bytes = sizeof(BatchHdr) + nreq * sizeof(ReqRec);
+  if ((e = hipMemcpyAsync(g->d_blk, slot->h_blk, bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return c->hip_fail(e, "request copy");
+  if (g->nreq64 > 0 && c->chain_pending && (e = hipStreamWaitEvent(s, c->chain_ev, 0)) != hipSuccess)
+    return c->hip_fail(e, "chain wait");
   if ((e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
   if ((e = hipGraphLaunch(g->exec, s)) != hipSuccess) return c->hip_fail(e, "graph launch");
   if ((e = hipEventRecord(slot->ev1, s)) != hipSuccess) return c->hip_fail(e, "event");
   if ((e = hipEventRecord(slot->done, s)) != hipSuccess) return c->hip_fail(e, "event");
+  if ((e = hipEventRecord(g->done, s)) != hipSuccess) return c->hip_fail(e, "event");
+  if (g->nreq64 > 0) {
+    if ((e = hipEventRecord(c->chain_ev, s)) != hipSuccess) return c->hip_fail(e, "chain record");
+    c->chain_pending = true;
+  }
+  g->launched = true;
   slot->busy = true;
   c->last_timed = c->cur_slot;
-  for (size_t i = 0; i < g->inst.size(); ++i) c->inst[g->inst[i]].x += g->count[i];
+  c->commit_plan();
   return PHPRNG_OK;
 }
 
@@ -1153,12 +1653,6 @@ extern "C" phprng_status phprng_graph_destroy(phprng_graph *g) {
   if (!g) return PHPRNG_E_INVALID;
   if (g->ctx) (void)hipSetDevice(g->ctx->device);
   (void)hipDeviceSynchronize();
-  if (g->exec) (void)hipGraphExecDestroy(g->exec);
-  if (g->graph) (void)hipGraphDestroy(g->graph);
-  (void)hipFree(g->d_src);
-  (void)hipFree(g->d_req);
-  (void)hipFree(g->d_gbase);
-  (void)hipFree(g->d_hdr);
   delete g;
   return PHPRNG_OK;
 }

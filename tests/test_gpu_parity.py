@@ -272,20 +272,20 @@ def test_state_get_set_and_jumps(ph, ctx, orc, tabs):
         compare_request(hc32, hr, 0, 7000, cc, rr, "restored")
         st = ctx.get_state(iid)
         assert (st[0], st[1], st[3]) == (m2, s2, k1 + 7000)
-    # 64-bit: restore to a state with a small skip logarithm
+    # 64-bit: restore to any state (m, s): small and arbitrary skip logarithms
     n64, e64, _ = orc.seed(64, SEED0 + 81, 2, (9, 17))
     ids64 = ctx.add_instances(64, n64, e64)
     p64, a64 = orc.lcg_params(64)
     for iid, n, e in zip(ids64, n64, e64):
         iid, n, e = int(iid), int(n), int(e)
-        t = rng.randrange(0, 1 << 26)
-        m1, s1 = rng.randrange(n), pow(a64, t, p64)
-        ctx.set_state(iid, m1, s1, 12345)
-        (_, hc64, hr), _ = _run(ph, ctx, [(iid, 3000)])
-        cc, rr, _ = oracle_draws(orc, tabs, 64, n, e, 0, 3000, m0=m1, s0=s1)
-        compare_request(hc64, hr, 0, 3000, cc, rr, "restored64")
-        with pytest.raises(ph.PhprngError):
-            ctx.set_state(iid, m1, rng.randrange(2, p64), 0)  # skip log beyond the 64-bit index range
+        for s1, k1 in ((pow(a64, rng.randrange(0, 1 << 26), p64), 12345), (rng.randrange(2, p64), (1 << 63) + 5)):
+            m1 = rng.randrange(n)
+            ctx.set_state(iid, m1, s1, k1)
+            assert ctx.get_state(iid) == (m1, s1, orc.encrypt(m1, e, n), k1)
+            (_, hc64, hr), _ = _run(ph, ctx, [(iid, 3000)])
+            cc, rr, (m2, s2) = oracle_draws(orc, tabs, 64, n, e, 0, 3000, m0=m1, s0=s1)
+            compare_request(hc64, hr, 0, 3000, cc, rr, "restored64")
+            assert ctx.get_state(iid) == (m2, s2, orc.encrypt(m2, e, n), k1 + 3000)
 
 
 def test_graph_replays_continue_streams(ph, ctx, orc, tabs):
@@ -526,3 +526,152 @@ def test_device_seeding_matches_oracle_draw(ph, orc, tabs, width, count, es, klo
         wc, wr, _ = oracle_draws(orc, tabs, width, int(n_o[i]), int(e_o[i]), int(k_o[i]), cnt)
         compare_request(hc32 if width == 32 else hc64, hr, off, cnt, wc, wr, "device-seeded")
     c.close()
+
+
+def test_64bit_positions_from_any_state(ph, ctx, orc, tabs):
+    """Width-64 starts that the old skip-index bound could not reach: whole
+    skip periods plus a table offset (q p(p-1)/2 of eq. (7)), an arbitrary
+    supplied s0 (its skip log is ~2^60) moved on the device by millions of
+    draws, a start one short of a whole period from such an s0 (summed as
+    the complement), a request whose skip log crosses 2^34, a table start,
+    and a move that is too far from both, which is refused."""
+    rng = random.Random(1500)
+    p, a = orc.lcg_params(64)
+    n64, e64, _ = orc.seed(64, SEED0 + 150, 6, (9, 17, 3))
+    n64, e64 = [int(x) for x in n64], [int(x) for x in e64]
+    b_full = lambda n: (p * (p - 1) // 2) % n
+    cases = []
+    # (a) s0 = 1, k0 = 5 (p - 1) + 12345: the table plus five whole periods
+    cases.append(dict(m0=0, s0=1, k0=5 * (p - 1) + 12345))
+    # (b) arbitrary s0, k0 = 3e6 + 777: the skips are summed on the device
+    cases.append(dict(m0=rng.randrange(n64[1]), s0=rng.randrange(2, p), k0=3 * 10 ** 6 + 777))
+    # (c) arbitrary s0, k0 = (p - 1) - 2^20 - 3: a whole period less 2^20 + 3 draws
+    cases.append(dict(m0=rng.randrange(n64[2]), s0=rng.randrange(2, p), k0=(p - 1) - (1 << 20) - 3))
+    # (d) s0 = a^(2^34 - 1000): generation crosses skip log 2^34
+    cases.append(dict(m0=rng.randrange(n64[3]), s0=pow(a, (1 << 34) - 1000, p), k0=0))
+    # (e) s0 = 1, k0 = 2^26 + 5: positioned from the table
+    cases.append(dict(m0=0, s0=1, k0=(1 << 26) + 5))
+    ids = []
+    for i, cs in enumerate(cases):
+        ids += [int(x) for x in ctx.add_instances(64, [n64[i]], [e64[i]], m0=[cs["m0"]], s0=[cs["s0"]],
+                                                  k0=[cs["k0"]])]
+    specs = [(iid, 5000) for iid in ids]
+    (_, hc64, hr), offs = _run(ph, ctx, specs, want=(False, True, True))
+    for i, (cs, iid, off) in enumerate(zip(cases, ids, offs)):
+        n, e = n64[i], e64[i]
+        k0, m0, s0 = cs["k0"], cs["m0"], cs["s0"]
+        if i == 2:
+            # one whole period from (m0, s0) is (m0 + p(p-1)/2, s0); then back 2^20 + 3
+            m, s = orc.jump_backward(p, a, n, (m0 + b_full(n)) % n, s0, (p - 1) - k0)
+        else:
+            m, s = orc.position(tabs[64] if s0 == 1 else None, p, a, n, m0, s0, k0)
+        assert ctx.get_state(iid)[3] == k0 + 5000
+        wc, wr, _, _ = orc.generate(p, a, n, e, m, s, 5000)
+        compare_request(hc64, hr, off, 5000, wc, wr, "w64 start case %d" % i)
+    # (f) too far from both the table and a whole period: refused, nothing added
+    before = ctx.instance_count()
+    with pytest.raises(ph.PhprngError) as ex:
+        ctx.add_instances(64, [n64[5]], [e64[5]], s0=[rng.randrange(2, p)], k0=[1 << 50])
+    assert ex.value.status == ph.PHPRNG_E_RANGE
+    assert ctx.instance_count() == before
+
+
+def test_64bit_jumps_on_each_path(ph, ctx, orc, tabs):
+    """Forward and backward width-64 jumps from small and arbitrary skip
+    logs: on the table, summed on the device, and as the complement of a
+    whole period; each state checked against the oracle stepping."""
+    rng = random.Random(1600)
+    p, a = orc.lcg_params(64)
+    n64, e64, _ = orc.seed(64, SEED0 + 160, 3, (9, 17))
+    for j, (n, e) in enumerate(zip(n64, e64)):
+        n, e = int(n), int(e)
+        m0 = rng.randrange(n)
+        s0 = 1 if j == 0 else rng.randrange(2, p)
+        iid = int(ctx.add_instances(64, [n], [e], m0=[m0], s0=[s0])[0])
+        m, s, k = m0, s0, 0
+        for d in (1, 2047, 1 << 20, 3 * 10 ** 6 + 5, -(10 ** 6), -(1 << 21) - 1, 777):
+            ctx.jump(iid, d)
+            if d >= 0:
+                m, s = orc.jump_forward(p, a, n, m, s, d)
+            else:
+                m, s = orc.jump_backward(p, a, n, m, s, -d)
+            k += d
+            assert ctx.get_state(iid) == (m, s, orc.encrypt(m, e, n), k), (j, d)
+        # a whole period less 5000 forward: the complement path
+        d = (p - 1) - 5000
+        ctx.jump(iid, d)
+        m, s = orc.jump_backward(p, a, n, (m + (p * (p - 1) // 2)) % n, s, 5000)
+        k += d
+        assert ctx.get_state(iid) == (m, s, orc.encrypt(m, e, n), k)
+        # and back again
+        ctx.jump(iid, -d)
+        m, s = orc.jump_forward(p, a, n, (m - (p * (p - 1) // 2)) % n, s, 5000)
+        k -= d
+        assert ctx.get_state(iid) == (m, s, orc.encrypt(m, e, n), k)
+        # draws continue from the jumped state
+        (_, hc64, hr), _ = _run(ph, ctx, [(iid, 4000)], want=(False, True, True))
+        wc, wr, _, _ = orc.generate(p, a, n, e, m, s, 4000)
+        compare_request(hc64, hr, 0, 4000, wc, wr, "w64 after jumps %d" % j)
+
+
+def test_graph_replays_interleaved_with_other_calls(ph, ctx, orc, tabs):
+    """Between graph replays the same instances are drawn by generate,
+    jumped and restored; every replay continues from where the instances
+    then are, for both widths."""
+    import torch
+    n32, e32, k32 = orc.seed(32, SEED0 + 170, 3, (9, 17), 0, 1 << 40)
+    n64, e64, k64 = orc.seed(64, SEED0 + 171, 2, (9, 17), 0, 1 << 22)
+    ids = [int(x) for x in ctx.add_instances(32, n32, e32, k0=k32)] + \
+          [int(x) for x in ctx.add_instances(64, n64, e64, k0=k64)]
+    count = 3000
+    offs = [i * count for i in range(len(ids))]
+    c32, c64, r = alloc_outputs(count * len(ids))
+    g = ctx.graph(ph.make_requests(ids, [count] * len(ids), offs), c32, c64, r)
+    p32, a32 = orc.lcg_params(32)
+    p64, a64 = orc.lcg_params(64)
+    rng = random.Random(1700)
+
+    def check(label):
+        torch.cuda.synchronize()
+        hc32, hc64, hr = to_host(c32, c64, r)
+        for iid, off in zip(ids, offs):
+            n, e, p, a, w = ctx.get_params(iid)
+            m, s, _, k = expect[iid]
+            wc, wr, m2, s2 = orc.generate(p, a, n, e, m, s, count)
+            compare_request(hc32 if w == 32 else hc64, hr, off, count, wc, wr, label)
+            expect[iid] = (m2, s2, None, k + count)
+
+    expect = {iid: ctx.get_state(iid) for iid in ids}
+    g.launch()
+    check("replay 1")
+    # generate on the same instances, then replay
+    hc = _run(ph, ctx, [(iid, 1111) for iid in ids])
+    for iid in ids:
+        n, e, p, a, w = ctx.get_params(iid)
+        m, s, _, k = expect[iid]
+        _, _, m2, s2 = orc.generate(p, a, n, e, m, s, 1111)
+        expect[iid] = (m2, s2, None, k + 1111)
+    g.launch()
+    check("replay after generate")
+    # jumps both ways and a restore, then replay twice
+    for iid in ids:
+        n, e, p, a, w = ctx.get_params(iid)
+        m, s, _, k = expect[iid]
+        ctx.jump(iid, 5000)
+        m, s = orc.jump_forward(p, a, n, m, s, 5000)
+        ctx.jump(iid, -7000)
+        m, s = orc.jump_backward(p, a, n, m, s, 7000)
+        expect[iid] = (m, s, None, k - 2000)
+    iid = ids[-1]
+    n, e, p, a, w = ctx.get_params(iid)
+    m1, s1 = rng.randrange(n), rng.randrange(2, p)
+    ctx.set_state(iid, m1, s1, 999)
+    expect[iid] = (m1, s1, None, 999)
+    g.launch()
+    check("replay after jumps")
+    g.launch()
+    check("second replay after jumps")
+    for iid in ids:
+        assert ctx.get_state(iid)[3] == expect[iid][3]
+        assert ctx.get_state(iid)[:2] == expect[iid][:2]
+    g.close()
