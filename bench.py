@@ -1,22 +1,34 @@
 #!/usr/bin/env python3
-"""Benchmark of the gfx950 Pohlig-Hellman generator (one GPU).
+"""Benchmark of the gfx950 Pohlig-Hellman generator on one GPU.
 
-Headline workload: 4096 seeded 32-bit instances (distinct admissible primes
-n in [2^31, 2^32), e drawn from {9, 17} coprime to n - 1, start position 0),
-2^18 draws each per step -- 1,073,741,824 uniforms per step written to HBM as
-FP64 uniforms (a variant also writes the u32 ciphertexts).  A step is one batched persistent
-launch over all 4096 streams; each step continues every stream where the
-previous one ended and overwrites the same output arrays.  The same
-workload is also timed in the plain form (one launch per instance), and the
-CPU oracle is timed on a bounded sample of it.
+One JSON line.  `value` is the headline: 4096 seeded width-32 instances
+(distinct admissible primes n in [2^31, 2^32), e from {9, 17} coprime to
+n - 1, start position 0), 2^18 draws each per step, FP64 uniforms written
+to HBM, one batched persistent launch per step (1,073,741,824 uniforms per
+step; each step continues every stream).  Beside it, in the same run:
 
-Prints one JSON line.  `value` is whole-job throughput (Guniforms/s) with
-all inputs resident on the device.
+  - the same batch as one launch per instance (the plain form), as a
+    captured-graph replay, with u32 ciphertexts too, on the unit skip;
+  - 1 instance x 10^6 draws (c + R);
+  - 65,536 instances with log-uniform lengths in [2^10, 2^22] and starts in
+    [0, 2^40) (c + R over the fewest launches whose outputs fit the device,
+    and R only in one launch);
+  - 1024 width-64 + 1024 width-32 instances x 2^20 in one launch (c + R),
+    and each width alone;
+  - serving: 10^6 resident instances, Poisson arrivals at three rates, p50
+    and p99 latency;
+  - the CPU oracle on the host's cores over a bounded sample of the headline
+    batch.
+
+Every workload runs on synthetic seeded instances; inputs are resident on
+the device when the timed region starts.  Launch shapes are autotuned per
+batch class (width 32, width 64, mixed) before timing and reported.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,20 +39,26 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-SEED_B = 0x14112484 + 1
+from tests import workloads as W  # noqa: E402
+
+METRIC = "Guniforms/s (32/64-bit moduli), batched vs plain launch; serve p50/p99 latency"
+SEED_B = W.SEED0 + 1
 N_INST = 4096
 PER = 1 << 18
-HBM_PEAK_GBS = 8000.0         # MI355X published HBM3E bandwidth
-ALU_PEAK_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz, one VALU op per lane per clock
-
+HBM_PEAK_GBS = 8000.0            # MI355X published HBM3E bandwidth
+CUS, CLOCK_HZ = 256, 2.4e9       # MI355X compute units and peak engine clock
+ALU_PEAK_OPS = CUS * 64 * CLOCK_HZ  # one wave64 VALU instruction per CU per clock
 
 KERNEL_SOURCES = ["paper_1411_2484_amd/csrc/kernels.hip", "paper_1411_2484_amd/csrc/arith.hpp",
                   "paper_1411_2484_amd/csrc/layout.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gen_persistent_traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "gen_persistent_counters.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
-    import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -48,17 +66,17 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel sources (else None)."""
+def committed_counters():
+    """Per-launch counter figures of the headline kernel from the committed
+    rocprofv3 runs, when they were taken on the current kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(COUNTERS_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    return t.get("traffic_bytes_per_launch")
+    return t
 
 
 def algorithmic_ops_32(e):
@@ -69,16 +87,73 @@ def algorithmic_ops_32(e):
     return 6 + 4 + 6 * chain + 5
 
 
-def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+def algorithmic_ops_64(e):
+    """VALU operations per width-64 draw in the same model with 32-bit limbs:
+    skip mod 2^61 - 1 (a 64 x 64 product, four multiply-adds, and the
+    Mersenne fold) 10, message 4, Montgomery products 19 each (full x y,
+    low q = lo(x y) n', high q n, borrow), uniform 9 (two conversions, five
+    FP64 operations)."""
+    chain = {3: 3, 5: 4, 9: 5, 17: 6}[int(e)]
+    return 10 + 4 + 19 * chain + 9
 
 
-def cpu_baseline(e_arr, n_arr, target_s=12.0):
-    """The oracle on the host's cores over a bounded sample of the headline
-    workload: batches of 256 of the instances, 2^18 draws each from position
-    0, cycling over the 4096 instances until about target_s seconds."""
+def roofline(draws, kernel_ms, ops_per_draw, bytes_per_draw):
+    """ALU and HBM fractions of a generation launch (algorithmic work only)."""
+    sec = kernel_ms * 1e-3
+    ops = draws * ops_per_draw / sec
+    gbs = draws * bytes_per_draw / sec / 1e9
+    return {"alu": {"achieved": ops / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Top/s",
+                    "frac": ops / ALU_PEAK_OPS, "ops_per_draw": ops_per_draw},
+            "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                    "bytes_per_draw": bytes_per_draw}}
+
+
+def timed(ctx, torch, fn, steps, warmup):
+    """(wall ms per step, generation-kernel ms per step) of `steps` calls of fn."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ctx.timing_reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, _ = ctx.timing_read()
+    return wall * 1e3 / steps, kms / steps
+
+
+def release(torch):
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(n_arr, e_arr, target_s):
+    """The oracle on all of the host's cores over a bounded sample of the
+    headline workload: batches of 256 of its instances, 2^18 draws each from
+    position 0, cycling over the 4096 instances for about target_s seconds."""
     import oracle
-    nthreads = min(os.cpu_count() or 1, 16)
+    nthreads = host_cores()
     p, a = oracle.lcg_params(32)
     done_inst = 0
     t0 = time.perf_counter()
@@ -93,145 +168,250 @@ def cpu_baseline(e_arr, n_arr, target_s=12.0):
             break
     draws = done_inst * PER
     return {"value": draws / el / 1e9, "unit": "Guniforms/s", "cores": nthreads, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
             "ns_per_uniform_per_core": el * nthreads / draws * 1e9,
-            "sample": "%d instance-streams of the headline workload (2^18 draws each from position 0, "
-                      "%d draws) in %.1f s" % (done_inst, draws, el)}
+            "sample": "%d instance-streams of the headline batch (2^18 draws each from position 0, u32 c + f64 R, "
+                      "%d draws) in %.1f s on %d threads" % (done_inst, draws, el, nthreads)}
 
 
-def common_line(metric_value, unit, steps, warmup, ms_per_step, config, **extra):
-    out = {
-        "metric": "Guniforms/s (32/64-bit moduli), batched vs plain launch; serve p50/p99 latency",
-        "value": metric_value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32/u64/f64", "data": "synthetic", "config": config,
-    }
-    out.update(extra)
-    return out
+# ---------------------------------------------------------------------------
+# headline: 4096 x 2^18, width 32
+# ---------------------------------------------------------------------------
+
+def section_headline(args, torch, ph, out):
+    dev = torch.device("cuda:0")
+    ctx = ph.Context(0, max_instances=N_INST)
+    ids = ctx.seed_instances(32, SEED_B, N_INST, (9, 17), 0, 0)
+    params = [ctx.get_params(int(i)) for i in ids]
+    n_arr = np.array([p[0] for p in params], dtype=np.uint64)
+    e_arr = np.array([p[1] for p in params], dtype=np.uint64)
+    total = N_INST * PER
+    r = torch.empty(total, dtype=torch.float64, device=dev)
+    reqs = ph.make_requests(ids, [PER] * N_INST, np.arange(N_INST, dtype=np.uint64) * PER)
+    if args.calib_copy_gib > 0:
+        nel = int(args.calib_copy_gib * (1 << 30) / 8)
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (nel * 8, nel * 8))
+        del src, dst
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        ctx.autotune(total)  # on the batch itself: 4096 streams x 2^18
+        log("autotune (width 32): %s in %.1f s" % (ctx.get_tuning_class(ph.PHPRNG_CLASS_W32),
+                                                    time.perf_counter() - t0))
+    tuning = ctx.get_tuning_class(ph.PHPRNG_CLASS_W32)
+
+    def gen(mode=ph.PHPRNG_MODE_PERSISTENT, c32=None):
+        ctx.generate(reqs, c32, None, r, capacity=total, mode=mode)
+
+    ms, kms = timed(ctx, torch, gen, args.steps, args.warmup)
+    value = total / (ms * 1e-3) / 1e9
+    log("persistent: %.3f ms/step wall, %.3f ms kernel, %.1f Guniforms/s" % (ms, kms, value))
+    ops_per_draw = float(np.mean([algorithmic_ops_32(e) for e in e_arr]))
+    roofs = roofline(total, kms, ops_per_draw, 8.0)
+    roof = dict(roofs["alu"])
+    roof.update({"bound": "alu", "kernel": "gen_persistent<%d, %d, false>" % (tuning["block_threads"],
+                                                                           tuning["unroll"]),
+                 "kernel_ms": kms, "units_per_launch": total, "traffic": None})
+    cnt = committed_counters()
+    if cnt:
+        roof["traffic"] = cnt.get("traffic_bytes_per_launch")
+        # issued VALU lane-instructions and the hardware's VALU-busy cycles,
+        # per launch from the counter runs, against this run's kernel time
+        if cnt.get("valu_insts_per_launch"):
+            issued = cnt["valu_insts_per_launch"] * 64 / (kms * 1e-3)
+            roof["issued_valu_frac"] = issued / ALU_PEAK_OPS
+        for k in ("valu_busy_frac", "clock_ghz", "cycle_weighted_frac", "cycle_weighted_model"):
+            if k in cnt:
+                roof[k] = cnt[k]
+    out.update({"value": value, "ms_per_step": ms, "roofline": roof, "roofline_hbm": roofs["hbm"]})
+    out["config"].update({"tuning": tuning})
+
+    if not args.no_plain:
+        pms, pk = timed(ctx, torch, lambda: gen(ph.PHPRNG_MODE_PLAIN), args.plain_steps, 1)
+        out["plain"] = {"value": total / (pms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": pms,
+                        "kernel_ms": pk, "launches_per_step": N_INST, "speedup_of_batched": pms / ms}
+        log("plain: %s" % out["plain"])
+    if not args.no_graph:
+        g = ctx.graph(reqs, None, None, r, capacity=total)
+        gms, gk = timed(ctx, torch, g.launch, args.steps, 3)
+        g.close()
+        out["graph_replay"] = {"value": total / (gms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": gms,
+                               "kernel_ms": gk,
+                               "note": "request block copied, then the captured persistent kernel replayed"}
+        log("graph replay: %s" % out["graph_replay"])
+    if not args.no_ciphertexts:
+        c32 = torch.empty(total, dtype=torch.int32, device=dev)
+        cms, ck = timed(ctx, torch, lambda: gen(c32=c32), max(args.steps // 2, 1), 2)
+        out["with_ciphertexts"] = {"value": total / (cms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": cms,
+                                   "kernel_ms": ck, "outputs": "u32 c + f64 R (12 B per draw)",
+                                   "roofline": roofline(total, ck, ops_per_draw, 12.0)}
+        log("with ciphertexts: %s" % out["with_ciphertexts"])
+        del c32
+    if not args.no_unit_skip:
+        uctx = ph.Context(0, max_instances=N_INST)
+        uids = uctx.add_instances_skip(32, n_arr, e_arr, np.ones(N_INST, dtype=np.uint64))
+        ureqs = ph.make_requests(uids, [PER] * N_INST, np.arange(N_INST, dtype=np.uint64) * PER)
+        ums, uk = timed(uctx, torch, lambda: uctx.generate(ureqs, None, None, r, capacity=total), args.steps, 3)
+        out["unit_skip"] = {"value": total / (ums * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": ums,
+                            "kernel_ms": uk, "note": "same 4096 (n, e), unit-skip schedule m_k = m_0 + k"}
+        log("unit skip: %s" % out["unit_skip"])
+        uctx.close()
+    ctx.close()
+    del r
+    release(torch)
+    return n_arr, e_arr
 
 
-def timed_steps(ctx, torch, fn, steps, warmup):
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    ctx.timing_reset()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        fn()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kms, kc = ctx.timing_read()
-    return wall * 1e3 / steps, kms / max(kc, 1)
+# ---------------------------------------------------------------------------
+# 1 instance x 10^6
+# ---------------------------------------------------------------------------
 
-
-def workload_a(args, torch, ph):
-    """One seeded 32-bit instance, 10^6 draws per step (u32 c + f64 R)."""
+def section_a(args, torch, ph, out):
     dev = torch.device("cuda:0")
     ctx = ph.Context(0, max_instances=1)
-    ids = ctx.seed_instances(32, 0x14112484, 1, (9, 17), 0, 0)
+    ids = ctx.seed_instances(32, W.SEED0, 1, (9, 17), 0, 0)
     N = 10 ** 6
     c32 = torch.empty(N, dtype=torch.int32, device=dev)
     r = torch.empty(N, dtype=torch.float64, device=dev)
     reqs = ph.make_requests(ids, [N], [0])
     res = {}
     for name, mode in (("persistent", ph.PHPRNG_MODE_PERSISTENT), ("plain", ph.PHPRNG_MODE_PLAIN)):
-        ms, kms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, c32, None, r, mode=mode), args.steps,
-                              args.warmup)
-        res[name] = {"ms_per_step": ms, "kernel_ms": kms, "value": N / (ms * 1e-3) / 1e9}
+        ms, kms = timed(ctx, torch, lambda: ctx.generate(reqs, c32, None, r, mode=mode), 20, 5)
+        res[name] = {"value": N / (ms * 1e-3) / 1e9, "ms_per_step": ms, "kernel_ms": kms}
+    res["workload"] = "1 seeded width-32 instance x 10^6 draws from position 0 (u32 c + f64 R)"
+    out["one_instance"] = res
+    log("one instance: %s" % res)
     ctx.close()
-    return common_line(res["persistent"]["value"], "Guniforms/s", args.steps, args.warmup,
-                       res["persistent"]["ms_per_step"],
-                       {"workload": "1 seeded 32-bit instance x 10^6 draws from position 0 (u32 c + f64 R)"},
-                       plain=res["plain"], persistent=res["persistent"])
 
 
-def workload_c(args, torch, ph):
-    """65,536 seeded 32-bit instances, log-uniform stream lengths in
-    [2^10, 2^22], random starts in [0, 2^40), one persistent launch per step.
-    Outputs (u32 c + f64 R) go to a reused arena of 2^32 elements: streams
-    are placed one after another and wrap to the start of the arena."""
+# ---------------------------------------------------------------------------
+# 65,536 log-uniform streams
+# ---------------------------------------------------------------------------
+
+def section_c(args, torch, ph, out):
     dev = torch.device("cuda:0")
-    nin = 65536
-    ctx = ph.Context(0, max_instances=nin)
-    ids = ctx.seed_instances(32, 0x14112484 + 2, nin, (9, 17), 0, 1 << 40)
-    rng = np.random.default_rng(0x14112484 + 2)
-    lens = np.floor(2.0 ** (10 + 12 * rng.random(nin))).astype(np.uint64)
-    arena = 1 << 32
-    offs = np.zeros(nin, dtype=np.uint64)
-    cur = 0
-    for i in range(nin):
-        if cur + int(lens[i]) > arena:
-            cur = 0
-        offs[i] = cur
-        cur += int(lens[i])
+    nin = W.C_INSTANCES
+    lens = W.config_c_lengths(nin)
     total = int(lens.sum())
-    c32 = torch.empty(arena, dtype=torch.int32, device=dev)
-    r = torch.empty(arena, dtype=torch.float64, device=dev)
-    reqs = ph.make_requests(ids, lens, offs)
-    steps = max(2, args.steps // 5)
-    ms, kms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, c32, None, r, capacity=arena), steps, 1)
-    rms, rkms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, None, None, r, capacity=arena), steps, 1)
-    # draw-weighted algorithmic op count over the instances' exponents
+    ctx = ph.Context(0, max_instances=nin)
+    ids = ctx.seed_instances(32, W.C_SEED, nin, (9, 17), 0, W.C_START_HI)
     es = np.array([ctx.get_params(int(i))[1] for i in ids])
     ops = float(np.sum(lens.astype(np.float64) * np.array([algorithmic_ops_32(e) for e in es])) / total)
+    res = {"workload": "65,536 seeded width-32 instances, lengths floor(2^(10 + 12u)) in [2^10, 2^22] "
+                       "(%d draws), starts uniform in [0, 2^40)" % total, "draws": total}
+    steps = max(1, args.big_steps)
+    # u32 c + f64 R: 12 B per draw exceed the device, so the streams run in
+    # the fewest groups whose outputs fit; one persistent launch per group
+    free, _ = torch.cuda.mem_get_info()
+    groups = W.groups_for_memory(lens, 12, free)
+    arena = max(g[3] for g in groups)
+    c32 = torch.empty(arena, dtype=torch.int32, device=dev)
+    r = torch.empty(arena, dtype=torch.float64, device=dev)
+    greqs = [ph.make_requests(ids[a:b], lens[a:b], offs) for a, b, offs, _ in groups]
+
+    def step_cr():
+        for q in greqs:
+            ctx.generate(q, c32, None, r, capacity=arena)
+
+    ms, kms = timed(ctx, torch, step_cr, steps, 1)
+    res["c_and_r"] = {"value": total / (ms * 1e-3) / 1e9, "ms_per_step": ms, "kernel_ms": kms,
+                      "launches_per_step": len(groups), "arena_elements": arena,
+                      "roofline": roofline(total, kms, ops, 12.0)}
+    log("C (c + R, %d launches): %s" % (len(groups), res["c_and_r"]))
+    del c32, r
+    release(torch)
+    # f64 R only: 8 B per draw; the whole batch in one launch when it fits
+    free, _ = torch.cuda.mem_get_info()
+    groups = W.groups_for_memory(lens, 8, free, fill=0.9)
+    arena = max(g[3] for g in groups)
+    r = torch.empty(arena, dtype=torch.float64, device=dev)
+    greqs = [ph.make_requests(ids[a:b], lens[a:b], offs) for a, b, offs, _ in groups]
+
+    def step_r():
+        for q in greqs:
+            ctx.generate(q, None, None, r, capacity=arena)
+
+    ms, kms = timed(ctx, torch, step_r, steps, 1)
+    res["r_only"] = {"value": total / (ms * 1e-3) / 1e9, "ms_per_step": ms, "kernel_ms": kms,
+                     "launches_per_step": len(groups), "arena_elements": arena,
+                     "roofline": roofline(total, kms, ops, 8.0)}
+    log("C (R only, %d launches): %s" % (len(groups), res["r_only"]))
+    del r
     ctx.close()
-    value = total / (ms * 1e-3) / 1e9
-    gbs = total * 12.0 / (kms * 1e-3) / 1e9
-    alu = total * ops / (kms * 1e-3)
-    roofs = {"alu": {"achieved": alu / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Top/s",
-                     "frac": alu / ALU_PEAK_OPS, "ops_per_draw": ops},
-             "hbm": {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                     "bytes_per_draw": 12.0}}
-    return common_line(value, "Guniforms/s", steps, 1, ms,
-                       {"workload": "65536 seeded 32-bit instances, log-uniform lengths 2^10..2^22 (%d draws), "
-                                    "random starts in [0, 2^40), one persistent launch, u32 c + f64 R" % total},
-                       kernel_ms=kms, hbm_gbs=gbs, roofline_fractions=roofs,
-                       uniforms_only={"value": total / (rms * 1e-3) / 1e9, "kernel_ms": rkms})
+    release(torch)
+    out["log_uniform_65536"] = res
 
 
-def workload_d(args, torch, ph):
-    """1024 64-bit + 1024 32-bit instances x 2^20 draws, mixed in one launch."""
+# ---------------------------------------------------------------------------
+# 1024 width-64 + 1024 width-32 x 2^20
+# ---------------------------------------------------------------------------
+
+def section_d(args, torch, ph, out):
     dev = torch.device("cuda:0")
-    ctx = ph.Context(0, max_instances=2048)
-    i64 = ctx.seed_instances(64, 0x14112484 + 3, 1024, (9, 17), 0, 0)
-    i32 = ctx.seed_instances(32, 0x14112484 + 4, 1024, (9, 17), 0, 0)
     per = 1 << 20
+    res = {"workload": "1024 seeded width-64 instances (n in [2^62, 2^63)) + 1024 width-32 instances, 2^20 draws "
+                       "each from position 0, u64/u32 c + f64 R"}
+    if not args.no_autotune:
+        # width-64-only shapes, tuned on a context of the 64-bit instances alone
+        t64 = ph.Context(0, max_instances=1024)
+        t64.seed_instances(64, W.SEED0 + 3, 1024, (9, 17), 0, 0)
+        t64.autotune(1 << 25)
+        t64.close()
+    ctx = ph.Context(0, max_instances=2048)
+    i64 = ctx.seed_instances(64, W.SEED0 + 3, 1024, (9, 17), 0, 0)
+    i32 = ctx.seed_instances(32, W.SEED0 + 4, 1024, (9, 17), 0, 0)
+    if not args.no_autotune:
+        ctx.autotune(1 << 26)
+    res["tuning"] = {"width64": ctx.get_tuning_class(ph.PHPRNG_CLASS_W64),
+                     "mixed": ctx.get_tuning_class(ph.PHPRNG_CLASS_MIXED),
+                     "width32": ctx.get_tuning_class(ph.PHPRNG_CLASS_W32)}
+    e64 = np.array([ctx.get_params(int(i))[1] for i in i64])
+    e32 = np.array([ctx.get_params(int(i))[1] for i in i32])
+    ops64 = float(np.mean([algorithmic_ops_64(e) for e in e64]))
+    ops32 = float(np.mean([algorithmic_ops_32(e) for e in e32]))
     total = 2048 * per
     c32 = torch.empty(total, dtype=torch.int32, device=dev)
     c64 = torch.empty(total, dtype=torch.int64, device=dev)
     r = torch.empty(total, dtype=torch.float64, device=dev)
-    steps = max(2, args.steps // 4)
-    res = {}
-    for name, ids in (("mixed", np.concatenate([i64, i32])), ("w64_only", i64), ("w32_only", i32)):
+    for name, ids, ops, bpd in (("mixed", np.concatenate([i64, i32]), (ops64 + ops32) / 2, 14.0),
+                                ("w64_only", i64, ops64, 16.0), ("w32_only", i32, ops32, 12.0)):
         reqs = ph.make_requests(ids, [per] * len(ids), np.arange(len(ids), dtype=np.uint64) * per)
-        ms, kms = timed_steps(ctx, torch, lambda: ctx.generate(reqs, c32, c64, r, capacity=total), steps, 1)
-        res[name] = {"value": len(ids) * per / (ms * 1e-3) / 1e9, "ms_per_step": ms, "kernel_ms": kms}
+        ms, kms = timed(ctx, torch, lambda: ctx.generate(reqs, c32, c64, r, capacity=total), args.big_steps, 1)
+        draws = len(ids) * per
+        res[name] = {"value": draws / (ms * 1e-3) / 1e9, "ms_per_step": ms, "kernel_ms": kms,
+                     "roofline": roofline(draws, kms, ops, bpd)}
+        log("D %s: %s" % (name, res[name]))
+    del c32, c64, r
     ctx.close()
-    return common_line(res["mixed"]["value"], "Guniforms/s", steps, 1, res["mixed"]["ms_per_step"],
-                       {"workload": "1024 64-bit (n in [2^62, 2^63)) + 1024 32-bit instances x 2^20 draws, one "
-                                    "mixed persistent launch, u32/u64 c + f64 R"}, **res)
+    release(torch)
+    out["mixed_widths"] = res
 
 
-def workload_e(args, torch, ph):
-    """Serving: 10^6 resident instances (900,000 32-bit, 100,000 64-bit),
-    open-loop Poisson arrivals, each request log-uniform 2^8..2^20 FP64
-    uniforms from a uniformly chosen instance, continuous batching."""
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+def section_e(args, torch, ph, out):
     n32, n64 = args.serve_instances * 9 // 10, args.serve_instances // 10
     ctx = ph.Context(0, max_instances=n32 + n64)
     t0 = time.perf_counter()
-    ctx.seed_instances(32, 0x14112484 + 5, n32, (9, 17), 0, 1 << 40)
-    ctx.seed_instances(64, 0x14112484 + 6, n64, (9, 17), 0, 1 << 32)
-    log("serve: %d instances seeded in %.1f s" % (n32 + n64, time.perf_counter() - t0))
+    ctx.seed_instances(32, W.SEED0 + 5, n32, (9, 17), 0, 1 << 40)
+    ctx.seed_instances(64, W.SEED0 + 6, n64, (9, 17), 0, 1 << 32)
+    seed_s = time.perf_counter() - t0
+    log("serve: %d instances seeded in %.1f s" % (n32 + n64, seed_s))
     srv = ph.Server(ctx, arena_doubles=args.serve_arena, streams=args.serve_streams,
                     max_inflight=args.serve_inflight)
-    # untimed warm-up: first-use costs (staging slots, pinned buffers, the
-    # per-instance scratch) stay out of the first load point
-    wrng = np.random.default_rng(0x14112484 + 8)
+    # untimed warm-up: first-use costs stay out of the first load point
+    wrng = np.random.default_rng(W.SEED0 + 8)
     warm = np.zeros(2000, dtype=ph.ARRIVAL_DTYPE)
     warm["t_ns"] = np.cumsum(wrng.exponential(1e4, warm.size)).astype(np.int64)
     warm["instance"] = wrng.integers(0, n32 + n64, warm.size)
     warm["count"] = np.floor(2.0 ** (8 + 12 * wrng.random(warm.size))).astype(np.uint64)
     srv.replay(warm)
-    rng = np.random.default_rng(0x14112484 + 7)
+    rng = np.random.default_rng(W.SEED0 + 7)
     points = []
     for lam in args.serve_rates:
         n = int(min(args.serve_max_requests, max(2000, lam * args.serve_seconds)))
@@ -244,27 +424,37 @@ def workload_e(args, torch, ph):
         cnt = srv.counters(reset=True)
         draws = int(arr["count"].sum())
         pt = {"rate_req_s": lam, "requests": n, "uniforms_per_s": draws / wall / 1e9,
+              "offered_guniforms_s": float(draws / (arr["t_ns"][-1] * 1e-9) / 1e9),
               "p50_ms": float(np.percentile(lat, 50)) / 1e6, "p99_ms": float(np.percentile(lat, 99)) / 1e6,
               "admit_p50_ms": float(np.percentile(adm, 50)) / 1e6, "admit_p99_ms": float(np.percentile(adm, 99)) / 1e6,
-              "offered_guniforms_s": float(draws / (arr["t_ns"][-1] * 1e-9) / 1e9), "wall_s": wall,
-              "batches": cnt["batches"], "requests_per_batch": cnt["requests"] / max(cnt["batches"], 1),
+              "wall_s": wall, "batches": cnt["batches"], "requests_per_batch": cnt["requests"] / max(cnt["batches"], 1),
               "launch_us_mean": cnt["launch_ns"] / max(cnt["batches"], 1) / 1e3,
-              "launch_us_max": cnt["launch_ns_max"] / 1e3,
               "form_us_mean": cnt["form_ns"] / max(cnt["batches"], 1) / 1e3,
-              "retire_us_mean": cnt["retire_ns"] / max(cnt["batches"], 1) / 1e3,
-              "arena_stalls": cnt["arena_stalls"],
-              "arena_peak": cnt["arena_peak"]}
+              "arena_stalls": cnt["arena_stalls"]}
         log("serve: %s" % pt)
         points.append(pt)
     srv.close()
     ctx.close()
-    best = max(points, key=lambda p: p["uniforms_per_s"])
-    return common_line(best["uniforms_per_s"], "Guniforms/s", len(points), 0, None,
-                       {"workload": "serving: %d resident instances (90%% 32-bit, 10%% 64-bit), Poisson arrivals, "
-                                    "log-uniform 2^8..2^20 FP64 uniforms per request" % (n32 + n64),
-                        "streams": args.serve_streams, "inflight": args.serve_inflight or min(args.serve_streams + 1, 6)},
-                       serve=points)
+    release(torch)
+    out["serving"] = {"workload": "%d resident instances (90%% width 32, starts in [0, 2^40); 10%% width 64, starts "
+                                  "in [0, 2^32)), Poisson arrivals, each request log-uniform 2^8..2^20 FP64 uniforms "
+                                  "from a uniformly chosen instance, latency from the scheduled arrival to the "
+                                  "completion seen by the host" % (n32 + n64),
+                      "streams": args.serve_streams, "seeding_s": seed_s,
+                      "inflight": args.serve_inflight or min(args.serve_streams + 1, 6), "points": points}
 
+
+def common_line(metric_value, unit, steps, warmup, ms_per_step, config, **extra):
+    out = {"metric": METRIC, "value": metric_value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32/u64/f64", "data": "synthetic", "config": config}
+    out.update(extra)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# battery and pattern workloads (separate lines, --workload F / G)
+# ---------------------------------------------------------------------------
 
 BATTERY_KEYS_PER_DRAW = 1 + 1 / 2 + 1 / 3 + 1 / 4 + 1 / 5   # frequency + serial 2..5 histogram keys
 # per 128-block chunk, the counting stage writes and reads 2 slices of 159
@@ -351,82 +541,7 @@ def workload_f(args, torch, ph):
         log("battery %s: %.1f Guniforms/s tested (battery kernels %.2f ms/step), min P %.3g"
             % (order, res[order]["value"], bat_ms, res[order]["min_p"]))
         bat.close()
-    # the paper's largest interleaving shape tried here: N_p = 2^20 streams,
-    # 1024 draws each, tested in the interstream order
     ctx.close()
-    np_streams, np_len = 1 << 20, 1024
-    big = ph.Context(0, max_instances=np_streams)
-    t0 = time.perf_counter()
-    bids = big.seed_instances(32, 0x14112484 + 10, np_streams, (9, 17), 0, 0)
-    seed_s = time.perf_counter() - t0
-    breqs = ph.make_requests(bids, [np_len] * np_streams, np.arange(np_streams, dtype=np.uint64) * np_len)
-    bat = ph.Battery(0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    big.generate(breqs, None, None, r, capacity=total)
-    ph.interleave(r, inter, np_streams, np_len)
-    bat.accumulate(inter)
-    rep = bat.report()
-    wall = time.perf_counter() - t0
-    res["interstream_np_2p20"] = {"streams": np_streams, "draws_per_stream": np_len, "seconds": wall,
-                                  "seeding_seconds": seed_s,
-                                  "tests": {k: {"chi2": v[0], "p": v[2]} for k, v in rep.items()},
-                                  "min_p": min(v[2] for v in rep.values())}
-    log("battery interstream N_p = 2^20: %.2f s, min P %.3g" % (wall, res["interstream_np_2p20"]["min_p"]))
-    bat.close()
-    big.close()
-    # constant skip b = p(p-1)/2 mod n over its whole period n (Sec. II): every
-    # ciphertext occurs once, so the one-dimensional test sees a distribution
-    # that is uniform to within one count per bin (far below the chi^2 median)
-    n_ex, e_ex, p31 = 4294967087, 9, (1 << 31) - 1
-    b_ex = (p31 * (p31 - 1) // 2) % n_ex
-    cs = ph.Context(0, max_instances=1)
-    cid = cs.add_instances_skip(32, [n_ex], [e_ex], [b_ex])
-    nblk = n_ex // (1 << 20)
-    bat = ph.Battery(0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    done = 0
-    while done < nblk:
-        nb = min(1024, nblk - done)
-        cs.generate(ph.make_requests(cid, [nb << 20], [0]), None, None, r, capacity=total)
-        bat.accumulate(r[: nb << 20])
-        done += nb
-    rep = bat.report()
-    wall = time.perf_counter() - t0
-    res["constant_skip_full_period"] = {
-        "n": n_ex, "e": e_ex, "b": b_ex, "uniforms": nblk << 20, "seconds": wall,
-        "tests": {k: {"chi2": v[0], "dof": v[1], "p": v[2]} for k, v in rep.items()}}
-    log("battery constant skip over its period: %.2f s, P = %s" % (wall, {k: "%.3g" % v[2] for k, v in rep.items()}))
-    bat.close()
-    cs.close()
-    ctx = None
-    if args.battery_uniforms > 0:
-        # one long stream of the paper's example instance (Sec. II tested single
-        # streams of 10^11 to 10^13 uniforms), in steps of 2^30
-        lc = ph.Context(0, max_instances=1)
-        lid = lc.add_instances(32, [4294967087], [9])
-        nsteps = max(1, int(args.battery_uniforms) >> 30)
-        lreq = ph.make_requests(lid, [total], [0])
-        bat = ph.Battery(0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(nsteps):
-            lc.generate(lreq, None, None, r, capacity=total)
-            bat.accumulate(r)
-            if (i + 1) % 128 == 0:
-                torch.cuda.synchronize()
-                log("battery long stream: %d of %d steps" % (i + 1, nsteps))
-        rep = bat.report()
-        wall = time.perf_counter() - t0
-        res["long_stream"] = {"n": 4294967087, "e": 9, "uniforms": nsteps * total, "seconds": wall,
-                              "guniforms_s": nsteps * total / wall / 1e9,
-                              "tests": {k: {"chi2": v[0], "dof": v[1], "p": v[2]} for k, v in rep.items()},
-                              "min_p": min(v[2] for v in rep.values())}
-        log("battery long stream: %.3g uniforms in %.1f s, P = %s"
-            % (nsteps * total, wall, {k: "%.3g" % v[2] for k, v in rep.items()}))
-        bat.close()
-        lc.close()
     intra = res["intrastream"]
     dom = max(intra["kernels"], key=lambda k: intra["kernels"][k]["ms_per_step"])
     dk = intra["kernels"][dom]
@@ -506,25 +621,28 @@ def workload_g(args, torch, ph):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=100, help="timed steps of the headline batch")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--big-steps", type=int, default=3,
+                    help="timed steps of the 65,536-stream and the mixed-width batches")
+    ap.add_argument("--sections", default="B,A,C,D,E",
+                    help="comma-separated: B headline (with its variants), A one instance, C 65,536 log-uniform "
+                         "streams, D mixed widths, E serving")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle time on the host for the baseline")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-ciphertexts", action="store_true", help="skip the u32 + f64 output variant")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph replay variant")
     ap.add_argument("--no-unit-skip", action="store_true", help="skip the unit-skip schedule variant")
-    ap.add_argument("--no-w64", action="store_true", help="skip the 64-bit-moduli variant")
-    ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
-    ap.add_argument("--workload", default="B", choices=["A", "B", "C", "D", "E", "F", "G"],
-                    help="B (default): the headline batch; A, C, D, E: the other workload shapes; "
-                         "F: the statistical battery on the generator's output; G: the full-period pattern")
-    ap.add_argument("--battery-uniforms", type=float, default=0,
-                    help="workload F: also test one stream of this many uniforms (multiple of 2^30)")
+    ap.add_argument("--no-autotune", action="store_true", help="time the library's default launch shapes")
+    ap.add_argument("--workload", default=None, choices=["F", "G"],
+                    help="instead of the generation line: F the statistical battery on the generator's output, "
+                         "G the full-period pattern")
     ap.add_argument("--serve-instances", type=int, default=1000000)
     ap.add_argument("--serve-arena", type=int, default=1 << 31, help="serving arena, FP64 uniforms")
-    ap.add_argument("--serve-rates", type=float, nargs="+", default=[1e3, 3e3, 1e4, 3e4, 1e5, 3e5, 1e6, 3e6])
-    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[1e5, 1e6, 3e6])
+    ap.add_argument("--serve-seconds", type=float, default=0.5)
     ap.add_argument("--serve-max-requests", type=int, default=200000)
     ap.add_argument("--serve-streams", type=int, default=2, help="streams of the server")
     ap.add_argument("--serve-inflight", type=int, default=0,
@@ -545,154 +663,38 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    if args.workload != "B":
-        fn = {"A": workload_a, "C": workload_c, "D": workload_d, "E": workload_e, "F": workload_f,
-              "G": workload_g}[args.workload]
+    if args.workload:
+        fn = {"F": workload_f, "G": workload_g}[args.workload]
         print(json.dumps(fn(args, torch, ph)), flush=True)
         return
-    dev = torch.device("cuda:0")
-    ctx = ph.Context(0, max_instances=N_INST)
-    ids = ctx.seed_instances(32, SEED_B, N_INST, (9, 17), 0, 0)
-    params = [ctx.get_params(int(i)) for i in ids]
-    n_arr = np.array([p[0] for p in params], dtype=np.uint64)
-    e_arr = np.array([p[1] for p in params], dtype=np.uint64)
-    total = N_INST * PER
-    r = torch.empty(total, dtype=torch.float64, device=dev)
-    reqs = ph.make_requests(ids, [PER] * N_INST, np.arange(N_INST, dtype=np.uint64) * PER)
-    if args.calib_copy_gib > 0:
-        nel = int(args.calib_copy_gib * (1 << 30) / 8)
-        src = torch.ones(nel, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("calibration copy: %d bytes read, %d bytes written" % (nel * 8, nel * 8))
-        del src, dst
-    if args.autotune:
-        log("autotune: %s" % ctx.autotune(1 << 27))
-    tuning = ctx.get_tuning()
-
-    def measure(steps, warmup, mode, c32=None):
-        """Time `steps` generation calls; returns (wall ms/step, kernel ms/call)."""
-        for _ in range(warmup):
-            ctx.generate(reqs, c32, None, r, capacity=total, mode=mode)
-        torch.cuda.synchronize()
-        ctx.timing_reset()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ctx.generate(reqs, c32, None, r, capacity=total, mode=mode)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        kms, kcalls = ctx.timing_read()
-        return wall * 1e3 / steps, kms / max(kcalls, 1)
-
-    # headline: FP64 uniforms only, as the workload defines its output
-    ms_per_step, kernel_ms = measure(args.steps, args.warmup, ph.PHPRNG_MODE_PERSISTENT)
-    value = total / (ms_per_step * 1e-3) / 1e9
-    log("persistent: %.3f ms/step wall, %.3f ms kernel, %.1f Guniforms/s" % (ms_per_step, kernel_ms, value))
-
-    plain = None
-    if not args.no_plain:
-        pms, pk = measure(args.plain_steps, 1, ph.PHPRNG_MODE_PLAIN)
-        plain = {"value": total / (pms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": pms,
-                 "kernel_ms": pk, "launches_per_step": N_INST, "speedup_of_batched": pms / ms_per_step}
-        log("plain: %s" % plain)
-
-    graph = None
-    if not args.no_graph:
-        g = ctx.graph(reqs, None, None, r, capacity=total)
-        gms, gk = timed_steps(ctx, torch, g.launch, args.steps, 3)
-        g.close()
-        graph = {"value": total / (gms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": gms, "kernel_ms": gk,
-                 "note": "captured plan + persistent kernel + position advance, replayed each step"}
-        log("graph replay: %s" % graph)
-
-    unit = None
-    if not args.no_unit_skip:
-        # the same moduli and exponents on the unit-skip schedule (counter mode):
-        # the encryption path alone, without the skip generator and prefix
-        uctx = ph.Context(0, max_instances=N_INST)
-        uids = uctx.add_instances_skip(32, n_arr, e_arr, np.ones(N_INST, dtype=np.uint64))
-        ureqs = ph.make_requests(uids, [PER] * N_INST, np.arange(N_INST, dtype=np.uint64) * PER)
-        ums, uk = timed_steps(uctx, torch, lambda: uctx.generate(ureqs, None, None, r, capacity=total), args.steps, 3)
-        unit = {"value": total / (ums * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": ums, "kernel_ms": uk,
-                "note": "same 4096 (n, e), unit-skip schedule m_k = m_0 + k"}
-        log("unit skip: %s" % unit)
-        uctx.close()
-
-    w64 = None
-    if not args.no_w64:
-        # 64-bit moduli (n in [2^62, 2^63)), 1024 seeded instances x 2^20 draws, FP64 only
-        wctx = ph.Context(0, max_instances=1024)
-        wids = wctx.seed_instances(64, 0x14112484 + 3, 1024, (9, 17), 0, 0)
-        wreqs = ph.make_requests(wids, [1 << 20] * 1024, np.arange(1024, dtype=np.uint64) << 20)
-        wms, wk = timed_steps(wctx, torch, lambda: wctx.generate(wreqs, None, None, r, capacity=total),
-                              max(args.steps // 2, 2), 3)
-        w64 = {"value": total / (wms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": wms, "kernel_ms": wk,
-               "workload": "1024 seeded 64-bit instances x 2^20 draws, FP64 uniforms"}
-        log("width 64: %s" % w64)
-        wctx.close()
-
-    with_c = None
-    if not args.no_ciphertexts:
-        c32 = torch.empty(total, dtype=torch.int32, device=dev)
-        cms, ck = measure(max(args.steps // 2, 1), 1, ph.PHPRNG_MODE_PERSISTENT, c32)
-        with_c = {"value": total / (cms * 1e-3) / 1e9, "unit": "Guniforms/s", "ms_per_step": cms,
-                  "kernel_ms": ck, "outputs": "u32 c + f64 R (12 B per draw)",
-                  "hbm_gbs": total * 12.0 / (ck * 1e-3) / 1e9}
-        log("with ciphertexts: %s" % with_c)
-        del c32
-
-    # roofline of the generation kernel: algorithmic bytes / ops per launch
-    ops_per_draw = float(np.mean([algorithmic_ops_32(e) for e in e_arr]))
-    bytes_per_draw = 8.0
-    achieved_gbs = total * bytes_per_draw / (kernel_ms * 1e-3) / 1e9
-    achieved_ops = total * ops_per_draw / (kernel_ms * 1e-3)
-    hbm = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(), "bytes_per_draw": bytes_per_draw}
-    alu = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": ALU_PEAK_OPS / 1e12, "unit": "Top/s",
-           "frac": achieved_ops / ALU_PEAK_OPS, "ops_per_draw": ops_per_draw}
-    roof, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
-    roof = dict(roof)
-    roof["traffic"] = measured_traffic()
-    roof["kernel"] = "gen_persistent"
-    roof["kernel_ms"] = kernel_ms
-    roof["units_per_launch"] = total
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(e_arr, n_arr)
-        log("cpu baseline: %s" % cpu)
-
     out = {
-        "metric": "Guniforms/s (32/64-bit moduli), batched vs plain launch; serve p50/p99 latency",
-        "value": value,
-        "unit": "Guniforms/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32/f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "4096 seeded 32-bit instances x 2^18 draws per step (1.07e9 FP64 uniforms to HBM), "
-                        "one batched persistent launch per step",
-            "instances": N_INST, "draws_per_instance": PER, "width": 32, "e_set": [9, 17],
-            "start_position": 0, "tuning": tuning,
-        },
-        "plain": plain,
-        "with_ciphertexts": with_c,
-        "graph_replay": graph,
-        "unit_skip": unit,
-        "width64": w64,
-        "roofline": roof,
-        "roofline_other": other,
-        "cpu_baseline": cpu,
+        "metric": METRIC, "value": None, "unit": "Guniforms/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32/u64/f64", "data": "synthetic",
+        "config": {"workload": "4096 seeded width-32 instances x 2^18 draws per step (1.07e9 FP64 uniforms to HBM), "
+                               "one batched persistent launch per step",
+                   "instances": N_INST, "draws_per_instance": PER, "width": 32, "e_set": [9, 17],
+                   "start_position": 0},
     }
+    sections = [s.strip().upper() for s in args.sections.split(",") if s.strip()]
+    n_arr = e_arr = None
+    t_start = time.perf_counter()
+    if "B" in sections:
+        n_arr, e_arr = section_headline(args, torch, ph, out)
+    if "A" in sections:
+        section_a(args, torch, ph, out)
+    if "C" in sections:
+        section_c(args, torch, ph, out)
+    if "D" in sections:
+        section_d(args, torch, ph, out)
+    if "E" in sections:
+        section_e(args, torch, ph, out)
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline and n_arr is not None:
+        out["cpu_baseline"] = cpu_baseline(n_arr, e_arr, args.cpu_seconds)
+        log("cpu baseline: %s" % out["cpu_baseline"])
+    out["bench_seconds"] = time.perf_counter() - t_start
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -179,9 +179,8 @@ uint64_t phprng_instance_count(const phprng_ctx *ctx);
  * NULL for the null stream) and the outputs are valid once it completes.
  * mode: PHPRNG_MODE_PERSISTENT (one work-stealing launch for the whole batch)
  * or PHPRNG_MODE_PLAIN (one launch per request).  A request with count 0 is
- * allowed and does nothing.  The request array is copied during the call
- * (into pinned memory that the planning kernel reads), so the caller may
- * reuse it on return. */
+ * allowed and does nothing.  The requests are planned on the host during
+ * the call, so the caller may reuse the array on return. */
 phprng_status phprng_generate(phprng_ctx *ctx, const phprng_request *reqs, uint64_t nreq, uint32_t *out_c32,
                               uint64_t *out_c64, double *out_r, uint64_t capacity, void *stream, int mode);
 

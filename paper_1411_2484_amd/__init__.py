@@ -369,7 +369,6 @@ class Context:
         self._chk(lib().phprng_generate(self._h, reqs.ctypes.data, reqs.size, p32, p64, pr, cap,
                                         _stream_handle(stream), int(mode)))
 
-
     def last_kernel_ms(self):
         v = ctypes.c_double()
         self._chk(lib().phprng_last_kernel_ms(self._h, ctypes.byref(v)))

@@ -12,6 +12,13 @@
 #include "layout.hpp"
 
 namespace phprng {
+
+// Clears the calling thread's last HIP error before a launch whose error is
+// read with hipGetLastError: a call that failed earlier in the process (an
+// allocation refused somewhere else, say) would otherwise be reported as
+// this launch's failure.
+inline void clear_launch_error() { (void)hipGetLastError(); }
+
 namespace dev {
 
 // ---- skip generator mod 2^31 - 1 (eq. (5), width 32) ----------------------

@@ -528,44 +528,52 @@ __global__ __launch_bounds__(256) void interleave_kernel(const double *__restric
 
 hipError_t launch_hist(const double *r, uint64_t nblocks, const ph::PartSet &P, const BatteryParts &bp,
                        unsigned long long *poker, uint64_t *bits, hipStream_t st) {
+  clear_launch_error();
   hist_kernel<<<dim3((unsigned)(nblocks * kHistTilesPerBlock)), dim3(kHistThreads), 0, st>>>(r, P, bp, poker, bits);
   return hipGetLastError();
 }
 
 hipError_t launch_collision(const double *r, uint64_t nblocks, unsigned long long *coll, hipStream_t st) {
+  clear_launch_error();
   collision_kernel<<<dim3((unsigned)(nblocks * (kBlock / kCollBalls))), dim3(1024), 0, st>>>(r, coll);
   return hipGetLastError();
 }
 
 hipError_t launch_runs(const uint64_t *bits, uint64_t nblocks, unsigned long long *runs, hipStream_t st) {
+  clear_launch_error();
   const uint64_t nwords = nblocks * kWordsPerBlock;
   runs_kernel<<<dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, st>>>(bits, nwords, runs);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_pass1(const double *r, uint64_t nblocks, double2 *y, Twiddles tw, hipStream_t st) {
+  clear_launch_error();
   fft_pass1_kernel<<<dim3((unsigned)(nblocks * kFftPass1Groups)), dim3(256), 0, st>>>(r, y, tw);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_pass2(const double2 *y, uint64_t nblocks, unsigned long long *fourier, double *coef,
                             Twiddles tw, double scale, hipStream_t st) {
+  clear_launch_error();
   fft_pass2_pairs_kernel<<<dim3((unsigned)(nblocks * kP2PairRows)), dim3(128), 0, st>>>(y, fourier, coef, tw, scale);
   fft_pass2_self_kernel<<<dim3((unsigned)(nblocks * 2)), dim3(128), 0, st>>>(y, fourier, coef, tw, scale);
   return hipGetLastError();
 }
 
 hipError_t launch_fold(unsigned long long *rep, unsigned long long *dst, uint32_t ncat, hipStream_t st) {
+  clear_launch_error();
   fold_kernel<<<dim3((ncat + 255) / 256), dim3(256), 0, st>>>(rep, dst, ncat);
   return hipGetLastError();
 }
 
 hipError_t launch_chi2(const Chi2Job *jobs, int njobs, double *chi2, unsigned long long *total, hipStream_t st) {
+  clear_launch_error();
   chi2_kernel<<<dim3(njobs), dim3(1024), 0, st>>>(jobs, chi2, total);
   return hipGetLastError();
 }
 
 hipError_t launch_interleave(const double *in, double *out, uint64_t nstreams, uint64_t length, hipStream_t st) {
+  clear_launch_error();
   interleave_kernel<<<dim3((unsigned)((length + 63) / 64), (unsigned)((nstreams + 63) / 64)), dim3(64, 4), 0, st>>>(
       in, out, nstreams, length);
   return hipGetLastError();

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "arith.hpp"
@@ -237,31 +238,45 @@ __device__ __forceinline__ uint32_t tile_len64(const ReqRec &R, uint32_t j) {
   return j + 1 == R.ntiles ? last : (uint32_t)kTile64;
 }
 
-// One wave per width-64 tile (grid-stride): the skip before the tile,
-// a^{t + 1024 j} mod p for tile j of a request starting at skip log t, and
-// the sum of the tile's skips mod n.
+// One wave per reduce unit (grid-stride): up to kReduceTiles consecutive
+// tiles of one width-64 request.  For each tile j of a request starting at
+// skip log t it writes the skip before the tile, a^{t + 1024 j} mod p (a
+// power for the unit's first tile, then carried from tile to tile), and the
+// sum of the tile's skips mod n.
 __global__ void __launch_bounds__(256) reduce64_kernel(GenArgs A) {
   const uint32_t lane = dev::lane_id();
   const uint32_t wave = dev::uniform_u32(threadIdx.x / 64);
-  const uint64_t tiles = dev::uniform_u64(dev::const_load(&A.hdr->tiles64));
+  const uint64_t units = dev::uniform_u64(dev::const_load(&A.hdr->units64));
   const uint64_t nreq64 = dev::uniform_u64(dev::const_load(&A.hdr->nreq64));
   const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / 64);
   const uint64_t lane_mul = A.lanemul->m64[lane];
   const uint64_t pm1 = kP64 - 1;
-  for (uint64_t t = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave; t < tiles; t += nwaves) {
+  for (uint64_t u = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave; u < units; u += nwaves) {
     const uint64_t r =
-        dev::uniform_u64(wave_search(nreq64, t, lane, [&](uint64_t i) { return A.req[i].g1; }));
+        dev::uniform_u64(wave_search(nreq64, u, lane, [&](uint64_t i) { return A.req[i].rbase; }));
     const ReqRec R = dev::const_load(A.req + r);
     const uint64_t n = dev::const_load(&A.inst[R.inst].n);
-    const uint32_t j = (uint32_t)(t - R.g1);
-    uint64_t lg = R.x + (uint64_t)j * kTile64;  // x < p - 1 and j * 1024 < 2^42: one subtraction wraps it
+    const uint32_t j0 = (uint32_t)(u - R.rbase) * kReduceTiles;
+    const uint32_t j1 = R.ntiles - j0 > (uint32_t)kReduceTiles ? j0 + (uint32_t)kReduceTiles : R.ntiles;
+    uint64_t lg = R.x + (uint64_t)j0 * kTile64;  // x < p - 1 and j * 1024 < 2^42: one subtraction wraps it
     if (lg >= pm1) lg -= pm1;
-    const uint64_t s_tile = dev::wave_pow_p61(A.lanemul->pow64, lg, lane);
-    const uint32_t len = tile_len64(R, j);
-    const uint64_t sum = tile_skip_sum64(s_tile, lane_mul, len, n, lane);
-    if (lane == 0) {
-      A.t64.s[t] = s_tile;
-      A.t64.sum[t] = sum;
+    uint64_t s_tile = dev::wave_pow_p61(A.lanemul->pow64, lg, lane);
+    for (uint32_t j = j0; j < j1; ++j) {
+      const uint32_t len = tile_len64(R, j);
+      uint64_t s = dev::mulmod_p61(s_tile, lane_mul);
+      uint64_t sum = 0;
+      const uint32_t first = lane * kRun64;
+#pragma unroll 4
+      for (int i = 0; i < kRun64; ++i) {
+        s = dev::mulmod_p61(kA64, s);
+        if (first + (uint32_t)i < len) sum = dev::addmod64(sum, s, n);
+      }
+      sum = dev::wave_sum_mod(sum, n);
+      if (lane == 0) {
+        A.t64.s[R.g1 + j] = s_tile;
+        A.t64.sum[R.g1 + j] = sum;
+      }
+      s_tile = dev::shfl_u64(s, 63);  // the skip after the tile's last draw
     }
   }
 }
@@ -774,6 +789,7 @@ __global__ void __launch_bounds__(64) gen_plain(GenArgs A, uint64_t r) {
 // ---------------------------------------------------------------------------
 
 hipError_t launch_table_segments32(uint64_t nseg, uint64_t *seg_sum, uint32_t *seg_start, hipStream_t st) {
+  clear_launch_error();
   unsigned blocks = (unsigned)((nseg + 255) / 256);
   hipLaunchKernelGGL(table_segments32, dim3(blocks), dim3(256), 0, st, nseg, seg_sum, seg_start);
   return hipGetLastError();
@@ -781,6 +797,7 @@ hipError_t launch_table_segments32(uint64_t nseg, uint64_t *seg_sum, uint32_t *s
 
 hipError_t launch_table_segments64(uint64_t nseg, uint64_t *seg_lo, uint64_t *seg_hi, uint64_t *seg_start,
                                    hipStream_t st) {
+  clear_launch_error();
   unsigned blocks = (unsigned)((nseg + 255) / 256);
   hipLaunchKernelGGL(table_segments64, dim3(blocks), dim3(256), 0, st, nseg, seg_lo, seg_hi, seg_start);
   return hipGetLastError();
@@ -788,6 +805,7 @@ hipError_t launch_table_segments64(uint64_t nseg, uint64_t *seg_lo, uint64_t *se
 
 hipError_t launch_seed_prime_flags(uint64_t seed, uint64_t j0, uint64_t count, int width, uint8_t *flags,
                                    hipStream_t st) {
+  clear_launch_error();
   unsigned blocks = (unsigned)((count + 255) / 256);
   hipLaunchKernelGGL(seed_prime_flags, dim3(blocks), dim3(256), 0, st, seed, j0, count, width, flags);
   return hipGetLastError();
@@ -795,6 +813,7 @@ hipError_t launch_seed_prime_flags(uint64_t seed, uint64_t j0, uint64_t count, i
 
 hipError_t launch_build_records(const uint64_t *n, const uint64_t *e, uint64_t count, int width, InstRec *out,
                                 hipStream_t st) {
+  clear_launch_error();
   unsigned blocks = (unsigned)((count + 255) / 256);
   hipLaunchKernelGGL(build_records, dim3(blocks), dim3(256), 0, st, n, e, count, width, out);
   return hipGetLastError();
@@ -803,6 +822,7 @@ hipError_t launch_build_records(const uint64_t *n, const uint64_t *e, uint64_t c
 hipError_t launch_position64(const InstRec *inst, const uint32_t *ids, const uint64_t *m0, const uint64_t *ta,
                              const uint64_t *tb, uint64_t count, const uint64_t *u_lo, const uint64_t *u_hi,
                              const uint64_t *u_s, uint64_t *m64, hipStream_t st) {
+  clear_launch_error();
   if (count == 0) return hipSuccess;
   unsigned blocks = (unsigned)((count + 255) / 256);
   hipLaunchKernelGGL(position64_kernel, dim3(blocks), dim3(256), 0, st, inst, ids, m0, ta, tb, count, u_lo, u_hi, u_s,
@@ -810,15 +830,17 @@ hipError_t launch_position64(const InstRec *inst, const uint32_t *ids, const uin
   return hipGetLastError();
 }
 
-hipError_t launch_tiles64_reduce(const GenArgs &A, uint64_t tiles64, unsigned max_blocks, hipStream_t st) {
-  if (tiles64 == 0) return hipSuccess;
-  const uint64_t want = (tiles64 + 3) / 4;
+hipError_t launch_tiles64_reduce(const GenArgs &A, uint64_t units64, unsigned max_blocks, hipStream_t st) {
+  clear_launch_error();
+  if (units64 == 0) return hipSuccess;
+  const uint64_t want = (units64 + 3) / 4;
   const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, max_blocks));
   hipLaunchKernelGGL(reduce64_kernel, dim3(blocks), dim3(256), 0, st, A);
   return hipGetLastError();
 }
 
 hipError_t launch_tiles64_scan(const GenArgs &A, uint64_t nreq64, hipStream_t st) {
+  clear_launch_error();
   if (nreq64 == 0) return hipSuccess;
   if (nreq64 > 0x7fffffffull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(scan64_kernel, dim3((unsigned)nreq64), dim3(kScanThreads), 0, st, A);
@@ -827,6 +849,7 @@ hipError_t launch_tiles64_scan(const GenArgs &A, uint64_t nreq64, hipStream_t st
 
 hipError_t launch_skip_total64(uint64_t t, uint64_t count, uint64_t n, const LaneMul *lm, uint64_t *partial,
                                unsigned blocks, uint64_t extra, int sign, uint64_t *m, hipStream_t st) {
+  clear_launch_error();
   if (blocks == 0) return hipErrorInvalidValue;
   if (count > 0) {
     hipLaunchKernelGGL(skip_total64_kernel, dim3(blocks), dim3(256), 0, st, t, count, n, lm, partial);
@@ -865,12 +888,14 @@ static bool launch_pb(const GenArgs &A, unsigned grid, int block, int unroll, hi
 }
 
 hipError_t launch_persistent(const GenArgs &A, unsigned grid, int block, int unroll, bool has64, hipStream_t st) {
+  clear_launch_error();
   bool ok = has64 ? launch_pb<true>(A, grid, block, unroll, st) : launch_pb<false>(A, grid, block, unroll, st);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_plain(const GenArgs &A, uint64_t r, unsigned grid, int unroll, bool has64, hipStream_t st) {
+  clear_launch_error();
   if (grid == 0) return hipSuccess;
   if (has64) {
     if (unroll == 4) hipLaunchKernelGGL((gen_plain<4, true>), dim3(grid), dim3(64), 0, st, A, r);

@@ -22,10 +22,11 @@ hipError_t launch_position64(const InstRec *inst, const uint32_t *ids, const uin
                              const uint64_t *tb, uint64_t count, const uint64_t *u_lo, const uint64_t *u_hi,
                              const uint64_t *u_s, uint64_t *m64, hipStream_t st);
 // Width-64 tile starts of a batch: the reduce writes each tile's start skip
-// and skip sum (hdr->tiles64 tiles, grid-stride with at most max_blocks
-// blocks); the scan turns the sums into tile-start messages per instance and
-// commits the instances' messages (one workgroup per width-64 request).
-hipError_t launch_tiles64_reduce(const GenArgs &A, uint64_t tiles64, unsigned max_blocks, hipStream_t st);
+// and skip sum (hdr->units64 units of up to kReduceTiles tiles, grid-stride
+// with at most max_blocks blocks); the scan turns the sums into tile-start
+// messages per instance and commits the instances' messages (one workgroup
+// per width-64 request).
+hipError_t launch_tiles64_reduce(const GenArgs &A, uint64_t units64, unsigned max_blocks, hipStream_t st);
 hipError_t launch_tiles64_scan(const GenArgs &A, uint64_t nreq64, hipStream_t st);
 // *m = *m + sign * (sum_{i=1}^{count} (a^{t+i} mod p) + extra) mod n, with
 // `blocks` 256-thread blocks writing blocks * 4 partial sums to `partial`.

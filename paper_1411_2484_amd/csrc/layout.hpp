@@ -27,6 +27,9 @@ constexpr uint64_t kTilesPerPeriod32 = ((uint64_t)kP32 - 1 + kTile32 - 1) / kTil
 // a table), so a width-64 tile needs the same LDS as a width-32 one.
 constexpr int kRun64 = 16;
 constexpr int kTile64 = 64 * kRun64;  // 1024 draws
+// The width-64 reduce takes up to this many consecutive tiles of a request
+// per wave.
+constexpr int kReduceTiles = 16;
 // Constant-skip tiles (both widths): 2048 draws aligned to multiples of 2048.
 constexpr int kTileCS = 2048;
 // The width-64 skip-prefix table (positioning and jumps only) covers skip
@@ -78,7 +81,7 @@ struct alignas(64) ReqRec {
   uint32_t nchunks;     // chunks of this request
   uint32_t seg;         // width 64 pseudorandom skip: number of consecutive requests of this instance
                         // starting here (0 for a request that is not the first of its instance)
-  uint64_t pad;
+  uint64_t rbase;       // width 64 pseudorandom skip: first reduce unit (kReduceTiles tiles) of this request
 };
 static_assert(sizeof(ReqRec) == 64, "ReqRec must be 64 bytes");
 
@@ -89,7 +92,8 @@ struct alignas(64) BatchHdr {
   uint64_t nreq;          // requests
   uint64_t nreq64;        // width-64 pseudorandom-skip requests (the first nreq64)
   uint64_t tiles64;       // their tiles (entries of the tile-state arrays)
-  uint64_t pad[4];
+  uint64_t units64;       // their reduce units
+  uint64_t pad[3];
 };
 static_assert(sizeof(BatchHdr) == 64, "BatchHdr must be 64 bytes");
 

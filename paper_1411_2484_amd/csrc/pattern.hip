@@ -152,6 +152,7 @@ __global__ __launch_bounds__(256) void pattern_sum_kernel(double *part, unsigned
 
 template <int EK>
 hipError_t launch_dim(const PatArgs &A, const ph::PartSet &P, unsigned grid, int dim, hipStream_t st) {
+  clear_launch_error();
   switch (dim) {
     case 2: pattern_kernel<EK, 2><<<grid, 256, 0, st>>>(A, P); break;
     case 3: pattern_kernel<EK, 3><<<grid, 256, 0, st>>>(A, P); break;
@@ -314,6 +315,7 @@ phprng_status phprng_pattern_chi2(const phprng_pattern *P, const uint64_t *hist,
   double *part = (double *)scratch;
   unsigned long long *ptot = (unsigned long long *)((char *)scratch + blocks * 8);
   const double tuples = (double)P->l0 * (double)(P->s_hi - P->s_lo);
+  phprng::clear_launch_error();
   pat::pattern_chi2_kernel<<<blocks, 256, 0, s>>>(reinterpret_cast<const unsigned long long *>(hist), ncell,
                                                    (int)P->dim, P->bins, P->n, tuples, part, ptot);
   pat::pattern_sum_kernel<<<1, 256, 0, s>>>(part, ptot, blocks);

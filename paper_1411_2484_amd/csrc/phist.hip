@@ -1,6 +1,8 @@
 // Stages 2 and 3 of the partitioned histograms (phist.hpp).
 #include "phist.hpp"
 
+#include "arith.hpp"
+
 namespace phprng {
 namespace ph {
 
@@ -67,11 +69,13 @@ __global__ __launch_bounds__(256) void add_kernel(PartSet P) {
 }  // namespace
 
 hipError_t launch_count(const PartSet &P, hipStream_t st) {
+  clear_launch_error();
   count_kernel<<<dim3(P.npart * P.nslice), dim3(1024), 0, st>>>(P);
   return hipGetLastError();
 }
 
 hipError_t launch_add(const PartSet &P, hipStream_t st) {
+  clear_launch_error();
   add_kernel<<<dim3(P.npart * (kPartCells / 256)), dim3(256), 0, st>>>(P);
   return hipGetLastError();
 }

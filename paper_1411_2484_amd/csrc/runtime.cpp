@@ -1,6 +1,6 @@
 // Host runtime behind include/phprng.h: instance tables, seeding, the skip
-// tables, request planning and kernel launches, jumps and state restore and
-// captured repeat draws.
+// tables, request planning and kernel launches, jumps and state restore,
+// captured repeat draws and the allocation-free entry point.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -67,7 +67,10 @@ int bit_length(uint64_t v) {
   return b;
 }
 
-// Requests the planning scratch holds before it grows.
+// Batches of at most this many requests are read by the kernels from pinned
+// host memory instead of a device copy.
+constexpr uint64_t kDirectRequests = 1024;
+// Planning vectors reserved at context creation.
 constexpr uint64_t kPlanReserve = 16384;
 
 // Width-64 draws per request: tiles are counted in 32 bits.
@@ -128,6 +131,7 @@ struct Plan {
   uint64_t nreq = 0;
   uint64_t nreq64 = 0;   // width-64 pseudorandom-skip requests (first in the staging order)
   uint64_t tiles64 = 0;  // their tiles
+  uint64_t units64 = 0;  // their reduce units (kReduceTiles tiles of one request)
   uint64_t tiles = 0;    // all tiles
   uint64_t total_chunks = 0;
   uint32_t tpc = 1;
@@ -162,8 +166,9 @@ struct phprng_ctx {
   // different streams) never overwrite a request block still in use.  A slot
   // is reused only after the event recorded behind its last kernel.
   struct Slot {
-    uint8_t *h_blk = nullptr;  // pinned: BatchHdr + ReqRec[cap]
-    uint8_t *d_blk = nullptr;  // device copy
+    uint8_t *h_blk = nullptr;            // pinned, mapped: BatchHdr + ReqRec[cap]
+    const uint8_t *h_blk_dev = nullptr;  // h_blk's address for kernels
+    uint8_t *d_blk = nullptr;            // device copy
     uint64_t cap = 0;
     WorkCtr *d_ctr = nullptr;
     uint64_t *d_t64 = nullptr;  // 3 * cap64 words
@@ -178,7 +183,8 @@ struct phprng_ctx {
   int last_timed = -1;
   double acc_ms = 0;  // cumulative kernel time of recycled slots
   uint64_t acc_calls = 0;
-  // Planning scratch kept across calls, so that a batch costs O(requests).
+  // Planning scratch kept across calls, so that a batch costs O(requests)
+  // and, below kPlanReserve requests, allocates nothing.
   std::vector<int64_t> where;  // per instance: index in `touched` during a plan, -1 otherwise
   std::vector<uint32_t> touched;
   std::vector<uint64_t> cur_x, cur_k;
@@ -343,14 +349,20 @@ struct phprng_ctx {
       if (s.h_blk) (void)hipHostFree(s.h_blk);
       s.d_blk = nullptr;
       s.h_blk = nullptr;
+      s.h_blk_dev = nullptr;
       s.cap = 0;
       const uint64_t bytes = sizeof(BatchHdr) + cap * sizeof(ReqRec);
       if ((e = hipMalloc(&s.d_blk, bytes)) != hipSuccess)
         return fail(PHPRNG_E_NOMEM, "request buffer: %s", hipGetErrorString(e));
-      if ((e = hipHostMalloc(&s.h_blk, bytes, hipHostMallocDefault)) != hipSuccess) {
+      // coherent: kernels may read the planned requests straight from it
+      if ((e = hipHostMalloc(&s.h_blk, bytes, hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess) {
         s.h_blk = nullptr;
         return fail(PHPRNG_E_NOMEM, "pinned request buffer: %s", hipGetErrorString(e));
       }
+      void *dp = nullptr;
+      if ((e = hipHostGetDevicePointer(&dp, s.h_blk, 0)) != hipSuccess || !dp)
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidValue, "pinned request buffer address");
+      s.h_blk_dev = static_cast<const uint8_t *>(dp);
       s.cap = cap;
     }
     *out = &s;
@@ -389,10 +401,10 @@ phprng_status phprng_ctx::build_table32() {
   uint64_t *d_sum = nullptr;
   uint32_t *d_start = nullptr;
   hipError_t e;
-  if ((e = hipMalloc(&d_sum, ne * sizeof(uint64_t))) != hipSuccess) return hip_fail(e, "table32 alloc");
+  if ((e = hipMalloc(&d_sum, ne * sizeof(uint64_t))) != hipSuccess) return fail(PHPRNG_E_NOMEM, "table32 alloc");
   if ((e = hipMalloc(&d_start, ne * sizeof(uint32_t))) != hipSuccess) {
     (void)hipFree(d_sum);
-    return hip_fail(e, "table32 alloc");
+    return fail(PHPRNG_E_NOMEM, "table32 alloc");
   }
   if ((e = launch_table_segments32(ne, d_sum, d_start, nullptr)) != hipSuccess) return hip_fail(e, "table32 launch");
   std::vector<uint64_t> sums(ne);
@@ -417,7 +429,7 @@ phprng_status phprng_ctx::build_table32() {
     return fail(PHPRNG_E_DEVICE, "32-bit skip-prefix table failed its full-period check");
   }
   d_s32 = d_start;
-  if ((e = hipMalloc(&d_u32, ne * sizeof(uint64_t))) != hipSuccess) return hip_fail(e, "table32 alloc");
+  if ((e = hipMalloc(&d_u32, ne * sizeof(uint64_t))) != hipSuccess) return fail(PHPRNG_E_NOMEM, "table32 alloc");
   if ((e = hipMemcpy(d_u32, u32.data(), ne * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "table32 upload");
   return PHPRNG_OK;
@@ -428,15 +440,15 @@ phprng_status phprng_ctx::build_table64() {
   const uint64_t ne = kTab64Range / kTableStride;
   uint64_t *d_lo = nullptr, *d_hi = nullptr, *d_start = nullptr;
   hipError_t e;
-  if ((e = hipMalloc(&d_lo, ne * 8)) != hipSuccess) return hip_fail(e, "table64 alloc");
+  if ((e = hipMalloc(&d_lo, ne * 8)) != hipSuccess) return fail(PHPRNG_E_NOMEM, "table64 alloc");
   if ((e = hipMalloc(&d_hi, ne * 8)) != hipSuccess) {
     (void)hipFree(d_lo);
-    return hip_fail(e, "table64 alloc");
+    return fail(PHPRNG_E_NOMEM, "table64 alloc");
   }
   if ((e = hipMalloc(&d_start, ne * 8)) != hipSuccess) {
     (void)hipFree(d_lo);
     (void)hipFree(d_hi);
-    return hip_fail(e, "table64 alloc");
+    return fail(PHPRNG_E_NOMEM, "table64 alloc");
   }
   auto give_up = [&](phprng_status st) {
     (void)hipFree(d_lo);
@@ -581,7 +593,7 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   // records
   BatchHdr *H = reinterpret_cast<BatchHdr *>(stage);
   ReqRec *R = reinterpret_cast<ReqRec *>(stage + sizeof(BatchHdr));
-  uint64_t tiles = 0, tiles64 = 0;
+  uint64_t tiles = 0, tiles64 = 0, units64 = 0;
   for (uint64_t p = 0; p < nreq; ++p) {
     const uint64_t i = order[p];
     const phprng_request &q = reqs[i];
@@ -598,6 +610,8 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
       nt = (q.count + kTile64 - 1) / kTile64;
       rr.g1 = tiles64;
       tiles64 += nt;
+      rr.rbase = units64;
+      units64 += (nt + kReduceTiles - 1) / kReduceTiles;
       rr.seg = p == seg_start[t] ? seg_count[t] : 0;
     } else if (h.sched == kSchedConstant) {
       rr.g1 = rr.x / kTileCS;
@@ -615,6 +629,7 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   out.nreq = nreq;
   out.nreq64 = c64l;
   out.tiles64 = tiles64;
+  out.units64 = units64;
   out.tiles = tiles;
   out.has64 = c64l + c64c > 0;
   out.has32 = c32 > 0;
@@ -645,6 +660,7 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   H->nreq = nreq;
   H->nreq64 = c64l;
   H->tiles64 = tiles64;
+  H->units64 = units64;
   *P = out;
   return PHPRNG_OK;
 }
@@ -684,7 +700,7 @@ GenArgs phprng_ctx::args(const uint8_t *d_blk, WorkCtr *ctr, uint64_t *t64, uint
 phprng_status phprng_ctx::launch(const Plan &P, const GenArgs &A, const ReqRec *hreq, hipStream_t s, int mode) {
   hipError_t e;
   if (P.nreq64 > 0) {
-    if ((e = launch_tiles64_reduce(A, P.tiles64, (unsigned)num_cus * 8, s)) != hipSuccess)
+    if ((e = launch_tiles64_reduce(A, P.units64, (unsigned)num_cus * 8, s)) != hipSuccess)
       return hip_fail(e, "tile reduce");
     if (chain_pending && (e = hipStreamWaitEvent(s, chain_ev, 0)) != hipSuccess) return hip_fail(e, "chain wait");
     if ((e = launch_tiles64_scan(A, P.nreq64, s)) != hipSuccess) return hip_fail(e, "tile scan");
@@ -774,7 +790,7 @@ phprng_status phprng_ctx::move64(uint32_t id, uint64_t d, bool forward, bool dry
   else if (pm1 - r <= kJumpMax) path = kComplement;
   else return fail(PHPRNG_E_RANGE, "width-64 move of %llu draws: off the table and too far from a whole skip period",
                    (unsigned long long)d);
-  if (dry_run) return PHPRNG_OK;
+  if (dry_run || d == 0) return PHPRNG_OK;
   if (path == kTable && !have64) {
     phprng_status bs = build_table64();
     if (bs != PHPRNG_OK) return bs;
@@ -1246,10 +1262,17 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
   if ((st = c->ensure_tiles(*slot, P.tiles64)) != PHPRNG_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  const uint64_t bytes = sizeof(BatchHdr) + nreq * sizeof(ReqRec);
-  if ((e = hipMemcpyAsync(slot->d_blk, slot->h_blk, bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
-    return c->hip_fail(e, "request copy");
-  GenArgs A = c->args(slot->d_blk, slot->d_ctr, slot->d_t64, slot->cap64, nreq, out_c32, out_c64, out_r, P.tpc);
+  // Small batches are read by the kernels straight from the pinned block (a
+  // few reads over the bus per chunk, no copy ahead of them); larger ones are
+  // copied to device memory first, where the chunk searches run locally.
+  const bool direct = nreq <= kDirectRequests;
+  if (!direct) {
+    const uint64_t bytes = sizeof(BatchHdr) + nreq * sizeof(ReqRec);
+    if ((e = hipMemcpyAsync(slot->d_blk, slot->h_blk, bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return c->hip_fail(e, "request copy");
+  }
+  GenArgs A = c->args(direct ? slot->h_blk_dev : slot->d_blk, slot->d_ctr, slot->d_t64, slot->cap64, nreq, out_c32,
+                      out_c64, out_r, P.tpc);
   if ((e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
   st = c->launch(P, A, reinterpret_cast<const ReqRec *>(slot->h_blk + sizeof(BatchHdr)), s, mode);
   if (st != PHPRNG_OK) return st;
@@ -1595,7 +1618,7 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
   hipStream_t cap_stream;
   if ((e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking)) != hipSuccess) return c->hip_fail(e, "stream");
   e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess && P.nreq64 > 0) e = launch_tiles64_reduce(A, P.tiles64, (unsigned)c->num_cus * 8, cap_stream);
+  if (e == hipSuccess && P.nreq64 > 0) e = launch_tiles64_reduce(A, P.units64, (unsigned)c->num_cus * 8, cap_stream);
   if (e == hipSuccess && P.nreq64 > 0) e = launch_tiles64_scan(A, P.nreq64, cap_stream);
   if (e == hipSuccess)
     e = launch_persistent(A, (unsigned)(c->num_cus * T.blocks_per_cu), T.block_threads, T.unroll, P.has64, cap_stream);

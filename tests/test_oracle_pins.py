@@ -580,3 +580,28 @@ def test_constant_skip_closed_form_and_full_period(orc):
                 assert orc.encrypt(orc.cskip_message(n, m0, b, k), e, n) == int(c[k - 1])
             for ci, ri in zip(c[:50], r[:50]):
                 assert float(ri) == (int(ci) + 1) / (n + 1)
+
+
+def test_oracle_reproduces_crosscheck_values(orc, tab32):
+    """The example instance of Sec. II from the base state: draws, states and
+    skip sums written by tests/golden/make_crosscheck_values.py from plain
+    Python integers (independent of the oracle's C code)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "crosscheck_values.json")) as f:
+        g = json.load(f)
+    n, e, p, a = g["n"], g["e"], g["p"], g["a"]
+    assert orc.lcg_params(32) == (p, a)
+    c, r, m, s = orc.generate(p, a, n, e, 0, 1, 10 ** 6)
+    for row in g["draws"]:
+        k = row["k"]
+        assert int(c[k - 1]) == row["c"] and r[k - 1] == float.fromhex(row["R"]), k
+        # eq. (7) positions from the checkpoints and by looping agree with the stepped state
+        assert orc.position(tab32, p, a, n, 0, 1, k) == (row["m"], row["s"])
+    assert (m, s) == (g["draws"][-1]["m"], g["draws"][-1]["s"])
+    assert orc.position(None, p, a, n, 0, 1, 10 ** 6) == (m, s)
+    assert tab32.prefix(10 ** 6) == g["U_1e6"]
+    assert tab32.prefix(p - 1) % n == g["full_period_skip_sum_mod_n"]
+    assert orc.inverse(a, p) == g["a_inverse_mod_p"]
+    assert orc.inverse(e, n - 1) == g["d"]
+    assert orc.decrypt(g["draws"][-1]["c"], e, n) == g["draws"][-1]["m"]
