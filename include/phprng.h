@@ -184,6 +184,21 @@ uint64_t phprng_instance_count(const phprng_ctx *ctx);
 phprng_status phprng_generate(phprng_ctx *ctx, const phprng_request *reqs, uint64_t nreq, uint32_t *out_c32,
                               uint64_t *out_c64, double *out_r, uint64_t capacity, void *stream, int mode);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): phprng_generate in
+ * persistent mode that calls no hipMalloc, hipFree or other allocating
+ * routine.  Its device scratch (the planned requests, the work counter and
+ * the width-64 tile state) is one fixed array per device, about 7.3 MB, held
+ * until the process ends; its host staging buffer is allocated when the
+ * context is created.  Limits: at most 16384 requests and 2^18 width-64
+ * tiles (2^28 width-64 draws) per call, else PHPRNG_E_RANGE with nothing
+ * changed.  Every call on a device shares that device's scratch: calls that
+ * overlap on one device (different streams, or different contexts) race;
+ * calls ordered on one stream do not.  Arguments and results as for
+ * phprng_generate; no kernel timing is recorded. */
+phprng_status phprng_generate_noalloc(phprng_ctx *ctx, const phprng_request *reqs, uint64_t nreq, uint32_t *out_c32,
+                                      uint64_t *out_c64, double *out_r, uint64_t capacity, void *stream);
+
 /* Move instance `id` by delta positions (eq. (7); delta < 0 moves backward as
  * in Sec. II).  PHPRNG_E_RANGE if the position would leave its range.  A
  * width-64 move of d = q (p - 1) + r draws adds q whole skip periods

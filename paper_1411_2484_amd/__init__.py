@@ -35,6 +35,9 @@ PHPRNG_CLASS_W32 = 0
 PHPRNG_CLASS_W64 = 1
 PHPRNG_CLASS_MIXED = 2
 
+NOALLOC_MAX_REQUESTS = 16384
+NOALLOC_MAX_TILES64 = 1 << 18
+
 _u64 = ctypes.c_uint64
 _pu64 = ctypes.POINTER(ctypes.c_uint64)
 _pu32 = ctypes.POINTER(ctypes.c_uint32)
@@ -110,6 +113,7 @@ SIGNATURES = {
                                                  _pu32]),
     "phprng_get_schedule": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int), _pu64]),
     "phprng_generate": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp, ctypes.c_int]),
+    "phprng_generate_noalloc": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _vp, _u64, _vp]),
     "phprng_jump": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_int64]),
     "phprng_get_state": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(phprng_state)]),
     "phprng_set_state": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(phprng_state)]),
@@ -368,6 +372,14 @@ class Context:
         p32, p64, pr, cap = _outputs(out_c32, out_c64, out_r, self.device, capacity)
         self._chk(lib().phprng_generate(self._h, reqs.ctypes.data, reqs.size, p32, p64, pr, cap,
                                         _stream_handle(stream), int(mode)))
+
+    def generate_noalloc(self, requests, out_c32=None, out_c64=None, out_r=None, capacity=None, stream=None):
+        """phprng_generate_noalloc: the persistent generation without any
+        allocation (fixed per-device scratch; see include/phprng.h)."""
+        reqs = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
+        p32, p64, pr, cap = _outputs(out_c32, out_c64, out_r, self.device, capacity)
+        self._chk(lib().phprng_generate_noalloc(self._h, reqs.ctypes.data, reqs.size, p32, p64, pr, cap,
+                                                _stream_handle(stream)))
 
     def last_kernel_ms(self):
         v = ctypes.c_double()

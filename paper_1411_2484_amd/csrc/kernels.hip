@@ -4,7 +4,8 @@
 //     scan per instance that also commits the instance's message),
 //   - batched generation (algorithm (9)) as a persistent work-stealing grid
 //     or as one plain grid per request,
-//   - width-64 positioning and jumps (eq. (7) sums on the device).
+//   - width-64 positioning and jumps (eq. (7) sums on the device),
+//   - the fixed scratch of the allocation-free entry point.
 //
 // Width-32 tiles are 2048 consecutive draws of one instance whose starting
 // state index is a multiple of 2048 within the skip period: the universal
@@ -782,6 +783,45 @@ __global__ void __launch_bounds__(64) gen_plain(GenArgs A, uint64_t r) {
   const ReqRec R = dev::const_load(A.req + r);
   if ((uint64_t)blockIdx.x >= R.nchunks) return;
   run_chunk<UNROLL, HAS64>(A, R, blockIdx.x, lds, lane);
+}
+
+// ---------------------------------------------------------------------------
+// fixed scratch of the allocation-free entry point
+// ---------------------------------------------------------------------------
+
+// One copy per device, held until the process ends.  Host code never passes
+// this name to a kernel: it takes the device address once per device
+// (scratch_address) and uses that.
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+__global__ void __launch_bounds__(64) clear_words(uint32_t *p, uint32_t nwords) {
+  for (uint32_t i = threadIdx.x; i < nwords; i += 64) p[i] = 0;
+}
+
+hipError_t scratch_address(int device, void **ptr) {
+  clear_launch_error();
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices || !ptr) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    // the work counter must start at zero; every launch leaves it so
+    hipLaunchKernelGGL(clear_words, dim3(1), dim3(64), 0, nullptr, static_cast<uint32_t *>(p),
+                       (uint32_t)(kScratchClearBytes / 4));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -7,6 +7,25 @@
 
 namespace phprng {
 
+// Fixed device scratch of the allocation-free entry point (one per device):
+// the work counter, the batch header, the planned requests and the width-64
+// tile state, at these byte offsets.
+constexpr int kMaxDevices = 64;
+constexpr uint64_t kNoAllocMaxRequests = 16384;
+constexpr uint64_t kNoAllocMaxTiles64 = 1ull << 18;
+constexpr uint64_t kScratchCtrOff = 0;
+constexpr uint64_t kScratchReqOff = 256;
+constexpr uint64_t kScratchHdrOff = kScratchReqOff - sizeof(BatchHdr);  // header right before the requests
+constexpr uint64_t kScratchTileOff = kScratchReqOff + kNoAllocMaxRequests * sizeof(ReqRec);
+constexpr uint64_t kScratchBytes = kScratchTileOff + 3 * kNoAllocMaxTiles64 * sizeof(uint64_t);
+constexpr uint64_t kScratchClearBytes = sizeof(WorkCtr);
+static_assert(kScratchTileOff % 256 == 0, "tile arrays aligned");
+
+// Device address of this device's scratch (the current device must be
+// `device`).  The first call on a device looks the address up and clears the
+// work counter; later calls return the kept address.
+hipError_t scratch_address(int device, void **ptr);
+
 hipError_t launch_table_segments32(uint64_t nseg, uint64_t *seg_sum, uint32_t *seg_start, hipStream_t st);
 hipError_t launch_table_segments64(uint64_t nseg, uint64_t *seg_lo, uint64_t *seg_hi, uint64_t *seg_start,
                                    hipStream_t st);

@@ -72,6 +72,7 @@ int bit_length(uint64_t v) {
 constexpr uint64_t kDirectRequests = 1024;
 // Planning vectors reserved at context creation.
 constexpr uint64_t kPlanReserve = 16384;
+static_assert(kNoAllocMaxRequests <= kPlanReserve, "allocation-free calls plan without growing a vector");
 
 // Width-64 draws per request: tiles are counted in 32 bits.
 constexpr uint64_t kMaxCount64 = (uint64_t)kTile64 << 32;
@@ -193,6 +194,12 @@ struct phprng_ctx {
   std::vector<uint32_t> req_pos;
   std::vector<uint32_t> order;
   phprng_tuning tuning[3] = {{256, 4, 8, 4}, {256, 4, 8, 4}, {256, 4, 8, 4}};
+  // allocation-free entry point: the device's fixed scratch and a pinned
+  // staging block for its requests
+  uint8_t *scratch = nullptr;
+  uint8_t *h_noalloc = nullptr;
+  hipEvent_t noalloc_copied = nullptr;
+  bool noalloc_pending = false;
   std::string err;
 
   ~phprng_ctx() {
@@ -208,6 +215,8 @@ struct phprng_ctx {
     (void)hipFree(d_s64);
     (void)hipFree(d_partial);
     if (chain_ev) (void)hipEventDestroy(chain_ev);
+    if (noalloc_copied) (void)hipEventDestroy(noalloc_copied);
+    if (h_noalloc) (void)hipHostFree(h_noalloc);
     for (auto &s : slots) {
       (void)hipFree(s.d_blk);
       if (s.h_blk) (void)hipHostFree(s.h_blk);
@@ -943,6 +952,16 @@ extern "C" phprng_status phprng_create(phprng_ctx **out, int device, uint64_t ma
   if (hipMalloc(&c->d_lanemul, sizeof(LaneMul)) != hipSuccess) return PHPRNG_E_NOMEM;
   if (hipMemcpy(c->d_lanemul, &lm, sizeof lm, hipMemcpyHostToDevice) != hipSuccess) return PHPRNG_E_DEVICE;
   if (hipEventCreateWithFlags(&c->chain_ev, hipEventDisableTiming) != hipSuccess) return PHPRNG_E_DEVICE;
+  // the fixed scratch of the allocation-free entry point, looked up once per device
+  void *sp = nullptr;
+  if (scratch_address(device, &sp) != hipSuccess || !sp) return PHPRNG_E_DEVICE;
+  c->scratch = static_cast<uint8_t *>(sp);
+  if (hipHostMalloc(&c->h_noalloc, sizeof(BatchHdr) + kNoAllocMaxRequests * sizeof(ReqRec), hipHostMallocDefault) !=
+      hipSuccess) {
+    c->h_noalloc = nullptr;
+    return PHPRNG_E_NOMEM;
+  }
+  if (hipEventCreateWithFlags(&c->noalloc_copied, hipEventDisableTiming) != hipSuccess) return PHPRNG_E_DEVICE;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (int cls = 0; cls < 3; ++cls) {
@@ -1280,6 +1299,44 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
   if ((e = hipEventRecord(slot->done, s)) != hipSuccess) return c->hip_fail(e, "event");
   slot->busy = true;
   c->last_timed = c->cur_slot;
+  c->commit_plan();
+  return PHPRNG_OK;
+}
+
+extern "C" phprng_status phprng_generate_noalloc(phprng_ctx *c, const phprng_request *reqs, uint64_t nreq,
+                                                 uint32_t *out_c32, uint64_t *out_c64, double *out_r,
+                                                 uint64_t capacity, void *stream) {
+  if (!c) return PHPRNG_E_INVALID;
+  if (nreq == 0) return PHPRNG_OK;
+  if (nreq > kNoAllocMaxRequests)
+    return c->fail(PHPRNG_E_RANGE, "allocation-free generation takes at most %llu requests per call",
+                   (unsigned long long)kNoAllocMaxRequests);
+  (void)hipSetDevice(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  // the pinned staging block is rewritten only after the previous call's copy ran
+  if (c->noalloc_pending) {
+    if ((e = hipEventSynchronize(c->noalloc_copied)) != hipSuccess) return c->hip_fail(e, "staging wait");
+    c->noalloc_pending = false;
+  }
+  Plan P;
+  phprng_status st = c->plan(reqs, nreq, capacity, PHPRNG_MODE_PERSISTENT, nullptr, kNoAllocMaxRequests,
+                             c->h_noalloc, &P);
+  if (st != PHPRNG_OK) return st;
+  if (P.tiles64 > kNoAllocMaxTiles64)
+    return c->fail(PHPRNG_E_RANGE, "allocation-free generation takes at most %llu width-64 tiles (%llu draws) per call",
+                   (unsigned long long)kNoAllocMaxTiles64, (unsigned long long)(kNoAllocMaxTiles64 * kTile64));
+  uint8_t *blk = c->scratch + kScratchHdrOff;
+  const uint64_t bytes = sizeof(BatchHdr) + nreq * sizeof(ReqRec);
+  if ((e = hipMemcpyAsync(blk, c->h_noalloc, bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return c->hip_fail(e, "request copy");
+  if ((e = hipEventRecord(c->noalloc_copied, s)) != hipSuccess) return c->hip_fail(e, "event");
+  c->noalloc_pending = true;
+  GenArgs A = c->args(blk, reinterpret_cast<WorkCtr *>(c->scratch + kScratchCtrOff),
+                      reinterpret_cast<uint64_t *>(c->scratch + kScratchTileOff), kNoAllocMaxTiles64, nreq, out_c32,
+                      out_c64, out_r, P.tpc);
+  st = c->launch(P, A, reinterpret_cast<const ReqRec *>(c->h_noalloc + sizeof(BatchHdr)), s, PHPRNG_MODE_PERSISTENT);
+  if (st != PHPRNG_OK) return st;
   c->commit_plan();
   return PHPRNG_OK;
 }

@@ -83,3 +83,5 @@ def test_generate_checks_before_the_library():
         ctx.generate(reqs, None, None, FakeTensor(torch.float32))
     with pytest.raises(ValueError):
         ctx.generate(reqs, None, None, torch.zeros(4, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        ctx.generate_noalloc(reqs, FakeTensor(torch.float64), None, None)
