@@ -218,14 +218,21 @@ def section_headline(args, torch, ph, out):
     cnt = committed_counters()
     if cnt:
         roof["traffic"] = cnt.get("traffic_bytes_per_launch")
-        # issued VALU lane-instructions and the hardware's VALU-busy cycles,
-        # per launch from the counter runs, against this run's kernel time
-        if cnt.get("valu_insts_per_launch"):
-            issued = cnt["valu_insts_per_launch"] * 64 / (kms * 1e-3)
-            roof["issued_valu_frac"] = issued / ALU_PEAK_OPS
-        for k in ("valu_busy_frac", "clock_ghz", "cycle_weighted_frac", "cycle_weighted_model"):
-            if k in cnt:
-                roof[k] = cnt[k]
+        # per launch from the counter runs, against this run's kernel time:
+        #   issued: VALU lane-instructions / (time x 64 lane-ops per CU per
+        #           clock at 2.4 GHz);
+        #   cycle-weighted: each issued instruction costed at the measured
+        #           chip-wide rate of its class (opcode mix of the kernel's
+        #           per-draw code), summed, / time;
+        #   sclk: busy cycles per XCD (GRBM_GUI_ACTIVE) / time.
+        n_valu = cnt.get("valu_insts_per_launch")
+        if n_valu:
+            roof["issued_valu_frac"] = n_valu * 64 / (kms * 1e-3) / ALU_PEAK_OPS
+            if cnt.get("valu_seconds_per_inst"):
+                roof["cycle_weighted_frac"] = n_valu * cnt["valu_seconds_per_inst"] / (kms * 1e-3)
+                roof["cycle_weighted_model"] = cnt.get("cycle_weighted_model")
+        if cnt.get("grbm_cycles_per_xcd"):
+            roof["sclk_ghz_est"] = cnt["grbm_cycles_per_xcd"] / (kms * 1e-3) / 1e9
     out.update({"value": value, "ms_per_step": ms, "roofline": roof, "roofline_hbm": roofs["hbm"]})
     out["config"].update({"tuning": tuning})
 

@@ -1,6 +1,10 @@
 """Build the gfx950 HIP library libphprng.so in-tree with hipcc.
 
 Usage: python -m paper_1411_2484_amd.build  (or call build()).
+
+The instruction-rate probe behind the measured per-class VALU rates is a
+measurement tool, not part of the library: build it on its own with
+python -m paper_1411_2484_amd.build --probe  (writes paper_1411_2484_amd/probe_rates).
 """
 
 from __future__ import annotations
@@ -38,8 +42,8 @@ def _run(cmd, what, verbose):
 
 
 def build(verbose: bool = False, jobs: int = 0) -> str:
-    """Compiles every source (in parallel, `jobs` at a time; 0: up to 8),
-    links libphprng.so and builds the instruction-rate probe."""
+    """Compiles every source (in parallel, `jobs` at a time; 0: up to 8) and
+    links libphprng.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
@@ -51,15 +55,10 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         cmds.append(([hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *lang, "-c",
                       os.path.join(CSRC, src), "-o", obj], src))
         objs.append(obj)
-    # instruction-rate probe (a standalone executable)
-    probe = os.path.join(HERE, "probe_rates")
-    cmds.append(([hipcc, *HIPCC_FLAGS, "-o", probe + ".tmp", os.path.join(CSRC, "probe_rates.hip")],
-                 "probe_rates.hip"))
     workers = jobs if jobs > 0 else max(1, min(8, os.cpu_count() or 1))
     with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as pool:
         for f in [pool.submit(_run, cmd, what, verbose) for cmd, what in cmds]:
             f.result()
-    os.replace(probe + ".tmp", probe)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -70,5 +69,15 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     return LIB
 
 
+def build_probe(verbose: bool = False) -> str:
+    """Builds the standalone instruction-rate probe (csrc/probe_rates.hip)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    probe = os.path.join(HERE, "probe_rates")
+    _run([hipcc, *HIPCC_FLAGS, "-o", probe + ".tmp", os.path.join(CSRC, "probe_rates.hip")], "probe_rates.hip",
+         verbose)
+    os.replace(probe + ".tmp", probe)
+    return probe
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build_probe(verbose=True) if "--probe" in sys.argv[1:] else build(verbose=True))
