@@ -2,8 +2,9 @@
 // 64-bit moduli from 32-bit limbs), Mersenne reductions for the skip
 // generators, and the wave-level helpers the kernels use.
 //
-// On gfx950 v_mul_lo_u32, v_mul_hi_u32 and v_mad_u64_u32 issue at the full
-// VALU rate, so a 32 x 32 -> 64 product is one v_mad_u64_u32.
+// A 32 x 32 -> 64 product (plus a 64-bit addend) is one v_mad_u64_u32; on
+// gfx950 it issues at about 60% of the rate of a plain 32-bit add, so the
+// 64-bit routines below are arranged to need few of them and no carries.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -138,37 +139,57 @@ struct W128 {
   uint64_t lo, hi;
 };
 
-// Full 64 x 64 -> 128 product from four 32 x 32 -> 64 multiply-adds.
-__device__ __forceinline__ W128 mul64w(uint64_t x, uint64_t y) {
-  uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
-  uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
-  uint64_t p00 = (uint64_t)x0 * y0;
-  uint64_t p01 = (uint64_t)x0 * y1 + (p00 >> 32);
-  uint64_t p10 = (uint64_t)x1 * y0 + (uint32_t)p01;
-  uint64_t p11 = (uint64_t)x1 * y1 + (p01 >> 32) + (p10 >> 32);
-  W128 r;
-  r.lo = (p10 << 32) | (uint32_t)p00;
-  r.hi = p11;
-  return r;
+// Full product of x, y < 2^63.  The high words are below 2^31, so
+// x1 y0 + x0 y1 + hi(x0 y0) < 2^64: three multiply-adds chain without a
+// carry, and each 64-bit addend is a whole register pair.
+__device__ __forceinline__ W128 mul63w(uint64_t x, uint64_t y) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+  const uint64_t p00 = (uint64_t)x0 * y0;
+  const uint64_t mid = (uint64_t)x1 * y0 + ((uint64_t)x0 * y1 + (p00 >> 32));
+  return {(mid << 32) | (uint32_t)p00, (uint64_t)x1 * y1 + (mid >> 32)};
 }
 
-// x y 2^{-64} mod n for x, y < n < 2^63; ninv = n^{-1} mod 2^64.
-__device__ __forceinline__ uint64_t mont64(uint64_t x, uint64_t y, uint64_t n, uint64_t ninv) {
-  W128 t = mul64w(x, y);
-  uint64_t q = t.lo * ninv;
-  uint64_t qh = mul64w(q, n).hi;
-  unsigned long r;
-  bool borrow = __builtin_usubl_overflow(t.hi, qh, &r);
-  return (uint64_t)r + (borrow ? n : 0ull);
+// x^2 for x < 2^63: the cross term is one product with 2 x1 < 2^32.
+__device__ __forceinline__ W128 sqr63w(uint64_t x) {
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
+  const uint64_t p00 = (uint64_t)x0 * x0;
+  // 2 x1 as one shift (the compiler otherwise forms it from both words)
+  uint32_t x1d;
+  asm("v_lshlrev_b32 %0, 1, %1" : "=v"(x1d) : "v"(x1));
+  const uint64_t mid = (uint64_t)x0 * x1d + (p00 >> 32);
+  return {(mid << 32) | (uint32_t)p00, (uint64_t)x1 * x1 + (mid >> 32)};
 }
 
-// v 2^{-64} mod n for v < n 2^64.
+// High word of q n for n < 2^63: with h = hi(q0 n0), a = q1 n0 + h < 2^64
+// and b = q0 n1 + lo(a) < 2^64, the high word is q1 n1 + hi(a) + hi(b).
+__device__ __forceinline__ uint64_t mulhi_n63(uint64_t q, uint64_t n) {
+  const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+  const uint32_t n0 = (uint32_t)n, n1 = (uint32_t)(n >> 32);
+  const uint64_t a = (uint64_t)q1 * n0 + __umulhi(q0, n0);
+  const uint64_t b = (uint64_t)q0 * n1 + (uint32_t)a;
+  return (uint64_t)q1 * n1 + (a >> 32) + (b >> 32);
+}
+
+// v 2^{-64} mod n for v < n 2^64, n < 2^63 odd; ninv = n^{-1} mod 2^64.  The
+// low words of v and q n cancel exactly, so the result is hi(v) - hi(q n)
+// (+ n).
 __device__ __forceinline__ uint64_t redc64(W128 v, uint64_t n, uint64_t ninv) {
-  uint64_t q = v.lo * ninv;
-  uint64_t qh = mul64w(q, n).hi;
+  const uint64_t q = v.lo * ninv;
+  const uint64_t qh = mulhi_n63(q, n);
   unsigned long r;
   bool borrow = __builtin_usubl_overflow(v.hi, qh, &r);
   return (uint64_t)r + (borrow ? n : 0ull);
+}
+
+// x y 2^{-64} mod n for x, y < n < 2^63.
+__device__ __forceinline__ uint64_t mont64(uint64_t x, uint64_t y, uint64_t n, uint64_t ninv) {
+  return redc64(mul63w(x, y), n, ninv);
+}
+
+// x^2 2^{-64} mod n for x < n < 2^63.
+__device__ __forceinline__ uint64_t msqr64(uint64_t x, uint64_t n, uint64_t ninv) {
+  return redc64(sqr63w(x), n, ninv);
 }
 
 // (m + s) mod n for m, s < n < 2^63 (no overflow of the sum).
@@ -177,32 +198,39 @@ __device__ __forceinline__ uint64_t addmod64(uint64_t m, uint64_t s, uint64_t n)
   return t >= n ? t - n : t;
 }
 
+// v mod n for v < 4n (n < 2^63, so 2n fits 64 bits).
+__device__ __forceinline__ uint64_t mod_below_4n(uint64_t v, uint64_t n) {
+  const uint64_t n2 = n << 1;
+  v = v >= n2 ? v - n2 : v;
+  return v >= n ? v - n : v;
+}
+
 template <int EK>
 __device__ __forceinline__ uint64_t encrypt64(uint64_t m, uint64_t n, uint64_t ninv, uint64_t kc, uint64_t e,
                                               int ebits) {
   uint64_t x;
   if constexpr (EK == 3) {
-    x = mont64(m, m, n, ninv);
+    x = msqr64(m, n, ninv);
     x = mont64(x, m, n, ninv);
   } else if constexpr (EK == 5) {
-    x = mont64(m, m, n, ninv);
-    x = mont64(x, x, n, ninv);
+    x = msqr64(m, n, ninv);
+    x = msqr64(x, n, ninv);
     x = mont64(x, m, n, ninv);
   } else if constexpr (EK == 9) {
-    x = mont64(m, m, n, ninv);
-    x = mont64(x, x, n, ninv);
-    x = mont64(x, x, n, ninv);
+    x = msqr64(m, n, ninv);
+    x = msqr64(x, n, ninv);
+    x = msqr64(x, n, ninv);
     x = mont64(x, m, n, ninv);
   } else if constexpr (EK == 17) {
-    x = mont64(m, m, n, ninv);
-    x = mont64(x, x, n, ninv);
-    x = mont64(x, x, n, ninv);
-    x = mont64(x, x, n, ninv);
+    x = msqr64(m, n, ninv);
+    x = msqr64(x, n, ninv);
+    x = msqr64(x, n, ninv);
+    x = msqr64(x, n, ninv);
     x = mont64(x, m, n, ninv);
   } else {
     x = m;
     for (int b = ebits - 2; b >= 0; --b) {
-      x = mont64(x, x, n, ninv);
+      x = msqr64(x, n, ninv);
       if ((e >> b) & 1) x = mont64(x, m, n, ninv);
     }
   }
@@ -211,7 +239,7 @@ __device__ __forceinline__ uint64_t encrypt64(uint64_t m, uint64_t n, uint64_t n
 
 // Skip generator mod 2^61 - 1 (width 64): fold the 122-bit product.
 __device__ __forceinline__ uint64_t mulmod_p61(uint64_t x, uint64_t y) {
-  W128 t = mul64w(x, y);
+  W128 t = mul63w(x, y);
   uint64_t lo = t.lo & kP64;
   uint64_t hi = (t.hi << 3) | (t.lo >> 61);
   uint64_t v = lo + hi;

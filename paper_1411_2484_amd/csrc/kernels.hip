@@ -262,15 +262,35 @@ __global__ void __launch_bounds__(256) reduce64_kernel(GenArgs A) {
     uint64_t lg = R.x + (uint64_t)j0 * kTile64;  // x < p - 1 and j * 1024 < 2^42: one subtraction wraps it
     if (lg >= pm1) lg -= pm1;
     uint64_t s_tile = dev::wave_pow_p61(A.lanemul->pow64, lg, lane);
+    const uint64_t a8 = A.lanemul->pow64[3];  // a^8
     for (uint32_t j = j0; j < j1; ++j) {
       const uint32_t len = tile_len64(R, j);
-      uint64_t s = dev::mulmod_p61(s_tile, lane_mul);
-      uint64_t sum = 0;
-      const uint32_t first = lane * kRun64;
+      uint64_t sum;
+      uint64_t s = dev::mulmod_p61(s_tile, lane_mul);  // skip before the lane's run
+      if (len == kTile64) {
+        // The run as two independent chains of 8 skips (more work in flight
+        // per lane).  Eight skips below 2^61 sum below 2^64 < 4n, so each
+        // chain is summed in plain 64-bit adds and reduced once.
+        uint64_t s2 = dev::mulmod_p61(s, a8);
+        uint64_t g1 = 0, g2 = 0;
+#pragma unroll
+        for (int i = 0; i < kRun64 / 2; ++i) {
+          s = dev::mulmod_p61(kA64, s);
+          s2 = dev::mulmod_p61(kA64, s2);
+          g1 += s;
+          g2 += s2;
+        }
+        sum = dev::addmod64(dev::mod_below_4n(g1, n), dev::mod_below_4n(g2, n), n);
+        s = s2;
+      } else {
+        // the request's last tile: only draws below len count
+        const uint32_t first = lane * kRun64;
+        sum = 0;
 #pragma unroll 4
-      for (int i = 0; i < kRun64; ++i) {
-        s = dev::mulmod_p61(kA64, s);
-        if (first + (uint32_t)i < len) sum = dev::addmod64(sum, s, n);
+        for (int i = 0; i < kRun64; ++i) {
+          s = dev::mulmod_p61(kA64, s);
+          if (first + (uint32_t)i < len) sum = dev::addmod64(sum, s, n);
+        }
       }
       sum = dev::wave_sum_mod(sum, n);
       if (lane == 0) {
@@ -566,13 +586,21 @@ __device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R,
     // ---- pass A
     uint64_t *row = L + lane * kRow64;
     uint64_t s = dev::mulmod_p61(s_t, lane_mul);
-    uint64_t sum = 0;
+    // eight skips below 2^61 sum below 2^64 < 4n: plain adds, one reduction per half run
+    uint64_t g1 = 0, g2 = 0;
 #pragma unroll 4
-    for (int i = 0; i < kRun64; ++i) {
+    for (int i = 0; i < kRun64 / 2; ++i) {
       s = dev::mulmod_p61(kA64, s);
       row[i] = s;
-      sum = dev::addmod64(sum, s, n);
+      g1 += s;
     }
+#pragma unroll 4
+    for (int i = kRun64 / 2; i < kRun64; ++i) {
+      s = dev::mulmod_p61(kA64, s);
+      row[i] = s;
+      g2 += s;
+    }
+    const uint64_t sum = dev::addmod64(dev::mod_below_4n(g1, n), dev::mod_below_4n(g2, n), n);
     // ---- pass B
     uint64_t m = dev::addmod64(m_t, dev::wave_exclusive_mod(sum, n, lane), n);
 #pragma unroll 4
@@ -754,24 +782,30 @@ __global__ void __launch_bounds__(BLOCK) gen_persistent(GenArgs A) {
   // therefore need no atomics, and large ones avoid the start-up burst.
   const uint32_t nwaves = gridDim.x * (BLOCK / 64);
   uint64_t c = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
+  auto run = [&](uint64_t chunk) {
+    const uint64_t r =
+        dev::uniform_u64(wave_search(A.nreq, chunk, lane, [&](uint64_t i) { return A.req[i].chunk_base; }));
+    const ReqRec R = dev::const_load(A.req + r);
+    run_chunk<UNROLL, HAS64>(A, R, chunk - R.chunk_base, L, lane);
+  };
+  if (total <= nwaves) {
+    // no more chunks than waves: no counter traffic at all
+    if (c < total) run(c);
+    return;
+  }
+  // Every wave grabs until a grab fails, so there are total - nwaves
+  // successful grabs and one failed grab per wave: the grabs return
+  // 0 .. total - 1, and the one returning total - 1 is the last of all.  Its
+  // wave puts the counter back to zero for the next launch.
   for (;;) {
     if (c >= total) break;
-    const uint64_t r =
-        dev::uniform_u64(wave_search(A.nreq, c, lane, [&](uint64_t i) { return A.req[i].chunk_base; }));
-    const ReqRec R = dev::const_load(A.req + r);
-    run_chunk<UNROLL, HAS64>(A, R, c - R.chunk_base, L, lane);
+    run(c);
     uint32_t next = 0;
-    if (lane == 0) next = atomicAdd(&A.ctr->counter, 1u);
-    c = (uint64_t)nwaves + dev::uniform_u32((uint32_t)__shfl((int)next, 0, 64));
-  }
-  // Every wave counts itself out; the last one leaves the counter at zero
-  // for the next launch (every other wave has made its last grab by then).
-  if (lane == 0) {
-    const uint32_t prev = atomicAdd(&A.ctr->done, 1u);
-    if (prev == nwaves - 1) {
-      __hip_atomic_store(&A.ctr->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&A.ctr->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) {
+      next = atomicAdd(&A.ctr->counter, 1u);
+      if ((uint64_t)next == total - 1) __hip_atomic_store(&A.ctr->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    c = (uint64_t)nwaves + dev::uniform_u32((uint32_t)__shfl((int)next, 0, 64));
   }
 }
 

@@ -97,12 +97,11 @@ struct alignas(64) BatchHdr {
 };
 static_assert(sizeof(BatchHdr) == 64, "BatchHdr must be 64 bytes");
 
-// Work-stealing counter of the generation kernel.  Both words are zero when
-// a launch starts; the last wave to finish clears them again.
+// Work-stealing counter of the generation kernel: zero when a launch starts;
+// the wave that makes the launch's last grab sets it back to zero.
 struct alignas(64) WorkCtr {
   uint32_t counter;
-  uint32_t done;
-  uint32_t pad[14];
+  uint32_t pad[15];
 };
 
 // Width-64 tile state of a batch: skip and message before each tile, and

@@ -663,6 +663,8 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
     rr.nchunks = (uint32_t)nc;
     chunks += nc;
   }
+  // the work counter hands out chunk numbers in 32 bits
+  if (chunks >= (1ull << 31)) return fail(PHPRNG_E_RANGE, "batch too large: %llu chunks", (unsigned long long)chunks);
   out.total_chunks = chunks;
   memset(H, 0, sizeof *H);
   H->total_chunks = chunks;
@@ -719,11 +721,14 @@ phprng_status phprng_ctx::launch(const Plan &P, const GenArgs &A, const ReqRec *
   const phprng_tuning &T = tuning[P.cls];
   if (mode == PHPRNG_MODE_PERSISTENT) {
     if (P.total_chunks == 0) return PHPRNG_OK;
-    // no more blocks than the batch can keep busy
+    // A batch with fewer chunks than the tuned grid has waves runs one wave
+    // per chunk in one-wave blocks, so that its waves spread over every
+    // compute unit instead of filling a few with whole blocks.
     const uint64_t wpb = (uint64_t)T.block_threads / 64;
-    const unsigned grid = (unsigned)std::max<uint64_t>(
-        1, std::min<uint64_t>((uint64_t)num_cus * T.blocks_per_cu, (P.total_chunks + wpb - 1) / wpb));
-    if ((e = launch_persistent(A, grid, T.block_threads, T.unroll, P.has64, s)) != hipSuccess)
+    const uint64_t full = (uint64_t)num_cus * T.blocks_per_cu * wpb;
+    const int block = P.total_chunks < full ? 64 : T.block_threads;
+    const unsigned grid = (unsigned)(P.total_chunks < full ? P.total_chunks : (uint64_t)num_cus * T.blocks_per_cu);
+    if ((e = launch_persistent(A, grid, block, T.unroll, P.has64, s)) != hipSuccess)
       return hip_fail(e, "persistent launch");
   } else {
     // one grid per request, from the host copy of the planned requests
