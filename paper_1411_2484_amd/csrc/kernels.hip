@@ -782,24 +782,20 @@ __global__ void __launch_bounds__(BLOCK) gen_persistent(GenArgs A) {
   // therefore need no atomics, and large ones avoid the start-up burst.
   const uint32_t nwaves = gridDim.x * (BLOCK / 64);
   uint64_t c = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
-  auto run = [&](uint64_t chunk) {
-    const uint64_t r =
-        dev::uniform_u64(wave_search(A.nreq, chunk, lane, [&](uint64_t i) { return A.req[i].chunk_base; }));
-    const ReqRec R = dev::const_load(A.req + r);
-    run_chunk<UNROLL, HAS64>(A, R, chunk - R.chunk_base, L, lane);
-  };
-  if (total <= nwaves) {
-    // no more chunks than waves: no counter traffic at all
-    if (c < total) run(c);
-    return;
-  }
   // Every wave grabs until a grab fails, so there are total - nwaves
   // successful grabs and one failed grab per wave: the grabs return
   // 0 .. total - 1, and the one returning total - 1 is the last of all.  Its
-  // wave puts the counter back to zero for the next launch.
+  // wave puts the counter back to zero for the next launch.  A batch with no
+  // more chunks than waves never touches the counter.  (One call site of
+  // run_chunk: a second one gets the whole chunk code outlined into a call.)
+  const bool grab = total > nwaves;
   for (;;) {
     if (c >= total) break;
-    run(c);
+    const uint64_t r =
+        dev::uniform_u64(wave_search(A.nreq, c, lane, [&](uint64_t i) { return A.req[i].chunk_base; }));
+    const ReqRec R = dev::const_load(A.req + r);
+    run_chunk<UNROLL, HAS64>(A, R, c - R.chunk_base, L, lane);
+    if (!grab) break;
     uint32_t next = 0;
     if (lane == 0) {
       next = atomicAdd(&A.ctr->counter, 1u);
