@@ -578,7 +578,7 @@ def pattern_ops_per_tuple(dim, e=9):
 
 
 def workload_g(args, torch, ph):
-    """Full-period local pattern of Sec. III with the Tests section's sizes:
+    """Full-period local pattern of Sec. II, Figs. 3-4 with the Tests section's sizes:
     the paper's safe prime n = 4294967087, e = 9, the 128 first points
     [0, 128), every skip of the period [1, p), D = 3, 4, 5 in 2^24 cells."""
     import oracle

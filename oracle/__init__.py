@@ -283,7 +283,7 @@ def count_many(values, mode, e=0, nthreads=0):
 
 
 def pattern_hist(n, e, p, a, x0, l0, dim, bins, s_lo, s_hi):
-    """Full-period local pattern histogram (Sec. III): counts of the D-1
+    """Full-period local pattern histogram (Sec. II, Figs. 3-4): counts of the D-1
     points that follow every first point c in [x0, x0 + l0), over skips
     s in [s_lo, s_hi), in bins^(dim-1) cells."""
     hist = np.zeros(int(bins) ** (int(dim) - 1), dtype=np.uint64)

@@ -1,4 +1,4 @@
-"""CPU oracle of the full-period local pattern analysis (Sec. III: the
+"""CPU oracle of the full-period local pattern analysis (Sec. II, Figs. 3-4: the
 D-dimensional pattern of consecutive ciphertexts over the whole period in
 O(p L0) steps; the Tests section applies chi-square tests to its histogram).
 

@@ -599,7 +599,7 @@ uint64_t pho_count_many(int nthreads, const uint64_t *v, uint64_t len, int mode,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Full-period local pattern (Sec. III: the D-dimensional pattern of         */
+/* Full-period local pattern (Sec. II, Figs. 3-4: the D-dimensional pattern of         */
 /* consecutive ciphertexts over the whole period, in O(p L0) steps)          */
 /* ------------------------------------------------------------------------ */
 

@@ -643,7 +643,7 @@ class Battery:
             pass
 
 
-# ---- full-period local pattern (Sec. III) ---------------------------------------
+# ---- full-period local pattern (Sec. II, Figs. 3-4) ---------------------------------------
 
 def pattern_spec(n, e, x0, l0, dim, bins, s_lo=1, s_hi=None):
     """phprng_pattern for a width-32 instance; s_hi defaults to p (the full period)."""

@@ -1,4 +1,4 @@
-// Full-period local pattern analysis of Sec. III on gfx950: the histogram of
+// Full-period local pattern analysis of Sec. II, Figs. 3-4 on gfx950: the histogram of
 // the D-1 ciphertexts that follow every first point of a window, over every
 // skip of the period, and its chi-square against the uniform model.
 //

@@ -1,4 +1,4 @@
-"""GPU parity of the full-period local pattern analysis (Sec. III) against the
+"""GPU parity of the full-period local pattern analysis (Sec. II, Figs. 3-4) against the
 CPU oracle: histograms bit for bit, chi^2 and P to floating tolerance, the
 full skip range checked through additivity and totals."""
 

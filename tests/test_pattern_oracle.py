@@ -1,4 +1,4 @@
-"""Pins of the full-period local pattern oracle (Sec. III): the O(p L0)
+"""Pins of the full-period local pattern oracle (Sec. II, Figs. 3-4): the O(p L0)
 enumeration equals the histogram of every window of D consecutive ciphertexts
 over one whole period generated step by step (tiny instances), plus counting
 identities of the cell widths and totals."""
