@@ -239,7 +239,7 @@ __device__ __forceinline__ uint32_t tile_len64(const ReqRec &R, uint32_t j) {
   return j + 1 == R.ntiles ? last : (uint32_t)kTile64;
 }
 
-// One wave per reduce unit (grid-stride): up to kReduceTiles consecutive
+// One wave per reduce unit (grid-stride): up to hdr->reduce_tiles consecutive
 // tiles of one width-64 request.  For each tile j of a request starting at
 // skip log t it writes the skip before the tile, a^{t + 1024 j} mod p (a
 // power for the unit's first tile, then carried from tile to tile), and the
@@ -249,6 +249,7 @@ __global__ void __launch_bounds__(256) reduce64_kernel(GenArgs A) {
   const uint32_t wave = dev::uniform_u32(threadIdx.x / 64);
   const uint64_t units = dev::uniform_u64(dev::const_load(&A.hdr->units64));
   const uint64_t nreq64 = dev::uniform_u64(dev::const_load(&A.hdr->nreq64));
+  const uint32_t rt = dev::uniform_u32((uint32_t)dev::const_load(&A.hdr->reduce_tiles));
   const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / 64);
   const uint64_t lane_mul = A.lanemul->m64[lane];
   const uint64_t pm1 = kP64 - 1;
@@ -257,8 +258,8 @@ __global__ void __launch_bounds__(256) reduce64_kernel(GenArgs A) {
         dev::uniform_u64(wave_search(nreq64, u, lane, [&](uint64_t i) { return A.req[i].rbase; }));
     const ReqRec R = dev::const_load(A.req + r);
     const uint64_t n = dev::const_load(&A.inst[R.inst].n);
-    const uint32_t j0 = (uint32_t)(u - R.rbase) * kReduceTiles;
-    const uint32_t j1 = R.ntiles - j0 > (uint32_t)kReduceTiles ? j0 + (uint32_t)kReduceTiles : R.ntiles;
+    const uint32_t j0 = (uint32_t)(u - R.rbase) * rt;
+    const uint32_t j1 = R.ntiles - j0 > rt ? j0 + rt : R.ntiles;
     uint64_t lg = R.x + (uint64_t)j0 * kTile64;  // x < p - 1 and j * 1024 < 2^42: one subtraction wraps it
     if (lg >= pm1) lg -= pm1;
     uint64_t s_tile = dev::wave_pow_p61(A.lanemul->pow64, lg, lane);

@@ -41,7 +41,7 @@ hipError_t launch_position64(const InstRec *inst, const uint32_t *ids, const uin
                              const uint64_t *tb, uint64_t count, const uint64_t *u_lo, const uint64_t *u_hi,
                              const uint64_t *u_s, uint64_t *m64, hipStream_t st);
 // Width-64 tile starts of a batch: the reduce writes each tile's start skip
-// and skip sum (hdr->units64 units of up to kReduceTiles tiles, grid-stride
+// and skip sum (hdr->units64 units of hdr->reduce_tiles tiles, grid-stride
 // with at most max_blocks blocks); the scan turns the sums into tile-start
 // messages per instance and commits the instances' messages (one workgroup
 // per width-64 request).

@@ -28,7 +28,7 @@ constexpr uint64_t kTilesPerPeriod32 = ((uint64_t)kP32 - 1 + kTile32 - 1) / kTil
 constexpr int kRun64 = 16;
 constexpr int kTile64 = 64 * kRun64;  // 1024 draws
 // The width-64 reduce takes up to this many consecutive tiles of a request
-// per wave.
+// per wave (fewer when the batch is too small to keep every wave busy).
 constexpr int kReduceTiles = 16;
 // Constant-skip tiles (both widths): 2048 draws aligned to multiples of 2048.
 constexpr int kTileCS = 2048;
@@ -81,7 +81,7 @@ struct alignas(64) ReqRec {
   uint32_t nchunks;     // chunks of this request
   uint32_t seg;         // width 64 pseudorandom skip: number of consecutive requests of this instance
                         // starting here (0 for a request that is not the first of its instance)
-  uint64_t rbase;       // width 64 pseudorandom skip: first reduce unit (kReduceTiles tiles) of this request
+  uint64_t rbase;       // width 64 pseudorandom skip: first reduce unit of this request
 };
 static_assert(sizeof(ReqRec) == 64, "ReqRec must be 64 bytes");
 
@@ -93,7 +93,8 @@ struct alignas(64) BatchHdr {
   uint64_t nreq64;        // width-64 pseudorandom-skip requests (the first nreq64)
   uint64_t tiles64;       // their tiles (entries of the tile-state arrays)
   uint64_t units64;       // their reduce units
-  uint64_t pad[3];
+  uint64_t reduce_tiles;  // tiles per reduce unit (1 .. kReduceTiles)
+  uint64_t pad[2];
 };
 static_assert(sizeof(BatchHdr) == 64, "BatchHdr must be 64 bytes");
 

@@ -74,6 +74,10 @@ constexpr uint64_t kDirectRequests = 1024;
 constexpr uint64_t kPlanReserve = 16384;
 static_assert(kNoAllocMaxRequests <= kPlanReserve, "allocation-free calls plan without growing a vector");
 
+// The width-64 reduce shrinks its units until a batch has this many of them
+// (its grid holds 2048 four-wave blocks).
+constexpr uint64_t kReduceWaves = 8192;
+
 // Width-64 draws per request: tiles are counted in 32 bits.
 constexpr uint64_t kMaxCount64 = (uint64_t)kTile64 << 32;
 // Width-64 jumps off the positioning table sum the skips on the device; the
@@ -132,7 +136,8 @@ struct Plan {
   uint64_t nreq = 0;
   uint64_t nreq64 = 0;   // width-64 pseudorandom-skip requests (first in the staging order)
   uint64_t tiles64 = 0;  // their tiles
-  uint64_t units64 = 0;  // their reduce units (kReduceTiles tiles of one request)
+  uint64_t units64 = 0;  // their reduce units (reduce_tiles tiles of one request)
+  uint32_t reduce_tiles = kReduceTiles;
   uint64_t tiles = 0;    // all tiles
   uint64_t total_chunks = 0;
   uint32_t tpc = 1;
@@ -619,8 +624,7 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
       nt = (q.count + kTile64 - 1) / kTile64;
       rr.g1 = tiles64;
       tiles64 += nt;
-      rr.rbase = units64;
-      units64 += (nt + kReduceTiles - 1) / kReduceTiles;
+
       rr.seg = p == seg_start[t] ? seg_count[t] : 0;
     } else if (h.sched == kSchedConstant) {
       rr.g1 = rr.x / kTileCS;
@@ -637,8 +641,17 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   Plan out;
   out.nreq = nreq;
   out.nreq64 = c64l;
+  // width-64 reduce units: up to kReduceTiles tiles each, fewer when the
+  // batch would leave most of the reduce grid idle
+  uint32_t rt = kReduceTiles;
+  while (rt > 1 && tiles64 < (uint64_t)rt * kReduceWaves) rt >>= 1;
+  for (uint64_t p = 0; p < c64l; ++p) {
+    R[p].rbase = units64;
+    units64 += ((uint64_t)R[p].ntiles + rt - 1) / rt;
+  }
   out.tiles64 = tiles64;
   out.units64 = units64;
+  out.reduce_tiles = rt;
   out.tiles = tiles;
   out.has64 = c64l + c64c > 0;
   out.has32 = c32 > 0;
@@ -672,6 +685,7 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   H->nreq64 = c64l;
   H->tiles64 = tiles64;
   H->units64 = units64;
+  H->reduce_tiles = rt;
   *P = out;
   return PHPRNG_OK;
 }

@@ -614,3 +614,41 @@ def test_graph_replays_interleaved_with_other_calls(ph, ctx, orc, tabs):
         assert ctx.get_state(iid)[3] == expect[iid][3]
         assert ctx.get_state(iid)[:2] == expect[iid][:2]
     g.close()
+
+
+@pytest.mark.parametrize("tiles", [3000, 20000, 45000])
+def test_64bit_reduce_unit_sizes(ph, orc, tiles):
+    """Width-64 batches whose tile totals make the reduce take units of 1, 2
+    and 4 tiles (a batch takes the largest unit, up to 16 tiles, that still
+    leaves 8192 units): ragged requests from arbitrary (m0, s0), eight
+    instances asked twice in the batch (the second request continues the
+    first), every draw compared with the oracle's stream."""
+    rng = np.random.default_rng(SEED0 + 1700 + tiles)
+    p, a = orc.lcg_params(64)
+    ninst = 24
+    n, e, _ = orc.seed(64, SEED0 + 1700 + tiles, ninst, (9, 17))
+    n = [int(x) for x in n]
+    m0 = [int(rng.integers(0, x)) for x in n]
+    s0 = [int(rng.integers(2, p)) for _ in range(ninst)]
+    c = ph.Context(0, max_instances=ninst)
+    ids = [int(x) for x in c.add_instances(64, n, [int(x) for x in e], m0=m0, s0=s0)]
+    inst_of_req = list(range(ninst)) + list(range(8))
+    avg = tiles * 1024 // len(inst_of_req)
+    counts = [int(x) for x in rng.integers(1, 2 * avg, len(inst_of_req))]
+    counts[:4] = [1, 1023, 1024, 1025]
+    specs = [(ids[i], cnt) for i, cnt in zip(inst_of_req, counts)]
+    (_, hc64, hr), offs = _run(ph, c, specs, want=(False, True, True))
+    per_inst = [0] * ninst
+    for i, cnt in zip(inst_of_req, counts):
+        per_inst[i] += cnt
+    wc, wr, _, _, woff = orc.generate_many(p, a, np.array(n, dtype=np.uint64), np.array(e, dtype=np.uint64),
+                                           np.array(m0, dtype=np.uint64), np.array(s0, dtype=np.uint64),
+                                           np.array(per_inst, dtype=np.uint64))
+    done = [0] * ninst
+    for (iid, cnt), i, off in zip(specs, inst_of_req, offs):
+        o = int(woff[i]) + done[i]
+        compare_request(hc64, hr, off, cnt, wc[o:o + cnt], wr[o:o + cnt], "w64 reduce units, instance %d" % i)
+        done[i] += cnt
+    for i in range(ninst):
+        assert c.get_position(ids[i]) == per_inst[i]
+    c.close()
