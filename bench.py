@@ -52,6 +52,7 @@ ALU_PEAK_OPS = CUS * 64 * CLOCK_HZ  # one wave64 VALU instruction per CU per clo
 KERNEL_SOURCES = ["paper_1411_2484_amd/csrc/kernels.hip", "paper_1411_2484_amd/csrc/arith.hpp",
                   "paper_1411_2484_amd/csrc/layout.hpp"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "gen_persistent_counters.json")
+COUNTERS_FILE_W64 = os.path.join(ROOT, "profiles", "gen_width64_counters.json")
 
 
 def log(msg):
@@ -66,11 +67,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def committed_counters():
-    """Per-launch counter figures of the headline kernel from the committed
-    rocprofv3 runs, when they were taken on the current kernel sources."""
+def committed_counters(path=COUNTERS_FILE):
+    """Per-launch counter figures (headline kernel, or the width-64 path) from
+    the committed rocprofv3 runs, when they were taken on the current kernel
+    sources."""
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -393,6 +395,14 @@ def section_d(args, torch, ph, out):
         draws = len(ids) * per
         res[name] = {"value": draws / (ms * 1e-3) / 1e9, "ms_per_step": ms, "kernel_ms": kms,
                      "roofline": roofline(draws, kms, ops, bpd)}
+        cnt = committed_counters(COUNTERS_FILE_W64) if name == "w64_only" else None
+        if cnt and cnt.get("valu_insts_per_launch"):
+            # reduce + scan + generation instructions of this launch against
+            # the time of all three (HIP events around the call's kernels)
+            alu = res[name]["roofline"]["alu"]
+            alu["issued_valu_frac"] = cnt["valu_insts_per_launch"] * 64 / (kms * 1e-3) / ALU_PEAK_OPS
+            if cnt.get("valu_seconds_per_inst"):
+                alu["cycle_weighted_frac"] = cnt["valu_insts_per_launch"] * cnt["valu_seconds_per_inst"] / (kms * 1e-3)
         log("D %s: %s" % (name, res[name]))
     del c32, c64, r
     ctx.close()
