@@ -80,8 +80,9 @@ typedef struct {
 typedef struct {
   int32_t block_threads;   /* 64, 128, 256 or 512 */
   int32_t blocks_per_cu;   /* resident blocks per compute unit for the persistent grid */
-  int32_t tiles_per_chunk; /* consecutive 2048-draw tiles a wave takes per work grab (1..64);
-                              halved for batches too small to give every wave 4 grabs */
+  int32_t tiles_per_chunk; /* consecutive tiles a wave takes per work grab (1..64; a tile is
+                              2048 draws at width 32 and for constant skips, 1024 draws at
+                              width 64); halved for batches too small to give every wave 4 grabs */
   int32_t unroll;          /* encryption-loop unroll: 1, 2 or 4 */
 } phprng_tuning;
 
@@ -272,8 +273,9 @@ phprng_status phprng_graph_destroy(phprng_graph *graph);
 
 /* Kernel time of the last phprng_generate / phprng_graph_launch call on the
  * context, in milliseconds, measured with HIP events recorded on its stream
- * right before and after the generation kernel(s); waits for that stream.
- * PLAIN mode reports the span of all its launches. */
+ * right before and after the call's kernels (for width-64 requests the
+ * tile-start reduce and scan, then the generation kernel or kernels); waits
+ * for that stream.  PLAIN mode reports the span of all its launches. */
 phprng_status phprng_last_kernel_ms(phprng_ctx *ctx, double *ms);
 
 /* Cumulative generation-kernel time (same events as above) and number of
