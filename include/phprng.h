@@ -118,7 +118,7 @@ const char *phprng_status_string(phprng_status st);
 /* Create a context on HIP device `device` with room for max_instances
  * instances (device records of 128 bytes each).  Builds the universal
  * 32-bit skip-prefix table of eq. (7b) on the device (12 MB); the 64-bit
- * table (200 MB) is built when the first width-64 instance is added.
+ * table (400 MB) is built when the first width-64 instance is added.
  * *ctx receives the context; the caller owns it and frees it with
  * phprng_destroy. */
 phprng_status phprng_create(phprng_ctx **ctx, int device, uint64_t max_instances);

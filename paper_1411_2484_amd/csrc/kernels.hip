@@ -64,10 +64,10 @@ __global__ void __launch_bounds__(256) table_segments64(uint64_t nseg, uint64_t 
                                                         uint64_t *seg_start) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nseg) return;
-  uint64_t s = dev::powmod_p61(kA64, i * kTableStride);
+  uint64_t s = dev::powmod_p61(kA64, i * kTab64Stride);
   seg_start[i] = s;
   uint64_t lo = 0, hi = 0;
-  for (uint64_t j = 0; j < kTableStride; ++j) {
+  for (uint64_t j = 0; j < kTab64Stride; ++j) {
     s = dev::mulmod_p61(kA64, s);
     uint64_t t = lo + s;
     hi += (t < lo) ? 1 : 0;
@@ -154,12 +154,13 @@ __global__ void __launch_bounds__(256) build_records(const uint64_t *n_arr, cons
 // ---------------------------------------------------------------------------
 
 // U(t) mod n for t < kTab64Range: the table entry at or below t plus at most
-// 2047 steps of the skip generator, then the 128-bit sum reduced mod n.
+// kTab64Stride - 1 steps of the skip generator, then the 128-bit sum reduced
+// mod n.
 __device__ uint64_t table_prefix64(const uint64_t *u_lo, const uint64_t *u_hi, const uint64_t *u_s, uint64_t t,
                                    uint64_t n, uint64_t ninv, uint64_t r2) {
-  const uint64_t i = t / kTableStride;
+  const uint64_t i = t / kTab64Stride;
   uint64_t lo = u_lo[i], hi = u_hi[i], s = u_s[i];
-  for (uint64_t x = i * kTableStride; x < t; ++x) {
+  for (uint64_t x = i * kTab64Stride; x < t; ++x) {
     s = dev::mulmod_p61(kA64, s);
     const uint64_t v = lo + s;
     hi += v < lo ? 1 : 0;
@@ -234,8 +235,9 @@ __device__ __forceinline__ uint64_t tile_skip_sum64(uint64_t s_tile, uint64_t la
 // "rem < 1024 ? rem : 1024" has been compiled for gfx950 into a select that
 // reads a stale SCC after the branch on the same comparison, which gave 1024
 // for every last tile.
-__device__ __forceinline__ uint32_t tile_len64(const ReqRec &R, uint32_t j) {
-  const uint32_t last = (uint32_t)(R.count - (uint64_t)(R.ntiles - 1) * kTile64);
+__device__ __forceinline__ uint32_t tile_len64(const ReqRec &R, uint32_t j, uint32_t head = 0) {
+  // one past the request's last draw, counted from the first tile's start
+  const uint32_t last = (uint32_t)(R.count + head - (uint64_t)(R.ntiles - 1) * kTile64);
   return j + 1 == R.ntiles ? last : (uint32_t)kTile64;
 }
 
@@ -301,6 +303,70 @@ __global__ void __launch_bounds__(256) reduce64_kernel(GenArgs A) {
       s_tile = dev::shfl_u64(s, 63);  // the skip after the tile's last draw
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// width-64 tile starts from the table (batches whose draws all lie below
+// kTab64Range)
+// ---------------------------------------------------------------------------
+
+// Table entry i of U reduced mod n: U(i * kTab64Stride) < 2^95 < n 2^64, so
+// one REDC and a product with R^2 give it.
+__device__ __forceinline__ uint64_t table_entry_mod64(const SkipTables &T, uint64_t i, uint64_t n, uint64_t ninv,
+                                                      uint64_t r2) {
+  dev::W128 w;
+  w.lo = dev::const_load(T.u64lo + i);
+  w.hi = dev::const_load(T.u64hi + i);
+  return dev::mont64(dev::redc64(w, n, ninv), r2, n, ninv);
+}
+
+// U(x) mod n for x < kTab64Range by the whole wave: the entry at or below x
+// plus the (at most kTab64Stride - 1) skips after it, lane l taking the 16
+// skip indices from T + 16 l + 1.  Every lane gets the result.
+__device__ uint64_t wave_prefix64(const SkipTables &T, uint64_t x, uint64_t n, uint64_t ninv, uint64_t r2,
+                                  uint64_t lane_mul, uint32_t lane) {
+  const uint64_t i = x / kTab64Stride;
+  const uint32_t rem = (uint32_t)(x - i * kTab64Stride);
+  uint64_t s = dev::mulmod_p61(dev::const_load(T.s64 + i), lane_mul);
+  uint64_t sum = 0;
+  const uint32_t first = lane * kRun64;
+#pragma unroll 4
+  for (int k = 0; k < kRun64; ++k) {
+    s = dev::mulmod_p61(kA64, s);
+    if (first + (uint32_t)k < rem) sum = dev::addmod64(sum, s, n);
+  }
+  return dev::addmod64(table_entry_mod64(T, i, n, ninv, r2), dev::wave_sum_mod(sum, n), n);
+}
+
+// One wave per width-64 request; the first request of each instance in the
+// batch (seg > 0) serves all of that instance's requests.  With m the
+// instance's committed message at skip log x (its first request's start),
+// mbase = m - U(x) mod n gives the message at any skip log t of the range as
+// mbase + U(t) (eq. (7b)).  Each tile of the requests starts at a table
+// entry, so its skip a^t and message come straight from the table.  The
+// wave then commits the message after the instance's last draw in the batch.
+__global__ void __launch_bounds__(64) tab64_kernel(GenArgs A) {
+  const uint32_t lane = dev::lane_id();
+  const ReqRec R0 = dev::const_load(A.req + blockIdx.x);
+  if (R0.seg == 0) return;
+  const InstRec &I = A.inst[R0.inst];
+  const uint64_t n = dev::const_load(&I.n), ninv = dev::const_load(&I.ninv), r2 = dev::const_load(&I.r2);
+  const uint64_t lane_mul = A.lanemul->m64[lane];
+  const uint64_t m0 = dev::uniform_u64(A.m64[R0.inst]);
+  const uint64_t u0 = wave_prefix64(A.tab, R0.x, n, ninv, r2, lane_mul, lane);
+  const uint64_t mbase = m0 >= u0 ? m0 - u0 : m0 + (n - u0);
+  for (uint32_t q = 0; q < R0.seg; ++q) {
+    const ReqRec R = dev::const_load(A.req + blockIdx.x + q);
+    const uint64_t e0 = R.x / kTab64Stride;
+    for (uint32_t j = lane; j < R.ntiles; j += 64) {
+      const uint64_t e = e0 + j;
+      A.t64.s[R.g1 + j] = dev::const_load(A.tab.s64 + e);
+      A.t64.m[R.g1 + j] = dev::addmod64(mbase, table_entry_mod64(A.tab, e, n, ninv, r2), n);
+    }
+  }
+  const ReqRec RL = dev::const_load(A.req + blockIdx.x + R0.seg - 1);
+  const uint64_t ue = wave_prefix64(A.tab, RL.x + RL.count, n, ninv, r2, lane_mul, lane);
+  if (lane == 0) A.m64[R0.inst] = dev::addmod64(mbase, ue, n);
 }
 
 // Scan per instance: one workgroup per width-64 request; the first request
@@ -531,15 +597,16 @@ struct Enc64 {
 };
 
 // Pass C, width 64: draw t = i*64 + lane lives at LDS row t / 16, column
-// t % 16, i.e. row 4 i + lane / 16.  MASKED tiles write only t < t_hi.
+// t % 16, i.e. row 4 i + lane / 16.  MASKED tiles write only t_lo <= t < t_hi.
 template <int UNROLL, int EK, int OUT, bool MASKED>
 __device__ __forceinline__ void passC64(const uint64_t *L, uint32_t lane, const Enc64 &K, uint64_t *c64, double *rr,
-                                        uint32_t t_hi) {
+                                        uint32_t t_lo, uint32_t t_hi) {
   const uint64_t *src = L + (lane >> 4) * kRow64 + (lane & 15);
+  const uint32_t span = t_hi - t_lo;
 #pragma unroll UNROLL
   for (int i = 0; i < kRun64; ++i) {
     const uint64_t m = src[i * 4 * kRow64];
-    if (!MASKED || ((uint32_t)i * 64u + lane < t_hi)) {
+    if (!MASKED || ((uint32_t)i * 64u + lane - t_lo < span)) {
       const uint64_t c = dev::encrypt64<EK>(m, K.n, K.ninv, K.kc, K.e, K.ebits);
       if (OUT & kOutC) c64[i * 64] = c;
       if (OUT & kOutR) rr[i * 64] = dev::uniform64(c, K.den, K.rcp);
@@ -549,27 +616,30 @@ __device__ __forceinline__ void passC64(const uint64_t *L, uint32_t lane, const 
 
 template <int UNROLL, int EK, bool MASKED>
 __device__ __forceinline__ void passC64_out(const uint64_t *L, uint32_t lane, const Enc64 &K, uint64_t *c64,
-                                            double *rr, uint32_t t_hi) {
-  if (c64 && rr) passC64<UNROLL, EK, kOutC | kOutR, MASKED>(L, lane, K, c64, rr, t_hi);
-  else if (rr) passC64<UNROLL, EK, kOutR, MASKED>(L, lane, K, c64, rr, t_hi);
-  else if (c64) passC64<UNROLL, EK, kOutC, MASKED>(L, lane, K, c64, rr, t_hi);
+                                            double *rr, uint32_t t_lo, uint32_t t_hi) {
+  if (c64 && rr) passC64<UNROLL, EK, kOutC | kOutR, MASKED>(L, lane, K, c64, rr, t_lo, t_hi);
+  else if (rr) passC64<UNROLL, EK, kOutR, MASKED>(L, lane, K, c64, rr, t_lo, t_hi);
+  else if (c64) passC64<UNROLL, EK, kOutC, MASKED>(L, lane, K, c64, rr, t_lo, t_hi);
 }
 
 template <int UNROLL, bool MASKED>
 __device__ __forceinline__ void passC64_e(int ekind, const uint64_t *L, uint32_t lane, const Enc64 &K, uint64_t *c64,
-                                          double *rr, uint32_t t_hi) {
+                                          double *rr, uint32_t t_lo, uint32_t t_hi) {
   switch (ekind) {
-    case 9: passC64_out<UNROLL, 9, MASKED>(L, lane, K, c64, rr, t_hi); break;
-    case 17: passC64_out<UNROLL, 17, MASKED>(L, lane, K, c64, rr, t_hi); break;
-    case 3: passC64_out<UNROLL, 3, MASKED>(L, lane, K, c64, rr, t_hi); break;
-    case 5: passC64_out<UNROLL, 5, MASKED>(L, lane, K, c64, rr, t_hi); break;
-    default: passC64_out<UNROLL, 0, MASKED>(L, lane, K, c64, rr, t_hi); break;
+    case 9: passC64_out<UNROLL, 9, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
+    case 17: passC64_out<UNROLL, 17, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
+    case 3: passC64_out<UNROLL, 3, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
+    case 5: passC64_out<UNROLL, 5, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
+    default: passC64_out<UNROLL, 0, MASKED>(L, lane, K, c64, rr, t_lo, t_hi); break;
   }
 }
 
-// Width 64: tile j of the request covers its draws [1024 j, 1024 (j + 1));
-// the state before the chunk's first tile comes from the scan, later tiles
-// continue from lane 63's last state.
+// Width 64: tile j of the request covers its draws [1024 j, 1024 (j + 1)),
+// or, when the batch's tiles start at table entries, the skip logarithms
+// (1024 (e0 + j), 1024 (e0 + j + 1)] with e0 = x / 1024, of which the first
+// tile skips the part before the request.  The state before the chunk's
+// first tile comes from the scan or the table kernel; later tiles continue
+// from lane 63's last state.
 template <int UNROLL>
 __device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R, uint64_t chunk, uint64_t *L,
                             uint32_t lane) {
@@ -581,6 +651,10 @@ __device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R,
 
   const uint32_t j_begin = (uint32_t)chunk * A.tiles_per_chunk;
   const uint32_t j_end = min(j_begin + A.tiles_per_chunk, R.ntiles);
+  const bool tab = dev::uniform_u32((uint32_t)dev::const_load(&A.hdr->tab64)) != 0;
+  // draw t of tile j is request draw (first draw of tile j) + t; at table
+  // entries the first tile starts x mod 1024 draws before the request
+  const uint32_t head = tab ? (uint32_t)(R.x & (kTab64Stride - 1)) : 0u;
   uint64_t m_t = dev::uniform_u64(dev::const_load(A.t64.m + R.g1 + j_begin));
   uint64_t s_t = dev::uniform_u64(dev::const_load(A.t64.s + R.g1 + j_begin));
   for (uint32_t j = j_begin; j < j_end; ++j) {
@@ -613,15 +687,16 @@ __device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R,
     s_t = dev::shfl_u64(s, 63);
     dev::wave_lds_sync();
     // ---- pass C
-    const uint32_t t_hi = tile_len64(R, j);
-    const uint64_t base = R.out_off + (uint64_t)j * kTile64 + lane;
+    const uint32_t t_lo = j == 0 ? head : 0u;
+    const uint32_t t_hi = tile_len64(R, j, head);
+    const int64_t base = (int64_t)R.out_off + (int64_t)j * kTile64 - (int64_t)head + (int64_t)lane;
     uint64_t *c64 = A.out_c64 ? A.out_c64 + base : nullptr;
     double *rr = A.out_r ? A.out_r + base : nullptr;
     const Enc64 K{n, ninv, kc, e, ebits, den, I.rcp};
-    if (t_hi == (uint32_t)kTile64)
-      passC64_e<UNROLL, false>(ekind, L, lane, K, c64, rr, t_hi);
+    if (t_lo == 0 && t_hi == (uint32_t)kTile64)
+      passC64_e<UNROLL, false>(ekind, L, lane, K, c64, rr, 0u, t_hi);
     else
-      passC64_e<1, true>(ekind, L, lane, K, c64, rr, t_hi);
+      passC64_e<1, true>(ekind, L, lane, K, c64, rr, t_lo, t_hi);
     dev::wave_lds_sync();
   }
 }
@@ -907,6 +982,14 @@ hipError_t launch_tiles64_reduce(const GenArgs &A, uint64_t units64, unsigned ma
   const uint64_t want = (units64 + 3) / 4;
   const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, max_blocks));
   hipLaunchKernelGGL(reduce64_kernel, dim3(blocks), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_tiles64_table(const GenArgs &A, uint64_t nreq64, hipStream_t st) {
+  clear_launch_error();
+  if (nreq64 == 0) return hipSuccess;
+  if (nreq64 > 0x7fffffffull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tab64_kernel, dim3((unsigned)nreq64), dim3(64), 0, st, A);
   return hipGetLastError();
 }
 

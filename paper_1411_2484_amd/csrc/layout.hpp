@@ -32,8 +32,11 @@ constexpr int kTile64 = 64 * kRun64;  // 1024 draws
 constexpr int kReduceTiles = 16;
 // Constant-skip tiles (both widths): 2048 draws aligned to multiples of 2048.
 constexpr int kTileCS = 2048;
-// The width-64 skip-prefix table (positioning and jumps only) covers skip
-// logarithms below this bound.
+// The width-64 skip-prefix table covers skip logarithms below kTab64Range
+// with an entry every kTab64Stride: it positions instances, serves jumps,
+// and gives the tile starts of batches whose width-64 draws all lie in its
+// range (tiles then start at entries, like width-32 tiles).
+constexpr uint64_t kTab64Stride = kTile64;
 constexpr uint64_t kTab64Range = 1ull << 34;
 
 // Device instance record (one 128-byte line).  All modular constants are
@@ -75,6 +78,7 @@ struct alignas(64) ReqRec {
   uint64_t out_off;     // output element offset
   uint64_t g1;          // width 32: global tile of the first draw (q * tiles per period + j);
                         // constant skip: x / kTileCS; width 64: first entry in the batch's tile-state arrays
+                        // (its tiles start at x + 1024 j, or at table entries when the batch's tab64 is set)
   uint64_t chunk_base;  // first chunk of this request in the batch
   uint32_t inst;        // instance id
   uint32_t ntiles;      // tiles touched
@@ -94,7 +98,8 @@ struct alignas(64) BatchHdr {
   uint64_t tiles64;       // their tiles (entries of the tile-state arrays)
   uint64_t units64;       // their reduce units
   uint64_t reduce_tiles;  // tiles per reduce unit (1 .. kReduceTiles)
-  uint64_t pad[2];
+  uint64_t tab64;         // 1: width-64 tiles start at table entries (all draws below kTab64Range)
+  uint64_t pad;
 };
 static_assert(sizeof(BatchHdr) == 64, "BatchHdr must be 64 bytes");
 
@@ -115,10 +120,13 @@ struct Tile64 {
 
 // Universal width-32 skip-prefix table: entry i holds U(i * stride) =
 // sum_{j=1}^{i*stride} (a^j mod p) and S(i * stride) = a^{i*stride} mod p.
+// The width-64 table holds the same below kTab64Range (U as 128 bits).
 struct SkipTables {
   const uint64_t *u32;  // U (< 2^62)
   const uint32_t *s32;  // S
   uint64_t n32;         // entries
+  const uint64_t *u64lo, *u64hi;  // width 64: U, low and high words
+  const uint64_t *s64;            // width 64: S
 };
 
 // Per-lane and per-tile skip multipliers.

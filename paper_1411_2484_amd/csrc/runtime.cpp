@@ -138,6 +138,7 @@ struct Plan {
   uint64_t tiles64 = 0;  // their tiles
   uint64_t units64 = 0;  // their reduce units (reduce_tiles tiles of one request)
   uint32_t reduce_tiles = kReduceTiles;
+  bool tab64 = false;    // width-64 tile starts from the table (tiles at table entries)
   uint64_t tiles = 0;    // all tiles
   uint64_t total_chunks = 0;
   uint32_t tpc = 1;
@@ -398,7 +399,7 @@ struct phprng_ctx {
   phprng_status build_table32();
   phprng_status build_table64();
   phprng_status plan(const phprng_request *reqs, uint64_t nreq, uint64_t capacity, int mode, const uint32_t *tpc_fix,
-                     uint64_t stage_cap, uint8_t *stage, Plan *P);
+                     uint64_t stage_cap, uint8_t *stage, Plan *P, bool allow_tab64 = true);
   void commit_plan();
   GenArgs args(const uint8_t *d_blk, WorkCtr *ctr, uint64_t *t64, uint64_t t64cap, uint64_t nreq, uint32_t *c32,
                uint64_t *c64, double *r, uint32_t tpc) const;
@@ -451,7 +452,7 @@ phprng_status phprng_ctx::build_table32() {
 
 phprng_status phprng_ctx::build_table64() {
   if (have64) return PHPRNG_OK;
-  const uint64_t ne = kTab64Range / kTableStride;
+  const uint64_t ne = kTab64Range / kTab64Stride;
   uint64_t *d_lo = nullptr, *d_hi = nullptr, *d_start = nullptr;
   hipError_t e;
   if ((e = hipMalloc(&d_lo, ne * 8)) != hipSuccess) return fail(PHPRNG_E_NOMEM, "table64 alloc");
@@ -490,11 +491,11 @@ phprng_status phprng_ctx::build_table64() {
   for (uint64_t i : {(uint64_t)1, ne / 3, ne - 1}) {
     u128 v = u[i - 1];
     uint64_t s = s64[i - 1];
-    for (uint64_t x = 0; x < kTableStride; ++x) {
+    for (uint64_t x = 0; x < kTab64Stride; ++x) {
       s = G.mulmod(G.a, s);
       v += s;
     }
-    if (v != u[i] || s != s64[i] || s != G.powmod(G.a, i * kTableStride))
+    if (v != u[i] || s != s64[i] || s != G.powmod(G.a, i * kTab64Stride))
       return give_up(fail(PHPRNG_E_DEVICE, "64-bit skip-prefix table failed its check at entry %llu",
                           (unsigned long long)i));
   }
@@ -525,7 +526,8 @@ static inline uint64_t tile_of32(uint64_t x) {
 // been issued.  tpc_fix: tiles per chunk to use as is (graphs), else the
 // tuned value, halved for batches too small to give every wave 4 chunks.
 phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64_t capacity, int mode,
-                               const uint32_t *tpc_fix, uint64_t stage_cap, uint8_t *stage, Plan *P) {
+                               const uint32_t *tpc_fix, uint64_t stage_cap, uint8_t *stage, Plan *P,
+                               bool allow_tab64) {
   if (nreq > 0 && !reqs) return fail(PHPRNG_E_INVALID, "null request array");
   if (nreq > stage_cap) return fail(PHPRNG_E_RANGE, "too many requests for the staging buffer");
   if (nreq >= (1ull << 31)) return fail(PHPRNG_E_RANGE, "too many requests");
@@ -607,6 +609,12 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   // records
   BatchHdr *H = reinterpret_cast<BatchHdr *>(stage);
   ReqRec *R = reinterpret_cast<ReqRec *>(stage + sizeof(BatchHdr));
+  // Width-64 tile starts come from the table when every width-64 draw of the
+  // batch lies below its range (tiles then start at table entries), else
+  // from the reduce and scan of the requests' own skips.
+  bool tab64 = allow_tab64 && have64 && c64l > 0;
+  for (uint64_t i = 0; tab64 && i < nreq; ++i)
+    if (lcg64(inst[reqs[i].instance]) && req_x[i] + reqs[i].count >= kTab64Range) tab64 = false;
   uint64_t tiles = 0, tiles64 = 0, units64 = 0;
   for (uint64_t p = 0; p < nreq; ++p) {
     const uint64_t i = order[p];
@@ -621,7 +629,10 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
     uint64_t nt = 0;
     if (lcg64(h)) {
       const size_t t = (size_t)where[q.instance];
-      nt = (q.count + kTile64 - 1) / kTile64;
+      if (tab64)
+        nt = q.count ? (rr.x + q.count - 1) / kTab64Stride - rr.x / kTab64Stride + 1 : 0;
+      else
+        nt = (q.count + kTile64 - 1) / kTile64;
       rr.g1 = tiles64;
       tiles64 += nt;
 
@@ -652,6 +663,7 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   out.tiles64 = tiles64;
   out.units64 = units64;
   out.reduce_tiles = rt;
+  out.tab64 = tab64;
   out.tiles = tiles;
   out.has64 = c64l + c64c > 0;
   out.has32 = c32 > 0;
@@ -686,6 +698,7 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   H->tiles64 = tiles64;
   H->units64 = units64;
   H->reduce_tiles = rt;
+  H->tab64 = tab64 ? 1 : 0;
   *P = out;
   return PHPRNG_OK;
 }
@@ -707,7 +720,7 @@ GenArgs phprng_ctx::args(const uint8_t *d_blk, WorkCtr *ctr, uint64_t *t64, uint
   A.req = reinterpret_cast<const ReqRec *>(d_blk + sizeof(BatchHdr));
   A.nreq = nreq;
   A.ctr = ctr;
-  A.tab = SkipTables{d_u32, d_s32, (uint64_t)u32.size()};
+  A.tab = SkipTables{d_u32, d_s32, (uint64_t)u32.size(), d_u64lo, d_u64hi, d_s64};
   A.lanemul = d_lanemul;
   A.t64.s = t64;
   A.t64.sum = t64 ? t64 + t64cap : nullptr;
@@ -725,10 +738,11 @@ GenArgs phprng_ctx::args(const uint8_t *d_blk, WorkCtr *ctr, uint64_t *t64, uint
 phprng_status phprng_ctx::launch(const Plan &P, const GenArgs &A, const ReqRec *hreq, hipStream_t s, int mode) {
   hipError_t e;
   if (P.nreq64 > 0) {
-    if ((e = launch_tiles64_reduce(A, P.units64, (unsigned)num_cus * 8, s)) != hipSuccess)
+    if (!P.tab64 && (e = launch_tiles64_reduce(A, P.units64, (unsigned)num_cus * 8, s)) != hipSuccess)
       return hip_fail(e, "tile reduce");
     if (chain_pending && (e = hipStreamWaitEvent(s, chain_ev, 0)) != hipSuccess) return hip_fail(e, "chain wait");
-    if ((e = launch_tiles64_scan(A, P.nreq64, s)) != hipSuccess) return hip_fail(e, "tile scan");
+    e = P.tab64 ? launch_tiles64_table(A, P.nreq64, s) : launch_tiles64_scan(A, P.nreq64, s);
+    if (e != hipSuccess) return hip_fail(e, "tile starts");
     if ((e = hipEventRecord(chain_ev, s)) != hipSuccess) return hip_fail(e, "chain record");
     chain_pending = true;
   }
@@ -1671,7 +1685,8 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
   phprng_status st = c->take_slot(nreq, &slot);
   if (st != PHPRNG_OK) return st;
   Plan P;
-  st = c->plan(reqs, nreq, capacity, PHPRNG_MODE_PERSISTENT, nullptr, slot->cap, slot->h_blk, &P);
+  // graphs keep the reduce-and-scan tile starts, which hold at any position
+  st = c->plan(reqs, nreq, capacity, PHPRNG_MODE_PERSISTENT, nullptr, slot->cap, slot->h_blk, &P, false);
   if (st != PHPRNG_OK) return st;
   std::unique_ptr<phprng_graph> g(new (std::nothrow) phprng_graph);
   if (!g) return PHPRNG_E_NOMEM;
@@ -1719,7 +1734,7 @@ extern "C" phprng_status phprng_graph_launch(phprng_graph *g, void *stream) {
   // the last launch (generate, jump, set_state)
   Plan P;
   uint64_t capacity = ~0ull;
-  st = c->plan(g->reqs.data(), nreq, capacity, PHPRNG_MODE_PERSISTENT, &g->tpc, slot->cap, slot->h_blk, &P);
+  st = c->plan(g->reqs.data(), nreq, capacity, PHPRNG_MODE_PERSISTENT, &g->tpc, slot->cap, slot->h_blk, &P, false);
   if (st != PHPRNG_OK) return st;
   if (P.nreq64 != g->nreq64 || P.tiles64 != g->tiles64)
     return c->fail(PHPRNG_E_INVALID, "graph requests no longer match their instances");

@@ -652,3 +652,53 @@ def test_64bit_reduce_unit_sizes(ph, orc, tiles):
     for i in range(ninst):
         assert c.get_position(ids[i]) == per_inst[i]
     c.close()
+
+
+def test_64bit_table_tile_starts_and_mode_changes(ph, orc):
+    """Width-64 batches whose draws all lie below the table's range take
+    their tile starts from the table (tiles at multiples of 1024 skip
+    logarithms, the first one entered part-way); a batch with one request
+    that crosses the range end takes the reduce and scan for all of its
+    width-64 requests.  Instances start at aligned and unaligned skip
+    logarithms, one of them twice in a batch, one request is empty, one ends
+    one draw before the range end; four batches switch between the two modes
+    and every draw is compared with the oracle's continuing stream."""
+    rng = np.random.default_rng(SEED0 + 1800)
+    p, a = orc.lcg_params(64)
+    n64, e64, _ = orc.seed(64, SEED0 + 1800, 7, (9, 17))
+    n64 = [int(x) for x in n64]
+    e64 = [int(x) for x in e64]
+    top = 1 << 34
+    logs = [0, 1, 1023, 1024, 12345, top - 5000, top - 1030]
+    m0 = [0] + [int(rng.integers(0, n)) for n in n64[1:]]
+    s0 = [pow(a, t, p) for t in logs]
+    c = ph.Context(0, max_instances=16)
+    ids = [int(x) for x in c.add_instances(64, n64, e64, m0=m0, s0=s0)]
+    n32, e32, _ = orc.seed(32, SEED0 + 1801, 1, (9, 17))
+    w32 = int(c.add_instances(32, [int(n32[0])], [int(e32[0])])[0])
+    A, B, C, D, E, F, G = range(7)
+    batches = [
+        [(A, 3000), (B, 1), (C, 1), (C, 2048), (D, 1024), (E, 0), (E, 5000), (F, 4000), (G, 1000), (-1, 3000)],
+        [(F, 3000), (A, 5000), (G, 29), (B, 1000), (-1, 100)],
+        [(A, 4097), (B, 3000), (C, 100), (D, 777), (E, 2048)],
+        [(F, 100), (A, 10)],
+    ]
+    done = [0] * 7
+    got = {i: [] for i in range(7)}
+    for batch in batches:
+        specs = [(ids[i] if i >= 0 else w32, cnt) for i, cnt in batch]
+        (_, hc64, hr), offs = _run(ph, c, specs, want=(False, True, True))
+        for (i, cnt), off in zip(batch, offs):
+            if i >= 0:
+                got[i].append((done[i], hc64[off:off + cnt].copy(), hr[off:off + cnt].copy()))
+                done[i] += cnt
+    for i in range(7):
+        wc, wr, wm, ws = orc.generate(p, a, n64[i], e64[i], m0[i], s0[i], done[i])
+        for start, gc, gr in got[i]:
+            cnt = gc.size
+            compare_request(gc, gr, 0, cnt, wc[start:start + cnt], wr[start:start + cnt],
+                            "w64 table/reduce instance %d draws %d..%d" % (i, start, start + cnt))
+        m, s, _, k = c.get_state(ids[i])
+        assert (m, s, k) == (int(wm), int(ws), done[i])
+        assert s == pow(a, logs[i] + done[i], p)
+    c.close()
