@@ -339,7 +339,8 @@ __device__ uint64_t wave_prefix64(const SkipTables &T, uint64_t x, uint64_t n, u
 }
 
 // One wave per width-64 request; the first request of each instance in the
-// batch (seg > 0) serves all of that instance's requests.  With m the
+// batch whose tiles start at table entries (seg count > 0 and kSegTable)
+// serves all of that instance's requests.  With m the
 // instance's committed message at skip log x (its first request's start),
 // mbase = m - U(x) mod n gives the message at any skip log t of the range as
 // mbase + U(t) (eq. (7b)).  Each tile of the requests starts at a table
@@ -348,14 +349,15 @@ __device__ uint64_t wave_prefix64(const SkipTables &T, uint64_t x, uint64_t n, u
 __global__ void __launch_bounds__(64) tab64_kernel(GenArgs A) {
   const uint32_t lane = dev::lane_id();
   const ReqRec R0 = dev::const_load(A.req + blockIdx.x);
-  if (R0.seg == 0) return;
+  const uint32_t seg = R0.seg & kSegCount;
+  if (seg == 0 || !(R0.seg & kSegTable)) return;
   const InstRec &I = A.inst[R0.inst];
   const uint64_t n = dev::const_load(&I.n), ninv = dev::const_load(&I.ninv), r2 = dev::const_load(&I.r2);
   const uint64_t lane_mul = A.lanemul->m64[lane];
   const uint64_t m0 = dev::uniform_u64(A.m64[R0.inst]);
   const uint64_t u0 = wave_prefix64(A.tab, R0.x, n, ninv, r2, lane_mul, lane);
   const uint64_t mbase = m0 >= u0 ? m0 - u0 : m0 + (n - u0);
-  for (uint32_t q = 0; q < R0.seg; ++q) {
+  for (uint32_t q = 0; q < seg; ++q) {
     const ReqRec R = dev::const_load(A.req + blockIdx.x + q);
     const uint64_t e0 = R.x / kTab64Stride;
     for (uint32_t j = lane; j < R.ntiles; j += 64) {
@@ -364,7 +366,7 @@ __global__ void __launch_bounds__(64) tab64_kernel(GenArgs A) {
       A.t64.m[R.g1 + j] = dev::addmod64(mbase, table_entry_mod64(A.tab, e, n, ninv, r2), n);
     }
   }
-  const ReqRec RL = dev::const_load(A.req + blockIdx.x + R0.seg - 1);
+  const ReqRec RL = dev::const_load(A.req + blockIdx.x + seg - 1);
   const uint64_t ue = wave_prefix64(A.tab, RL.x + RL.count, n, ninv, r2, lane_mul, lane);
   if (lane == 0) A.m64[R0.inst] = dev::addmod64(mbase, ue, n);
 }
@@ -381,8 +383,9 @@ __global__ void __launch_bounds__(kScanThreads) scan64_kernel(GenArgs A) {
   __shared__ uint64_t wtot[kScanThreads / 64];
   const uint64_t r = blockIdx.x;
   const ReqRec R = dev::const_load(A.req + r);
-  if (R.seg == 0) return;
-  const ReqRec L = dev::const_load(A.req + r + R.seg - 1);
+  const uint32_t seg = R.seg & kSegCount;
+  if (seg == 0 || (R.seg & kSegTable)) return;
+  const ReqRec L = dev::const_load(A.req + r + seg - 1);
   const uint64_t n = dev::const_load(&A.inst[R.inst].n);
   const uint64_t t0 = R.g1, t1 = L.g1 + L.ntiles;
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -635,7 +638,7 @@ __device__ __forceinline__ void passC64_e(int ekind, const uint64_t *L, uint32_t
 }
 
 // Width 64: tile j of the request covers its draws [1024 j, 1024 (j + 1)),
-// or, when the batch's tiles start at table entries, the skip logarithms
+// or, when the instance's tiles start at table entries, the skip logarithms
 // (1024 (e0 + j), 1024 (e0 + j + 1)] with e0 = x / 1024, of which the first
 // tile skips the part before the request.  The state before the chunk's
 // first tile comes from the scan or the table kernel; later tiles continue
@@ -651,7 +654,7 @@ __device__ void run_chunk64(const GenArgs &A, const InstRec &I, const ReqRec &R,
 
   const uint32_t j_begin = (uint32_t)chunk * A.tiles_per_chunk;
   const uint32_t j_end = min(j_begin + A.tiles_per_chunk, R.ntiles);
-  const bool tab = dev::uniform_u32((uint32_t)dev::const_load(&A.hdr->tab64)) != 0;
+  const bool tab = (R.seg & kSegTable) != 0;
   // draw t of tile j is request draw (first draw of tile j) + t; at table
   // entries the first tile starts x mod 1024 draws before the request
   const uint32_t head = tab ? (uint32_t)(R.x & (kTab64Stride - 1)) : 0u;

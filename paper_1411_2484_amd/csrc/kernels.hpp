@@ -47,9 +47,10 @@ hipError_t launch_position64(const InstRec *inst, const uint32_t *ids, const uin
 // per width-64 request).
 hipError_t launch_tiles64_reduce(const GenArgs &A, uint64_t units64, unsigned max_blocks, hipStream_t st);
 hipError_t launch_tiles64_scan(const GenArgs &A, uint64_t nreq64, hipStream_t st);
-// Width-64 tile starts from the table for a batch whose width-64 draws all
-// lie below kTab64Range (hdr->tab64): one wave per width-64 request; also
-// commits the instances' messages.
+// Width-64 tile starts from the table for the instances whose draws in the
+// batch all lie below kTab64Range (kSegTable in their requests' seg): one
+// wave per width-64 request; also commits those instances' messages.  The
+// scan serves the other instances.
 hipError_t launch_tiles64_table(const GenArgs &A, uint64_t nreq64, hipStream_t st);
 // *m = *m + sign * (sum_{i=1}^{count} (a^{t+i} mod p) + extra) mod n, with
 // `blocks` 256-thread blocks writing blocks * 4 partial sums to `partial`.

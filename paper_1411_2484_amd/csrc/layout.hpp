@@ -78,16 +78,20 @@ struct alignas(64) ReqRec {
   uint64_t out_off;     // output element offset
   uint64_t g1;          // width 32: global tile of the first draw (q * tiles per period + j);
                         // constant skip: x / kTileCS; width 64: first entry in the batch's tile-state arrays
-                        // (its tiles start at x + 1024 j, or at table entries when the batch's tab64 is set)
+                        // (its tiles start at x + 1024 j, or at table entries when seg has kSegTable)
   uint64_t chunk_base;  // first chunk of this request in the batch
   uint32_t inst;        // instance id
   uint32_t ntiles;      // tiles touched
   uint32_t nchunks;     // chunks of this request
   uint32_t seg;         // width 64 pseudorandom skip: number of consecutive requests of this instance
-                        // starting here (0 for a request that is not the first of its instance)
+                        // starting here (0 for a request that is not the first of its instance), plus
+                        // kSegTable when the instance's tiles start at table entries
   uint64_t rbase;       // width 64 pseudorandom skip: first reduce unit of this request
 };
 static_assert(sizeof(ReqRec) == 64, "ReqRec must be 64 bytes");
+// ReqRec::seg: the table flag and the request count of an instance segment.
+constexpr uint32_t kSegTable = 1u << 31;
+constexpr uint32_t kSegCount = kSegTable - 1;
 
 // Per-call totals, copied with the requests (kernels read them from device
 // memory, so that captured graphs take new values at every launch).
@@ -98,8 +102,7 @@ struct alignas(64) BatchHdr {
   uint64_t tiles64;       // their tiles (entries of the tile-state arrays)
   uint64_t units64;       // their reduce units
   uint64_t reduce_tiles;  // tiles per reduce unit (1 .. kReduceTiles)
-  uint64_t tab64;         // 1: width-64 tiles start at table entries (all draws below kTab64Range)
-  uint64_t pad;
+  uint64_t pad[2];
 };
 static_assert(sizeof(BatchHdr) == 64, "BatchHdr must be 64 bytes");
 

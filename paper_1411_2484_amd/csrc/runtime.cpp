@@ -138,7 +138,8 @@ struct Plan {
   uint64_t tiles64 = 0;  // their tiles
   uint64_t units64 = 0;  // their reduce units (reduce_tiles tiles of one request)
   uint32_t reduce_tiles = kReduceTiles;
-  bool tab64 = false;    // width-64 tile starts from the table (tiles at table entries)
+  bool any_tab = false;     // some width-64 instance takes its tile starts from the table
+  bool any_reduce = false;  // some takes them from the reduce and scan
   uint64_t tiles = 0;    // all tiles
   uint64_t total_chunks = 0;
   uint32_t tpc = 1;
@@ -196,6 +197,7 @@ struct phprng_ctx {
   std::vector<uint32_t> touched;
   std::vector<uint64_t> cur_x, cur_k;
   std::vector<uint32_t> seg_count, seg_start;
+  std::vector<uint8_t> seg_tab;  // per touched instance: width-64 tile starts from the table
   std::vector<uint64_t> req_x;
   std::vector<uint32_t> req_pos;
   std::vector<uint32_t> order;
@@ -609,12 +611,14 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   // records
   BatchHdr *H = reinterpret_cast<BatchHdr *>(stage);
   ReqRec *R = reinterpret_cast<ReqRec *>(stage + sizeof(BatchHdr));
-  // Width-64 tile starts come from the table when every width-64 draw of the
-  // batch lies below its range (tiles then start at table entries), else
-  // from the reduce and scan of the requests' own skips.
-  bool tab64 = allow_tab64 && have64 && c64l > 0;
-  for (uint64_t i = 0; tab64 && i < nreq; ++i)
-    if (lcg64(inst[reqs[i].instance]) && req_x[i] + reqs[i].count >= kTab64Range) tab64 = false;
+  // A width-64 instance's tile starts come from the table when all of its
+  // draws in the batch lie below the table's range (its tiles then start at
+  // table entries), else from the reduce and scan of its requests' skips.
+  seg_tab.assign(touched.size(), (uint8_t)(allow_tab64 && have64));
+  for (uint64_t i = 0; i < nreq; ++i)
+    if (lcg64(inst[reqs[i].instance]) && req_x[i] + reqs[i].count >= kTab64Range)
+      seg_tab[(size_t)where[reqs[i].instance]] = 0;
+  bool any_tab = false, any_reduce = false;
   uint64_t tiles = 0, tiles64 = 0, units64 = 0;
   for (uint64_t p = 0; p < nreq; ++p) {
     const uint64_t i = order[p];
@@ -629,14 +633,16 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
     uint64_t nt = 0;
     if (lcg64(h)) {
       const size_t t = (size_t)where[q.instance];
-      if (tab64)
+      const bool tab = seg_tab[t] != 0;
+      if (tab)
         nt = q.count ? (rr.x + q.count - 1) / kTab64Stride - rr.x / kTab64Stride + 1 : 0;
       else
         nt = (q.count + kTile64 - 1) / kTile64;
       rr.g1 = tiles64;
       tiles64 += nt;
-
-      rr.seg = p == seg_start[t] ? seg_count[t] : 0;
+      rr.seg = (p == seg_start[t] ? seg_count[t] : 0) | (tab ? kSegTable : 0u);
+      any_tab = any_tab || tab;
+      any_reduce = any_reduce || !tab;
     } else if (h.sched == kSchedConstant) {
       rr.g1 = rr.x / kTileCS;
       nt = q.count ? (rr.x + q.count - 1) / kTileCS - rr.g1 + 1 : 0;
@@ -654,16 +660,22 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   out.nreq64 = c64l;
   // width-64 reduce units: up to kReduceTiles tiles each, fewer when the
   // batch would leave most of the reduce grid idle
+  uint64_t tiles_reduce = 0;
+  for (uint64_t p = 0; p < c64l; ++p)
+    if (!(R[p].seg & kSegTable)) tiles_reduce += R[p].ntiles;
   uint32_t rt = kReduceTiles;
-  while (rt > 1 && tiles64 < (uint64_t)rt * kReduceWaves) rt >>= 1;
+  while (rt > 1 && tiles_reduce < (uint64_t)rt * kReduceWaves) rt >>= 1;
   for (uint64_t p = 0; p < c64l; ++p) {
+    // requests with table tile starts take no unit (the reduce's search
+    // passes over them: they share the next request's first unit)
     R[p].rbase = units64;
-    units64 += ((uint64_t)R[p].ntiles + rt - 1) / rt;
+    if (!(R[p].seg & kSegTable)) units64 += ((uint64_t)R[p].ntiles + rt - 1) / rt;
   }
   out.tiles64 = tiles64;
   out.units64 = units64;
   out.reduce_tiles = rt;
-  out.tab64 = tab64;
+  out.any_tab = any_tab;
+  out.any_reduce = any_reduce;
   out.tiles = tiles;
   out.has64 = c64l + c64c > 0;
   out.has32 = c32 > 0;
@@ -698,7 +710,6 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   H->tiles64 = tiles64;
   H->units64 = units64;
   H->reduce_tiles = rt;
-  H->tab64 = tab64 ? 1 : 0;
   *P = out;
   return PHPRNG_OK;
 }
@@ -738,11 +749,11 @@ GenArgs phprng_ctx::args(const uint8_t *d_blk, WorkCtr *ctr, uint64_t *t64, uint
 phprng_status phprng_ctx::launch(const Plan &P, const GenArgs &A, const ReqRec *hreq, hipStream_t s, int mode) {
   hipError_t e;
   if (P.nreq64 > 0) {
-    if (!P.tab64 && (e = launch_tiles64_reduce(A, P.units64, (unsigned)num_cus * 8, s)) != hipSuccess)
+    if (P.any_reduce && (e = launch_tiles64_reduce(A, P.units64, (unsigned)num_cus * 8, s)) != hipSuccess)
       return hip_fail(e, "tile reduce");
     if (chain_pending && (e = hipStreamWaitEvent(s, chain_ev, 0)) != hipSuccess) return hip_fail(e, "chain wait");
-    e = P.tab64 ? launch_tiles64_table(A, P.nreq64, s) : launch_tiles64_scan(A, P.nreq64, s);
-    if (e != hipSuccess) return hip_fail(e, "tile starts");
+    if (P.any_tab && (e = launch_tiles64_table(A, P.nreq64, s)) != hipSuccess) return hip_fail(e, "table tile starts");
+    if (P.any_reduce && (e = launch_tiles64_scan(A, P.nreq64, s)) != hipSuccess) return hip_fail(e, "tile scan");
     if ((e = hipEventRecord(chain_ev, s)) != hipSuccess) return hip_fail(e, "chain record");
     chain_pending = true;
   }
@@ -961,6 +972,7 @@ extern "C" phprng_status phprng_create(phprng_ctx **out, int device, uint64_t ma
   try {
     for (auto *v : {&c->touched, &c->seg_count, &c->seg_start, &c->req_pos, &c->order})
       v->reserve(kPlanReserve);
+    c->seg_tab.reserve(kPlanReserve);
     for (auto *v : {&c->cur_x, &c->cur_k, &c->req_x}) v->reserve(kPlanReserve);
   } catch (...) {
     return PHPRNG_E_NOMEM;

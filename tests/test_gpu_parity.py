@@ -655,14 +655,15 @@ def test_64bit_reduce_unit_sizes(ph, orc, tiles):
 
 
 def test_64bit_table_tile_starts_and_mode_changes(ph, orc):
-    """Width-64 batches whose draws all lie below the table's range take
-    their tile starts from the table (tiles at multiples of 1024 skip
-    logarithms, the first one entered part-way); a batch with one request
-    that crosses the range end takes the reduce and scan for all of its
-    width-64 requests.  Instances start at aligned and unaligned skip
+    """A width-64 instance whose draws in a batch all lie below the table's
+    range takes its tile starts from the table (tiles at multiples of 1024
+    skip logarithms, the first one entered part-way); an instance with a
+    request that crosses the range end takes the reduce and scan, in the same
+    batch as table instances.  Instances start at aligned and unaligned skip
     logarithms, one of them twice in a batch, one request is empty, one ends
-    one draw before the range end; four batches switch between the two modes
-    and every draw is compared with the oracle's continuing stream."""
+    one draw before the range end; over four batches instances move from one
+    way to the other, and every draw and the final states are compared with
+    the oracle's continuing streams."""
     rng = np.random.default_rng(SEED0 + 1800)
     p, a = orc.lcg_params(64)
     n64, e64, _ = orc.seed(64, SEED0 + 1800, 7, (9, 17))
