@@ -10,7 +10,9 @@
   - the example instance of Sec. II from the base state: the draws, states
     and skip sums of tests/golden/crosscheck_values.json;
   - the autotuner: a legal shape, positions and width-64 messages restored,
-    and the same draws with the tuned shape as with the default one.
+    and the same draws with the tuned shape as with the default one;
+  - positions at the top of the uint64 range: draws up to position 2^64 - 1
+    for both widths, then one draw more refused.
 """
 
 import json
@@ -183,3 +185,42 @@ def test_autotune_shape_state_and_outputs(ph, orc):
     assert c2.get_tuning_class(ph.PHPRNG_CLASS_MIXED) == best
     c2.close()
     c.close()
+
+
+def test_positions_at_the_top_of_the_uint64_range(ph, ctx, orc, tab32):
+    """Positions use the whole uint64 range: a width-32 instance (eq. (7)
+    over the whole skip period) and a width-64 unit-skip instance placed
+    3000 draws below 2^64 draw up to the last position, 2^64 - 1, in two
+    batches; one draw more is refused with nothing changed."""
+    import torch
+    top = (1 << 64) - 1
+    k0 = top - 2999
+    p, a = orc.lcg_params(32)
+    n32, e32, _ = orc.seed(32, SEED0 + 400, 1, (9, 17))
+    n32, e32 = int(n32[0]), int(e32[0])
+    n64, e64, _ = orc.seed(64, SEED0 + 401, 1, (9, 17))
+    n64, e64 = int(n64[0]), int(e64[0])
+    i32 = int(ctx.add_instances(32, [n32], [e32], k0=[k0])[0])
+    b, m0 = 987654321, 12345
+    i64 = int(ctx.add_instances_skip(64, [n64], [e64], [b], m0=[m0], k0=[k0])[0])
+    assert ctx.get_position(i32) == k0 and ctx.get_position(i64) == k0
+    m32, s32 = orc.position(tab32, p, a, n32, 0, 1, k0)
+    w32c, w32r, _, _ = orc.generate(p, a, n32, e32, m32, s32, 2999)
+    w64c, w64r, _ = orc.generate_cskip(n64, e64, b, (m0 + k0 * b) % n64, 2999)
+    done = 0
+    for cnt in (2000, 999):
+        c32, c64, r = alloc_outputs(2 * cnt)
+        ctx.generate(ph.make_requests([i32, i64], [cnt, cnt], [0, cnt]), c32, c64, r)
+        hc32, hc64, hr = to_host(c32, c64, r)
+        compare_request(hc32, hr, 0, cnt, w32c[done:done + cnt], w32r[done:done + cnt], "w32 top")
+        compare_request(hc64, hr, cnt, cnt, w64c[done:done + cnt], w64r[done:done + cnt], "w64 unit skip top")
+        done += cnt
+    assert ctx.get_position(i32) == top and ctx.get_position(i64) == top
+    before = [ctx.get_state(i32), ctx.get_state(i64)]
+    c32, c64, r = alloc_outputs(2)
+    for iid in (i32, i64):
+        with pytest.raises(ph.PhprngError) as ex:
+            ctx.generate(ph.make_requests([iid], [1], [0]), c32, c64, r)
+        assert ex.value.status == ph.PHPRNG_E_RANGE
+    assert [ctx.get_state(i32), ctx.get_state(i64)] == before
+    torch.cuda.synchronize()
