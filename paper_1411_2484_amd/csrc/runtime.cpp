@@ -118,7 +118,8 @@ struct phprng_graph {
   hipEvent_t done = nullptr;  // after the previous launch
   bool launched = false;
   std::vector<phprng_request> reqs;
-  uint64_t nreq64 = 0, tiles64 = 0;
+  uint64_t nreq64 = 0;
+  uint64_t cap64 = 0;  // width-64 tile-state entries: enough for either way of finding tile starts
   uint32_t tpc = 1;
   bool has64 = false;
   ~phprng_graph() {
@@ -401,7 +402,7 @@ struct phprng_ctx {
   phprng_status build_table32();
   phprng_status build_table64();
   phprng_status plan(const phprng_request *reqs, uint64_t nreq, uint64_t capacity, int mode, const uint32_t *tpc_fix,
-                     uint64_t stage_cap, uint8_t *stage, Plan *P, bool allow_tab64 = true);
+                     uint64_t stage_cap, uint8_t *stage, Plan *P);
   void commit_plan();
   GenArgs args(const uint8_t *d_blk, WorkCtr *ctr, uint64_t *t64, uint64_t t64cap, uint64_t nreq, uint32_t *c32,
                uint64_t *c64, double *r, uint32_t tpc) const;
@@ -528,8 +529,7 @@ static inline uint64_t tile_of32(uint64_t x) {
 // been issued.  tpc_fix: tiles per chunk to use as is (graphs), else the
 // tuned value, halved for batches too small to give every wave 4 chunks.
 phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64_t capacity, int mode,
-                               const uint32_t *tpc_fix, uint64_t stage_cap, uint8_t *stage, Plan *P,
-                               bool allow_tab64) {
+                               const uint32_t *tpc_fix, uint64_t stage_cap, uint8_t *stage, Plan *P) {
   if (nreq > 0 && !reqs) return fail(PHPRNG_E_INVALID, "null request array");
   if (nreq > stage_cap) return fail(PHPRNG_E_RANGE, "too many requests for the staging buffer");
   if (nreq >= (1ull << 31)) return fail(PHPRNG_E_RANGE, "too many requests");
@@ -614,7 +614,7 @@ phprng_status phprng_ctx::plan(const phprng_request *reqs, uint64_t nreq, uint64
   // A width-64 instance's tile starts come from the table when all of its
   // draws in the batch lie below the table's range (its tiles then start at
   // table entries), else from the reduce and scan of its requests' skips.
-  seg_tab.assign(touched.size(), (uint8_t)(allow_tab64 && have64));
+  seg_tab.assign(touched.size(), (uint8_t)have64);
   for (uint64_t i = 0; i < nreq; ++i)
     if (lcg64(inst[reqs[i].instance]) && req_x[i] + reqs[i].count >= kTab64Range)
       seg_tab[(size_t)where[reqs[i].instance]] = 0;
@@ -1697,20 +1697,24 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
   phprng_status st = c->take_slot(nreq, &slot);
   if (st != PHPRNG_OK) return st;
   Plan P;
-  // graphs keep the reduce-and-scan tile starts, which hold at any position
-  st = c->plan(reqs, nreq, capacity, PHPRNG_MODE_PERSISTENT, nullptr, slot->cap, slot->h_blk, &P, false);
+  st = c->plan(reqs, nreq, capacity, PHPRNG_MODE_PERSISTENT, nullptr, slot->cap, slot->h_blk, &P);
   if (st != PHPRNG_OK) return st;
   std::unique_ptr<phprng_graph> g(new (std::nothrow) phprng_graph);
   if (!g) return PHPRNG_E_NOMEM;
   g->ctx = c;
   g->reqs.assign(reqs, reqs + nreq);
   g->nreq64 = P.nreq64;
-  g->tiles64 = P.tiles64;
   g->tpc = P.tpc;
   g->has64 = P.has64;
+  // Each replay finds every instance's tile starts in whichever way its
+  // position allows (the table, or the reduce and scan): a request takes
+  // ceil(count / 1024) tiles the second way and at most one more the first.
+  uint64_t cap64 = 1;
+  for (uint64_t i = 0; i < nreq; ++i)
+    if (lcg64(c->inst[reqs[i].instance])) cap64 += (reqs[i].count + kTile64 - 1) / kTile64 + 1;
+  g->cap64 = cap64;
   hipError_t e;
   const uint64_t bytes = sizeof(BatchHdr) + nreq * sizeof(ReqRec);
-  const uint64_t cap64 = std::max<uint64_t>(P.tiles64, 1);
   if ((e = hipMalloc(&g->d_blk, bytes)) != hipSuccess) return c->hip_fail(e, "graph alloc");
   if ((e = hipMalloc(&g->d_ctr, sizeof(WorkCtr))) != hipSuccess) return c->hip_fail(e, "graph alloc");
   if ((e = hipMemset(g->d_ctr, 0, sizeof(WorkCtr))) != hipSuccess) return c->hip_fail(e, "graph alloc");
@@ -1721,7 +1725,11 @@ extern "C" phprng_status phprng_graph_create(phprng_ctx *c, const phprng_request
   hipStream_t cap_stream;
   if ((e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking)) != hipSuccess) return c->hip_fail(e, "stream");
   e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess && P.nreq64 > 0) e = launch_tiles64_reduce(A, P.units64, (unsigned)c->num_cus * 8, cap_stream);
+  // all three tile-start kernels, on grids that fit any replay: each reads
+  // from the replay's block which instances are its own
+  const unsigned reduce_blocks = (unsigned)c->num_cus * 8;
+  if (e == hipSuccess && P.nreq64 > 0) e = launch_tiles64_reduce(A, 4ull * reduce_blocks, reduce_blocks, cap_stream);
+  if (e == hipSuccess && P.nreq64 > 0) e = launch_tiles64_table(A, P.nreq64, cap_stream);
   if (e == hipSuccess && P.nreq64 > 0) e = launch_tiles64_scan(A, P.nreq64, cap_stream);
   if (e == hipSuccess)
     e = launch_persistent(A, (unsigned)(c->num_cus * T.blocks_per_cu), T.block_threads, T.unroll, P.has64, cap_stream);
@@ -1746,9 +1754,9 @@ extern "C" phprng_status phprng_graph_launch(phprng_graph *g, void *stream) {
   // the last launch (generate, jump, set_state)
   Plan P;
   uint64_t capacity = ~0ull;
-  st = c->plan(g->reqs.data(), nreq, capacity, PHPRNG_MODE_PERSISTENT, &g->tpc, slot->cap, slot->h_blk, &P, false);
+  st = c->plan(g->reqs.data(), nreq, capacity, PHPRNG_MODE_PERSISTENT, &g->tpc, slot->cap, slot->h_blk, &P);
   if (st != PHPRNG_OK) return st;
-  if (P.nreq64 != g->nreq64 || P.tiles64 != g->tiles64)
+  if (P.nreq64 != g->nreq64 || P.tiles64 > g->cap64)
     return c->fail(PHPRNG_E_INVALID, "graph requests no longer match their instances");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;

@@ -703,3 +703,40 @@ def test_64bit_table_tile_starts_and_mode_changes(ph, orc):
         assert (m, s, k) == (int(wm), int(ws), done[i])
         assert s == pow(a, logs[i] + done[i], p)
     c.close()
+
+
+def test_graph_replays_cross_the_table_range(ph, orc):
+    """A captured graph over width-64 instances keeps up as replays carry
+    one instance across skip logarithm 2^34 (table tile starts, then the
+    reduce and scan from the replay that crosses it on) while another stays
+    in range; every replay against the oracle's continuing streams."""
+    import torch
+    p, a = orc.lcg_params(64)
+    n64, e64, _ = orc.seed(64, SEED0 + 1900, 2, (9, 17))
+    n64, e64 = [int(x) for x in n64], [int(x) for x in e64]
+    logs = [(1 << 34) - 2500, 777]
+    m0 = [123456789 % n64[0], 42]
+    s0 = [pow(a, t, p) for t in logs]
+    c = ph.Context(0, max_instances=4)
+    ids = [int(x) for x in c.add_instances(64, n64, e64, m0=m0, s0=s0)]
+    count = 1000
+    c64 = torch.full((2 * count,), -1, dtype=torch.int64, device="cuda:0")
+    r = torch.full((2 * count,), -1.0, dtype=torch.float64, device="cuda:0")
+    g = c.graph(ph.make_requests(ids, [count, count], [0, count]), None, c64, r)
+    replays = 5
+    streams = [orc.generate(p, a, n64[i], e64[i], m0[i], s0[i], replays * count) for i in range(2)]
+    for k in range(replays):
+        g.launch()
+        torch.cuda.synchronize()
+        hc64 = c64.cpu().numpy().view(np.uint64)
+        hr = r.cpu().numpy()
+        for i in range(2):
+            wc, wr, _, _ = streams[i]
+            compare_request(hc64, hr, i * count, count, wc[k * count:(k + 1) * count], wr[k * count:(k + 1) * count],
+                            "graph replay %d instance %d" % (k, i))
+    for i in range(2):
+        _, _, wm, ws = streams[i]
+        m, s, _, kk = c.get_state(ids[i])
+        assert (m, s, kk) == (int(wm), int(ws), replays * count)
+    g.close()
+    c.close()
