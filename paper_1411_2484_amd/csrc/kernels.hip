@@ -1,7 +1,8 @@
 // gfx950 kernels for the Pohlig-Hellman parameter-split generator:
 //   - skip-prefix table segments (eq. (7b) building blocks),
-//   - width-64 tile starts from the requests' own skip sums (reduce, then a
-//     scan per instance that also commits the instance's message),
+//   - width-64 tile starts, from the 64-bit table for instances that stay
+//     in its range, else from the requests' own skip sums (reduce, then a
+//     scan per instance); both commit the instance's message,
 //   - batched generation (algorithm (9)) as a persistent work-stealing grid
 //     or as one plain grid per request,
 //   - width-64 positioning and jumps (eq. (7) sums on the device),
@@ -10,8 +11,9 @@
 // Width-32 tiles are 2048 consecutive draws of one instance whose starting
 // state index is a multiple of 2048 within the skip period: the universal
 // table holds the skip-prefix sum U and the skip a^r there.  Width-64 tiles
-// are 1024 draws counted from the first draw of their request; their start
-// states come from the reduce and scan kernels.  One wave computes a tile in
+// are 1024 draws, starting at multiples of 1024 skip logarithms (table
+// entries) or counted from the first draw of their request (reduce and
+// scan).  One wave computes a tile in
 // three passes over its LDS row block:
 //   A. lane l steps the skip generator over its run of draws, keeps the
 //      skips in LDS and sums them;
