@@ -367,16 +367,19 @@ def section_d(args, torch, ph, out):
     res = {"workload": "1024 seeded width-64 instances (n in [2^62, 2^63)) + 1024 width-32 instances, 2^20 draws "
                        "each from position 0, u64/u32 c + f64 R"}
     if not args.no_autotune:
-        # width-64-only shapes, tuned on a context of the 64-bit instances alone
+        # width-64-only shapes, tuned on a context of the 64-bit instances
+        # alone, with 2^18 draws per instance: enough chunks to keep every
+        # candidate grid busy, as the timed 2^20-draw streams do (a smaller
+        # tuning batch favours grids too small for the timed one)
         t64 = ph.Context(0, max_instances=1024)
         t64.seed_instances(64, W.SEED0 + 3, 1024, (9, 17), 0, 0)
-        t64.autotune(1 << 25)
+        t64.autotune(1 << 28)
         t64.close()
     ctx = ph.Context(0, max_instances=2048)
     i64 = ctx.seed_instances(64, W.SEED0 + 3, 1024, (9, 17), 0, 0)
     i32 = ctx.seed_instances(32, W.SEED0 + 4, 1024, (9, 17), 0, 0)
     if not args.no_autotune:
-        ctx.autotune(1 << 26)
+        ctx.autotune(1 << 29)
     res["tuning"] = {"width64": ctx.get_tuning_class(ph.PHPRNG_CLASS_W64),
                      "mixed": ctx.get_tuning_class(ph.PHPRNG_CLASS_MIXED),
                      "width32": ctx.get_tuning_class(ph.PHPRNG_CLASS_W32)}

@@ -4,7 +4,9 @@
 //
 // A 32 x 32 -> 64 product (plus a 64-bit addend) is one v_mad_u64_u32; on
 // gfx950 it issues at about 60% of the rate of a plain 32-bit add, so the
-// 64-bit routines below are arranged to need few of them and no carries.
+// 64-bit routines below are arranged to need few of them and few carries
+// (the one carry the Montgomery reduction cannot avoid is the
+// multiply-add's own carry-out).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -139,6 +141,15 @@ struct W128 {
   uint64_t lo, hi;
 };
 
+// a b + c in one v_mad_u64_u32.  Written out because the compiler
+// reassociates a sum of two such products plus a 32-bit term into two
+// products and a separate 64-bit add.
+__device__ __forceinline__ uint64_t mad_u64_u32(uint32_t a, uint32_t b, uint64_t c) {
+  uint64_t r, carry;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 // Full product of x, y < 2^63.  The high words are below 2^31, so
 // x1 y0 + x0 y1 + hi(x0 y0) < 2^64: three multiply-adds chain without a
 // carry, and each 64-bit addend is a whole register pair.
@@ -146,7 +157,7 @@ __device__ __forceinline__ W128 mul63w(uint64_t x, uint64_t y) {
   const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32);
   const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
   const uint64_t p00 = (uint64_t)x0 * y0;
-  const uint64_t mid = (uint64_t)x1 * y0 + ((uint64_t)x0 * y1 + (p00 >> 32));
+  const uint64_t mid = mad_u64_u32(x1, y0, (uint64_t)x0 * y1 + (p00 >> 32));
   return {(mid << 32) | (uint32_t)p00, (uint64_t)x1 * y1 + (mid >> 32)};
 }
 
@@ -192,6 +203,52 @@ __device__ __forceinline__ uint64_t msqr64(uint64_t x, uint64_t n, uint64_t ninv
   return redc64(sqr63w(x), n, ninv);
 }
 
+// redc64 for a modulus that is the same in every lane of the wave (n and
+// ninv are read from scalar registers; the compiler reads them from the
+// first active lane if they sit in vector registers).  Same result as
+// redc64, in fewer instructions: with q = lo(v) ninv mod 2^64 and
+// h = hi(q0 n0), the middle column q1 n0 + h + q0 n1 can exceed 64 bits,
+// and the multiply-add's carry-out supplies that bit, so
+// hi(q n) = q1 n1 + (hi(middle) + carry 2^32) takes one multiply-add; the
+// borrow of hi(v) - hi(q n) then selects the n that is added back (the
+// compiler's form recomputes that borrow with a 64-bit compare).
+//
+// v0-v3 hold the intermediate register pairs (declared clobbered), and VCC
+// carries each carry or borrow: gfx950 wants two wait states between a
+// VALU write of VCC and a VALU read of it, hence the s_nop lines.
+__device__ __forceinline__ uint64_t redc64_uniform(W128 v, uint64_t n, uint64_t ninv) {
+  const uint64_t q = v.lo * ninv;
+  const uint64_t h = __umulhi((uint32_t)q, (uint32_t)n);
+  uint64_t r;
+  asm("v_mad_u64_u32 v[0:1], vcc, %[q1], %[n0], %[h]\n\t"   // q1 n0 + h < 2^64
+      "v_mad_u64_u32 v[0:1], vcc, %[q0], %[n1], v[0:1]\n\t"  // + q0 n1, carry-out in VCC
+      "v_mov_b32 v2, v1\n\t"
+      "s_nop 0\n\t"
+      "v_cndmask_b32_e64 v3, 0, 1, vcc\n\t"                  // v[2:3] = hi(middle) + carry 2^32
+      "v_mad_u64_u32 v[2:3], vcc, %[q1], %[n1], v[2:3]\n\t"  // hi(q n) < 2^64
+      "v_sub_co_u32 v0, vcc, %[p0], v2\n\t"
+      "s_nop 1\n\t"
+      "v_subb_co_u32 v1, vcc, %[p1], v3, vcc\n\t"           // hi(v) - hi(q n), borrow in VCC
+      "s_nop 1\n\t"
+      "v_cndmask_b32 v2, 0, %[vn0], vcc\n\t"
+      "v_cndmask_b32 v3, 0, %[vn1], vcc\n\t"
+      "v_lshl_add_u64 %[r], v[0:1], 0, v[2:3]"               // + (borrow ? n : 0)
+      : [r] "=v"(r)
+      : [q0] "v"((uint32_t)q), [q1] "v"((uint32_t)(q >> 32)), [n0] "s"((uint32_t)n),
+        [n1] "s"((uint32_t)(n >> 32)), [h] "v"(h), [p0] "v"((uint32_t)v.hi), [p1] "v"((uint32_t)(v.hi >> 32)),
+        [vn0] "v"((uint32_t)n), [vn1] "v"((uint32_t)(n >> 32))
+      : "v0", "v1", "v2", "v3", "vcc");
+  return r;
+}
+
+__device__ __forceinline__ uint64_t mont64_uniform(uint64_t x, uint64_t y, uint64_t n, uint64_t ninv) {
+  return redc64_uniform(mul63w(x, y), n, ninv);
+}
+
+__device__ __forceinline__ uint64_t msqr64_uniform(uint64_t x, uint64_t n, uint64_t ninv) {
+  return redc64_uniform(sqr63w(x), n, ninv);
+}
+
 // (m + s) mod n for m, s < n < 2^63 (no overflow of the sum).
 __device__ __forceinline__ uint64_t addmod64(uint64_t m, uint64_t s, uint64_t n) {
   uint64_t t = m + s;
@@ -205,36 +262,39 @@ __device__ __forceinline__ uint64_t mod_below_4n(uint64_t v, uint64_t n) {
   return v >= n ? v - n : v;
 }
 
+// m^e mod n (algorithm (9)) by a fixed chain for e = 3, 5, 9, 17, else by
+// left-to-right squaring; n, ninv and kc = 2^{64 e} mod n are the same in
+// every lane of the wave (one instance per tile).
 template <int EK>
 __device__ __forceinline__ uint64_t encrypt64(uint64_t m, uint64_t n, uint64_t ninv, uint64_t kc, uint64_t e,
                                               int ebits) {
   uint64_t x;
   if constexpr (EK == 3) {
-    x = msqr64(m, n, ninv);
-    x = mont64(x, m, n, ninv);
+    x = msqr64_uniform(m, n, ninv);
+    x = mont64_uniform(x, m, n, ninv);
   } else if constexpr (EK == 5) {
-    x = msqr64(m, n, ninv);
-    x = msqr64(x, n, ninv);
-    x = mont64(x, m, n, ninv);
+    x = msqr64_uniform(m, n, ninv);
+    x = msqr64_uniform(x, n, ninv);
+    x = mont64_uniform(x, m, n, ninv);
   } else if constexpr (EK == 9) {
-    x = msqr64(m, n, ninv);
-    x = msqr64(x, n, ninv);
-    x = msqr64(x, n, ninv);
-    x = mont64(x, m, n, ninv);
+    x = msqr64_uniform(m, n, ninv);
+    x = msqr64_uniform(x, n, ninv);
+    x = msqr64_uniform(x, n, ninv);
+    x = mont64_uniform(x, m, n, ninv);
   } else if constexpr (EK == 17) {
-    x = msqr64(m, n, ninv);
-    x = msqr64(x, n, ninv);
-    x = msqr64(x, n, ninv);
-    x = msqr64(x, n, ninv);
-    x = mont64(x, m, n, ninv);
+    x = msqr64_uniform(m, n, ninv);
+    x = msqr64_uniform(x, n, ninv);
+    x = msqr64_uniform(x, n, ninv);
+    x = msqr64_uniform(x, n, ninv);
+    x = mont64_uniform(x, m, n, ninv);
   } else {
     x = m;
     for (int b = ebits - 2; b >= 0; --b) {
-      x = msqr64(x, n, ninv);
-      if ((e >> b) & 1) x = mont64(x, m, n, ninv);
+      x = msqr64_uniform(x, n, ninv);
+      if ((e >> b) & 1) x = mont64_uniform(x, m, n, ninv);
     }
   }
-  return mont64(x, kc, n, ninv);
+  return mont64_uniform(x, kc, n, ninv);
 }
 
 // Skip generator mod 2^61 - 1 (width 64): fold the 122-bit product.
