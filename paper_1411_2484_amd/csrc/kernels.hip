@@ -362,10 +362,37 @@ __global__ void __launch_bounds__(64) tab64_kernel(GenArgs A) {
   for (uint32_t q = 0; q < seg; ++q) {
     const ReqRec R = dev::const_load(A.req + blockIdx.x + q);
     const uint64_t e0 = R.x / kTab64Stride;
-    for (uint32_t j = lane; j < R.ntiles; j += 64) {
-      const uint64_t e = e0 + j;
-      A.t64.s[R.g1 + j] = dev::const_load(A.tab.s64 + e);
-      A.t64.m[R.g1 + j] = dev::addmod64(mbase, table_entry_mod64(A.tab, e, n, ninv, r2), n);
+    // the table reads of kTabGroup tiles per lane are issued before any of
+    // them is used, so their latencies overlap (a long request has up to
+    // 16 tiles per lane)
+    constexpr int kTabGroup = 8;
+    for (uint32_t j0 = 0; j0 < R.ntiles; j0 += 64 * kTabGroup) {
+      // lanes past the request's last tile compute on zeros and store nothing
+      uint64_t sv[kTabGroup] = {}, ulo[kTabGroup] = {}, uhi[kTabGroup] = {};
+#pragma unroll
+      for (int k = 0; k < kTabGroup; ++k) {
+        const uint32_t j = j0 + 64 * k + lane;
+        if (j < R.ntiles) {
+          sv[k] = dev::const_load(A.tab.s64 + e0 + j);
+          ulo[k] = dev::const_load(A.tab.u64lo + e0 + j);
+          uhi[k] = dev::const_load(A.tab.u64hi + e0 + j);
+        }
+      }
+      uint64_t mv[kTabGroup];
+#pragma unroll
+      for (int k = 0; k < kTabGroup; ++k) {
+        // mbase + U(1024 e) mod n, U as table_entry_mod64 reduces it
+        const uint64_t u = dev::mont64_uniform(dev::redc64_uniform({ulo[k], uhi[k]}, n, ninv), r2, n, ninv);
+        mv[k] = dev::addmod64(mbase, u, n);
+      }
+#pragma unroll
+      for (int k = 0; k < kTabGroup; ++k) {
+        const uint32_t j = j0 + 64 * k + lane;
+        if (j < R.ntiles) {
+          A.t64.s[R.g1 + j] = sv[k];
+          A.t64.m[R.g1 + j] = mv[k];
+        }
+      }
     }
   }
   const ReqRec RL = dev::const_load(A.req + blockIdx.x + seg - 1);
