@@ -12,7 +12,11 @@
   - the autotuner: a legal shape, positions and width-64 messages restored,
     and the same draws with the tuned shape as with the default one;
   - positions at the top of the uint64 range: draws up to position 2^64 - 1
-    for both widths, then one draw more refused.
+    for both widths, then one draw more refused;
+  - width-64 moduli at both ends of [2^62, 2^63) with every exponent chain
+    (3, 5, 9, 17, a generic small one, 65537 and one above 2^31), messages
+    near n - 1, both launch forms: the Montgomery reduction's middle column
+    carries out of 64 bits most often for the largest moduli.
 """
 
 import json
@@ -224,3 +228,43 @@ def test_positions_at_the_top_of_the_uint64_range(ph, ctx, orc, tab32):
         assert ex.value.status == ph.PHPRNG_E_RANGE
     assert [ctx.get_state(i32), ctx.get_state(i64)] == before
     torch.cuda.synchronize()
+
+
+def _primes_from(orc, start, step, count):
+    out, n = [], start | 1
+    while len(out) < count:
+        if orc.is_prime(n):
+            out.append(n)
+        n += 2 * step
+    return out
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_width64_moduli_at_the_range_ends(ph, ctx, orc, mode):
+    rng = random.Random(3300 + mode)
+    p, a = orc.lcg_params(64)
+    low = _primes_from(orc, (1 << 62) + 1, 1, 3)
+    high = _primes_from(orc, (1 << 63) - 1, -1, 3)
+    exps = [3, 5, 9, 17, 7, 65537, (1 << 31) + 11]
+    ns, es, ms, ss = [], [], [], []
+    for i, n in enumerate(low + high):
+        for e in exps[i % 2::2] + ([exps[-1]] if i % 2 else []):
+            if orc.check_instance(64, n, e) != 0:
+                continue
+            s = rng.randrange(1, p)
+            ns.append(n)
+            es.append(e)
+            ms.append(n - 1 - rng.randrange(0, 1 << 20))
+            ss.append(s)
+    assert {x for x in es} >= {3, 5, 9, 17}
+    ids = [int(i) for i in ctx.add_instances(64, ns, es, m0=ms, s0=ss)]
+    count = 3000
+    reqs = ph.make_requests(ids, [count] * len(ids), np.arange(len(ids), dtype=np.uint64) * count)
+    c32, c64, r = alloc_outputs(count * len(ids), False, True, True)
+    ctx.generate(reqs, c32, c64, r, mode=mode)
+    _, hc64, hr = to_host(c32, c64, r)
+    for j, (n, e, m, s) in enumerate(zip(ns, es, ms, ss)):
+        wc, wr, _, _ = orc.generate(p, a, n, e, m, s, count)
+        lo = j * count
+        compare_request(hc64[lo:lo + count], hr[lo:lo + count], 0, count, wc, wr,
+                        "w64 n=%d e=%d mode %d" % (n, e, mode))
