@@ -1,0 +1,132 @@
+"""GPU parity on seeded random batches, bit for bit against the oracle.
+
+Each batch mixes width-64 instances positioned from the base state (their
+tiles start from the 64-bit table) with width-64 instances set to arbitrary
+carried states (m, s) (their tiles start from the reduce and scan), every
+width-64 exponent chain (3, 5, 9, 17 and generic ones), and width-32
+instances at random positions.  An instance takes one to three requests in
+one call, in call order, interleaved with the other instances' requests and
+written to shuffled output ranges.  Three consecutive calls (persistent,
+plain, then the allocation-free entry point) check that every instance
+continues from where the previous call left it.
+"""
+
+import random
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import alloc_outputs, compare_request, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ph():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1411_2484_amd as ph
+    ph.lib()
+    return ph
+
+
+def _prime(orc, rng, lo, hi):
+    while True:
+        n = rng.randrange(lo, hi) | 1
+        if orc.is_prime(n):
+            return n
+
+
+def _exponent(orc, rng, width, n, choices):
+    for e in rng.sample(choices, len(choices)):
+        if orc.check_instance(width, n, e) == 0:
+            return e
+    return None
+
+
+def _make_instances(ph, ctx, orc, tab32, tab64, rng):
+    """(id, width, n, e, m, s): the oracle's state of each new instance."""
+    out = []
+    chains = [3, 5, 7, 9, 11, 13, 17, 65537, rng.randrange(1 << 20, 1 << 32) | 1]
+    for kind in ["table"] * 12 + ["carried"] * 12 + ["w32"] * 12:
+        width = 32 if kind == "w32" else 64
+        lo, hi = (1 << 31, 1 << 32) if width == 32 else (1 << 62, 1 << 63)
+        while True:
+            n = _prime(orc, rng, lo, hi)
+            e = _exponent(orc, rng, width, n, chains if width == 64 else [3, 5, 9, 17, 65537])
+            if e is not None:
+                break
+        p, a = orc.lcg_params(width)
+        if kind == "carried":
+            m, s = rng.randrange(n), rng.randrange(2, p)
+            iid = int(ctx.add_instances(width, [n], [e], m0=[m], s0=[s])[0])
+        else:
+            k = rng.randrange(1 << 28) if width == 64 else rng.randrange(1 << 40)
+            iid = int(ctx.add_instances(width, [n], [e], k0=[k])[0])
+            m, s = orc.position(tab64 if width == 64 else tab32, p, a, n, 0, 1, k)
+        out.append([iid, width, n, e, m, s])
+    return out
+
+
+def _batch(ph, ctx, orc, insts, rng, mode):
+    """One call over all instances (mode None: the allocation-free entry
+    point); checks it and advances the oracle states."""
+    per = []
+    for _ in insts:
+        nreq = rng.choice([1, 1, 2, 3])
+        per.append([rng.choice([1, 2047, 2048, 2049, 1023, 1025, rng.randrange(1, 40000)]) for _ in range(nreq)])
+    # interleave the instances' request lists, each kept in its own order
+    queue = [i for i, lst in enumerate(per) for _ in lst]
+    rng.shuffle(queue)
+    nxt = [0] * len(insts)
+    order = []
+    for i in queue:
+        order.append((i, nxt[i]))
+        nxt[i] += 1
+    counts = [per[i][j] for i, j in order]
+    slots = list(range(len(order)))
+    rng.shuffle(slots)
+    offs = [0] * len(order)
+    cur = 0
+    for q in slots:
+        offs[q] = cur
+        cur += counts[q]
+    c32, c64, r = alloc_outputs(cur, True, True, True)
+    reqs = ph.make_requests([insts[i][0] for i, _ in order], counts, offs)
+    if mode is None:
+        ctx.generate_noalloc(reqs, c32, c64, r, capacity=cur)
+    else:
+        ctx.generate(reqs, c32, c64, r, capacity=cur, mode=mode)
+    hc32, hc64, hr = to_host(c32, c64, r)
+    done = [0] * len(insts)
+    want = {}
+    for i, inst in enumerate(insts):
+        iid, width, n, e, m, s = inst
+        p, a = orc.lcg_params(width)
+        wc, wr, m2, s2 = orc.generate(p, a, n, e, m, s, sum(per[i]))
+        want[i] = (wc, wr)
+        inst[4], inst[5] = m2, s2
+    for q, (i, j) in enumerate(order):
+        iid, width, n, e = insts[i][:4]
+        wc, wr = want[i]
+        lo = done[i]
+        done[i] += counts[q]
+        compare_request(hc32 if width == 32 else hc64, hr, offs[q], counts[q], wc[lo:lo + counts[q]],
+                        wr[lo:lo + counts[q]], "w%d inst %d (n=%d e=%d) request %d mode %s" % (width, iid, n, e, j, mode))
+    # positions reported by the library match the draws taken
+    for i, inst in enumerate(insts):
+        m, s = ctx.get_state(inst[0])[:2]
+        assert (m, s) == (inst[4], inst[5]), "state of instance %d after the call" % inst[0]
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14])
+def test_random_mixed_batches(ph, orc, tab32, tab64, seed):
+    rng = random.Random(0x5EED0000 + seed)
+    ctx = ph.Context(0, max_instances=64)
+    try:
+        insts = _make_instances(ph, ctx, orc, tab32, tab64, rng)
+        _batch(ph, ctx, orc, insts, rng, mode=ph.PHPRNG_MODE_PERSISTENT)
+        _batch(ph, ctx, orc, insts, rng, mode=ph.PHPRNG_MODE_PLAIN)
+        _batch(ph, ctx, orc, insts, rng, mode=None)
+    finally:
+        ctx.close()
