@@ -312,32 +312,37 @@ __global__ void __launch_bounds__(256) reduce64_kernel(GenArgs A) {
 // kTab64Range)
 // ---------------------------------------------------------------------------
 
-// Table entry i of U reduced mod n: U(i * kTab64Stride) < 2^95 < n 2^64, so
-// one REDC and a product with R^2 give it.
-__device__ __forceinline__ uint64_t table_entry_mod64(const SkipTables &T, uint64_t i, uint64_t n, uint64_t ninv,
-                                                      uint64_t r2) {
-  dev::W128 w;
-  w.lo = dev::const_load(T.u64lo + i);
-  w.hi = dev::const_load(T.u64hi + i);
-  return dev::mont64(dev::redc64(w, n, ninv), r2, n, ninv);
+// A table entry U(i * kTab64Stride) (128 bits, read as w) reduced mod n:
+// U < 2^95 < n 2^64, so one REDC and a product with R^2 give it.  n is the
+// same in every lane of the wave.
+__device__ __forceinline__ uint64_t table_u_mod64(dev::W128 w, uint64_t n, uint64_t ninv, uint64_t r2) {
+  return dev::mont64_uniform(dev::redc64_uniform(w, n, ninv), r2, n, ninv);
 }
 
-// U(x) mod n for x < kTab64Range by the whole wave: the entry at or below x
-// plus the (at most kTab64Stride - 1) skips after it, lane l taking the 16
-// skip indices from T + 16 l + 1.  Every lane gets the result.
-__device__ uint64_t wave_prefix64(const SkipTables &T, uint64_t x, uint64_t n, uint64_t ninv, uint64_t r2,
-                                  uint64_t lane_mul, uint32_t lane) {
-  const uint64_t i = x / kTab64Stride;
-  const uint32_t rem = (uint32_t)(x - i * kTab64Stride);
-  uint64_t s = dev::mulmod_p61(dev::const_load(T.s64 + i), lane_mul);
-  uint64_t sum = 0;
+// U(x) mod n and U(y) mod n for x, y < kTab64Range by the whole wave: the
+// entry at or below each plus the (at most kTab64Stride - 1) skips after
+// it, lane l taking the 16 skip indices from T + 16 l + 1.  The table reads
+// of both positions are issued before either is used, and the two skip
+// chains run side by side.  Every lane gets both results.
+__device__ void wave_prefix64_pair(const SkipTables &T, uint64_t x, uint64_t y, uint64_t n, uint64_t ninv,
+                                   uint64_t r2, uint64_t lane_mul, uint32_t lane, uint64_t *ux, uint64_t *uy) {
+  const uint64_t ix = x / kTab64Stride, iy = y / kTab64Stride;
+  const uint32_t rx = (uint32_t)(x - ix * kTab64Stride), ry = (uint32_t)(y - iy * kTab64Stride);
+  const uint64_t sx0 = dev::const_load(T.s64 + ix), sy0 = dev::const_load(T.s64 + iy);
+  const dev::W128 wx{dev::const_load(T.u64lo + ix), dev::const_load(T.u64hi + ix)};
+  const dev::W128 wy{dev::const_load(T.u64lo + iy), dev::const_load(T.u64hi + iy)};
+  uint64_t sx = dev::mulmod_p61(sx0, lane_mul), sy = dev::mulmod_p61(sy0, lane_mul);
+  uint64_t sumx = 0, sumy = 0;
   const uint32_t first = lane * kRun64;
 #pragma unroll 4
   for (int k = 0; k < kRun64; ++k) {
-    s = dev::mulmod_p61(kA64, s);
-    if (first + (uint32_t)k < rem) sum = dev::addmod64(sum, s, n);
+    sx = dev::mulmod_p61(kA64, sx);
+    sy = dev::mulmod_p61(kA64, sy);
+    if (first + (uint32_t)k < rx) sumx = dev::addmod64(sumx, sx, n);
+    if (first + (uint32_t)k < ry) sumy = dev::addmod64(sumy, sy, n);
   }
-  return dev::addmod64(table_entry_mod64(T, i, n, ninv, r2), dev::wave_sum_mod(sum, n), n);
+  *ux = dev::addmod64(table_u_mod64(wx, n, ninv, r2), dev::wave_sum_mod(sumx, n), n);
+  *uy = dev::addmod64(table_u_mod64(wy, n, ninv, r2), dev::wave_sum_mod(sumy, n), n);
 }
 
 // One wave per width-64 request; the first request of each instance in the
@@ -357,7 +362,10 @@ __global__ void __launch_bounds__(64) tab64_kernel(GenArgs A) {
   const uint64_t n = dev::const_load(&I.n), ninv = dev::const_load(&I.ninv), r2 = dev::const_load(&I.r2);
   const uint64_t lane_mul = A.lanemul->m64[lane];
   const uint64_t m0 = dev::uniform_u64(A.m64[R0.inst]);
-  const uint64_t u0 = wave_prefix64(A.tab, R0.x, n, ninv, r2, lane_mul, lane);
+  // U at the instance's first and last positions in the batch
+  const ReqRec RL = dev::const_load(A.req + blockIdx.x + seg - 1);
+  uint64_t u0, ue;
+  wave_prefix64_pair(A.tab, R0.x, RL.x + RL.count, n, ninv, r2, lane_mul, lane, &u0, &ue);
   const uint64_t mbase = m0 >= u0 ? m0 - u0 : m0 + (n - u0);
   for (uint32_t q = 0; q < seg; ++q) {
     const ReqRec R = dev::const_load(A.req + blockIdx.x + q);
@@ -381,9 +389,8 @@ __global__ void __launch_bounds__(64) tab64_kernel(GenArgs A) {
       uint64_t mv[kTabGroup];
 #pragma unroll
       for (int k = 0; k < kTabGroup; ++k) {
-        // mbase + U(1024 e) mod n, U as table_entry_mod64 reduces it
-        const uint64_t u = dev::mont64_uniform(dev::redc64_uniform({ulo[k], uhi[k]}, n, ninv), r2, n, ninv);
-        mv[k] = dev::addmod64(mbase, u, n);
+        // mbase + U(1024 e) mod n
+        mv[k] = dev::addmod64(mbase, table_u_mod64({ulo[k], uhi[k]}, n, ninv, r2), n);
       }
 #pragma unroll
       for (int k = 0; k < kTabGroup; ++k) {
@@ -395,8 +402,6 @@ __global__ void __launch_bounds__(64) tab64_kernel(GenArgs A) {
       }
     }
   }
-  const ReqRec RL = dev::const_load(A.req + blockIdx.x + seg - 1);
-  const uint64_t ue = wave_prefix64(A.tab, RL.x + RL.count, n, ninv, r2, lane_mul, lane);
   if (lane == 0) A.m64[R0.inst] = dev::addmod64(mbase, ue, n);
 }
 
