@@ -347,10 +347,21 @@ struct phprng_ctx {
   phprng_status take_slot(uint64_t nreq, Slot **out) {
     cur_slot = (cur_slot + 1) % kSlots;
     Slot &s = slots[cur_slot];
-    hipError_t e;
     if (s.busy) {
-      if ((e = retire(s)) != hipSuccess) return hip_fail(e, "slot wait");
+      hipError_t e = retire(s);
+      if (e != hipSuccess) return hip_fail(e, "slot wait");
     }
+    phprng_status st = prepare_slot(s, nreq);
+    if (st != PHPRNG_OK) return st;
+    *out = &s;
+    return PHPRNG_OK;
+  }
+
+  // Creates a slot's events and work counter on its first use and sizes its
+  // request buffers for nreq requests.  Context creation does this for every
+  // slot, so that calls pay only for growth beyond typical batches.
+  phprng_status prepare_slot(Slot &s, uint64_t nreq) {
+    hipError_t e;
     if (!s.ev0) {
       if ((e = hipEventCreate(&s.ev0)) != hipSuccess) return hip_fail(e, "event");
       if ((e = hipEventCreate(&s.ev1)) != hipSuccess) return hip_fail(e, "event");
@@ -383,7 +394,6 @@ struct phprng_ctx {
       s.h_blk_dev = static_cast<const uint8_t *>(dp);
       s.cap = cap;
     }
-    *out = &s;
     return PHPRNG_OK;
   }
 
@@ -1007,6 +1017,14 @@ extern "C" phprng_status phprng_create(phprng_ctx **out, int device, uint64_t ma
     return PHPRNG_E_NOMEM;
   }
   if (hipEventCreateWithFlags(&c->noalloc_copied, hipEventDisableTiming) != hipSuccess) return PHPRNG_E_DEVICE;
+  // every staging slot ready for typical batches (8192 requests, 2^16
+  // width-64 tiles): the allocations of a first use would otherwise wait
+  // for the device in the middle of a caller's stream of calls
+  for (auto &slot : c->slots) {
+    phprng_status st = c->prepare_slot(slot, phprng_ctx::kMinSlotRequests);
+    if (st == PHPRNG_OK) st = c->ensure_tiles(slot, 1);
+    if (st != PHPRNG_OK) return st;
+  }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (int cls = 0; cls < 3; ++cls) {
