@@ -118,9 +118,12 @@ const char *phprng_status_string(phprng_status st);
 /* Create a context on HIP device `device` with room for max_instances
  * instances (device records of 128 bytes each).  Builds the universal
  * 32-bit skip-prefix table of eq. (7b) on the device (12 MB); the 64-bit
- * table (400 MB) is built when the first width-64 instance is added.
- * *ctx receives the context; the caller owns it and frees it with
- * phprng_destroy. */
+ * table (400 MB) is built when the first width-64 instance is added.  Also
+ * sets up the context's eight staging slots for batches of up to 8192
+ * requests and 2^16 width-64 tiles (about 4 MB of pinned host memory and
+ * 17 MB of device memory); a larger batch grows a slot, and that growth
+ * waits for the device.  *ctx receives the context; the caller owns it and
+ * frees it with phprng_destroy. */
 phprng_status phprng_create(phprng_ctx **ctx, int device, uint64_t max_instances);
 phprng_status phprng_destroy(phprng_ctx *ctx);
 
