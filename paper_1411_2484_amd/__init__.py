@@ -220,10 +220,16 @@ def phprng_draw_instances(width, seed, count, e_set=(9, 17), k_lo=0, k_hi=0):
     return n, e, k
 
 
-def _stream_handle(stream):
+def _stream_handle(stream, device=None):
+    """Raw HIP stream: `stream` itself (an int or a torch stream), else the
+    current torch stream of `device` (of the current device when None)."""
     if stream is None:
         import torch
-        return torch.cuda.current_stream().cuda_stream
+        dev = torch.cuda.current_device() if device is None else int(device)
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            return raw(dev)  # the handle without building a Stream object
+        return torch.cuda.current_stream(dev).cuda_stream
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
@@ -371,7 +377,7 @@ class Context:
         reqs = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
         p32, p64, pr, cap = _outputs(out_c32, out_c64, out_r, self.device, capacity)
         self._chk(lib().phprng_generate(self._h, reqs.ctypes.data, reqs.size, p32, p64, pr, cap,
-                                        _stream_handle(stream), int(mode)))
+                                        _stream_handle(stream, self.device), int(mode)))
 
     def generate_noalloc(self, requests, out_c32=None, out_c64=None, out_r=None, capacity=None, stream=None):
         """phprng_generate_noalloc: the persistent generation without any
@@ -379,7 +385,7 @@ class Context:
         reqs = np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
         p32, p64, pr, cap = _outputs(out_c32, out_c64, out_r, self.device, capacity)
         self._chk(lib().phprng_generate_noalloc(self._h, reqs.ctypes.data, reqs.size, p32, p64, pr, cap,
-                                                _stream_handle(stream)))
+                                                _stream_handle(stream, self.device)))
 
     def last_kernel_ms(self):
         v = ctypes.c_double()
@@ -457,13 +463,13 @@ class Graph:
         p32, p64, pr, cap = _outputs(out_c32, out_c64, out_r, ctx.device, capacity)
         h = _vp()
         _check(lib().phprng_graph_create(ctx.handle, reqs.ctypes.data, reqs.size, p32, p64, pr, cap,
-                                         _stream_handle(stream), ctypes.byref(h)),
+                                         _stream_handle(stream, ctx.device), ctypes.byref(h)),
                ctx.handle)
         self._h = h
         self._ctx = ctx
 
     def launch(self, stream=None):
-        _check(lib().phprng_graph_launch(self._h, _stream_handle(stream)), self._ctx.handle)
+        _check(lib().phprng_graph_launch(self._h, _stream_handle(stream, self._ctx.device)), self._ctx.handle)
 
     def close(self):
         if getattr(self, "_h", None):

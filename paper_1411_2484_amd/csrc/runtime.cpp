@@ -182,7 +182,7 @@ struct phprng_ctx {
     WorkCtr *d_ctr = nullptr;
     uint64_t *d_t64 = nullptr;  // 3 * cap64 words
     uint64_t cap64 = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, done = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the call's kernels; ev1 also marks the slot free
     bool busy = false;
   };
   static constexpr int kSlots = 8;
@@ -233,7 +233,6 @@ struct phprng_ctx {
       (void)hipFree(s.d_t64);
       if (s.ev0) (void)hipEventDestroy(s.ev0);
       if (s.ev1) (void)hipEventDestroy(s.ev1);
-      if (s.done) (void)hipEventDestroy(s.done);
     }
   }
 
@@ -331,7 +330,7 @@ struct phprng_ctx {
 
   // Wait for a slot's work and add its kernel time to the running total.
   hipError_t retire(Slot &s) {
-    hipError_t e = hipEventSynchronize(s.done);
+    hipError_t e = hipEventSynchronize(s.ev1);
     if (e != hipSuccess) return e;
     float f = 0;
     if (hipEventElapsedTime(&f, s.ev0, s.ev1) == hipSuccess) {
@@ -365,7 +364,6 @@ struct phprng_ctx {
     if (!s.ev0) {
       if ((e = hipEventCreate(&s.ev0)) != hipSuccess) return hip_fail(e, "event");
       if ((e = hipEventCreate(&s.ev1)) != hipSuccess) return hip_fail(e, "event");
-      if ((e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
       if ((e = hipMalloc(&s.d_ctr, sizeof(WorkCtr))) != hipSuccess) return fail(PHPRNG_E_NOMEM, "work counter");
       // the generation kernel expects a zero counter and leaves it so
       if ((e = hipMemset(s.d_ctr, 0, sizeof(WorkCtr))) != hipSuccess) return hip_fail(e, "work counter");
@@ -1359,7 +1357,6 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
   st = c->launch(P, A, reinterpret_cast<const ReqRec *>(slot->h_blk + sizeof(BatchHdr)), s, mode);
   if (st != PHPRNG_OK) return st;
   if ((e = hipEventRecord(slot->ev1, s)) != hipSuccess) return c->hip_fail(e, "event");
-  if ((e = hipEventRecord(slot->done, s)) != hipSuccess) return c->hip_fail(e, "event");
   slot->busy = true;
   c->last_timed = c->cur_slot;
   c->commit_plan();
@@ -1788,7 +1785,6 @@ extern "C" phprng_status phprng_graph_launch(phprng_graph *g, void *stream) {
   if ((e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
   if ((e = hipGraphLaunch(g->exec, s)) != hipSuccess) return c->hip_fail(e, "graph launch");
   if ((e = hipEventRecord(slot->ev1, s)) != hipSuccess) return c->hip_fail(e, "event");
-  if ((e = hipEventRecord(slot->done, s)) != hipSuccess) return c->hip_fail(e, "event");
   if ((e = hipEventRecord(g->done, s)) != hipSuccess) return c->hip_fail(e, "event");
   if (g->nreq64 > 0) {
     if ((e = hipEventRecord(c->chain_ev, s)) != hipSuccess) return c->hip_fail(e, "chain record");
