@@ -288,6 +288,15 @@ phprng_status phprng_last_kernel_ms(phprng_ctx *ctx, double *ms);
 phprng_status phprng_timing_reset(phprng_ctx *ctx);
 phprng_status phprng_timing_read(phprng_ctx *ctx, double *total_ms, uint64_t *calls);
 
+/* Per-call kernel timing on (on != 0, the default) or off.  Off, a call
+ * records only the event that ends its kernels (the staging slot's
+ * completion), not the one before them: one HIP event record fewer per
+ * call, about 5 microseconds of host time on MI355X with ROCm 7, for
+ * latency-bound callers such as a serving loop.  Calls made with timing off
+ * are not counted by phprng_timing_read, and phprng_last_kernel_ms fails
+ * after one.  phprng_autotune times its candidates either way. */
+phprng_status phprng_set_timing(phprng_ctx *ctx, int on);
+
 /* ---- serving: continuous batching over resident instances -------------------*/
 
 /* A server owns a device output arena and a scheduler thread that runs

@@ -140,6 +140,7 @@ SIGNATURES = {
     "phprng_server_replay": (ctypes.c_int, [_vp, _vp, _u64, ctypes.POINTER(ctypes.c_int64),
                                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "phprng_timing_reset": (ctypes.c_int, [_vp]),
+    "phprng_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "phprng_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)]),
     "phprng_battery_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int]),
     "phprng_battery_destroy": (ctypes.c_int, [_vp]),
@@ -394,6 +395,10 @@ class Context:
 
     def timing_reset(self):
         self._chk(lib().phprng_timing_reset(self._h))
+
+    def set_timing(self, on):
+        """phprng_set_timing: per-call kernel timing on (default) or off."""
+        self._chk(lib().phprng_set_timing(self._h, 1 if on else 0))
 
     def timing_read(self):
         """(total generation-kernel ms, timed calls) since timing_reset."""

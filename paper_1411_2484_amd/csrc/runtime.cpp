@@ -184,12 +184,14 @@ struct phprng_ctx {
     uint64_t cap64 = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the call's kernels; ev1 also marks the slot free
     bool busy = false;
+    bool timed = false;  // ev0 was recorded before the call's kernels
   };
   static constexpr int kSlots = 8;
   static constexpr uint64_t kMinSlotRequests = 8192;
   Slot slots[kSlots];
   int cur_slot = 0;
   int last_timed = -1;
+  bool timing_on = true;  // record ev0 before each call's kernels (phprng_set_timing)
   double acc_ms = 0;  // cumulative kernel time of recycled slots
   uint64_t acc_calls = 0;
   // Planning scratch kept across calls, so that a batch costs O(requests)
@@ -333,7 +335,7 @@ struct phprng_ctx {
     hipError_t e = hipEventSynchronize(s.ev1);
     if (e != hipSuccess) return e;
     float f = 0;
-    if (hipEventElapsedTime(&f, s.ev0, s.ev1) == hipSuccess) {
+    if (s.timed && hipEventElapsedTime(&f, s.ev0, s.ev1) == hipSuccess) {
       acc_ms += f;
       acc_calls += 1;
     }
@@ -1353,12 +1355,13 @@ extern "C" phprng_status phprng_generate(phprng_ctx *c, const phprng_request *re
   }
   GenArgs A = c->args(direct ? slot->h_blk_dev : slot->d_blk, slot->d_ctr, slot->d_t64, slot->cap64, nreq, out_c32,
                       out_c64, out_r, P.tpc);
-  if ((e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
+  if (c->timing_on && (e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
   st = c->launch(P, A, reinterpret_cast<const ReqRec *>(slot->h_blk + sizeof(BatchHdr)), s, mode);
   if (st != PHPRNG_OK) return st;
   if ((e = hipEventRecord(slot->ev1, s)) != hipSuccess) return c->hip_fail(e, "event");
   slot->busy = true;
-  c->last_timed = c->cur_slot;
+  slot->timed = c->timing_on;
+  c->last_timed = c->timing_on ? c->cur_slot : -1;
   c->commit_plan();
   return PHPRNG_OK;
 }
@@ -1403,7 +1406,8 @@ extern "C" phprng_status phprng_generate_noalloc(phprng_ctx *c, const phprng_req
 
 extern "C" phprng_status phprng_last_kernel_ms(phprng_ctx *c, double *ms) {
   if (!c || !ms) return PHPRNG_E_INVALID;
-  if (c->last_timed < 0) return c->fail(PHPRNG_E_INVALID, "no timed launch yet");
+  if (c->last_timed < 0)
+    return c->fail(PHPRNG_E_INVALID, "the last call was not timed (no call yet, or timing off: phprng_set_timing)");
   phprng_ctx::Slot &s = c->slots[c->last_timed];
   hipError_t e = hipEventSynchronize(s.ev1);
   if (e != hipSuccess) return c->hip_fail(e, "event sync");
@@ -1423,6 +1427,12 @@ extern "C" phprng_status phprng_timing_reset(phprng_ctx *c) {
   }
   c->acc_ms = 0;
   c->acc_calls = 0;
+  return PHPRNG_OK;
+}
+
+extern "C" phprng_status phprng_set_timing(phprng_ctx *c, int on) {
+  if (!c) return PHPRNG_E_INVALID;
+  c->timing_on = on != 0;
   return PHPRNG_OK;
 }
 
@@ -1627,6 +1637,9 @@ extern "C" phprng_status phprng_autotune(phprng_ctx *c, uint64_t draws, phprng_t
     }
   }
   const phprng_tuning orig = c->tuning[cls];
+  // the candidates are timed with events whatever the caller's setting
+  const bool timing_was = c->timing_on;
+  c->timing_on = true;
   // one timed call: median kernel time of `reps` calls of shape t
   auto run = [&](const phprng_tuning &t, int reps) -> double {
     c->tuning[cls] = t;
@@ -1684,6 +1697,7 @@ extern "C" phprng_status phprng_autotune(phprng_ctx *c, uint64_t draws, phprng_t
     g_tune_cache[TuneKey{c->arch, c->num_cus, cls}] = bestT;
   }
   if (best) *best = c->tuning[cls];
+  c->timing_on = timing_was;
   return result;
 }
 
@@ -1782,7 +1796,7 @@ extern "C" phprng_status phprng_graph_launch(phprng_graph *g, void *stream) {
     return c->hip_fail(e, "request copy");
   if (g->nreq64 > 0 && c->chain_pending && (e = hipStreamWaitEvent(s, c->chain_ev, 0)) != hipSuccess)
     return c->hip_fail(e, "chain wait");
-  if ((e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
+  if (c->timing_on && (e = hipEventRecord(slot->ev0, s)) != hipSuccess) return c->hip_fail(e, "event");
   if ((e = hipGraphLaunch(g->exec, s)) != hipSuccess) return c->hip_fail(e, "graph launch");
   if ((e = hipEventRecord(slot->ev1, s)) != hipSuccess) return c->hip_fail(e, "event");
   if ((e = hipEventRecord(g->done, s)) != hipSuccess) return c->hip_fail(e, "event");
@@ -1792,7 +1806,8 @@ extern "C" phprng_status phprng_graph_launch(phprng_graph *g, void *stream) {
   }
   g->launched = true;
   slot->busy = true;
-  c->last_timed = c->cur_slot;
+  slot->timed = c->timing_on;
+  c->last_timed = c->timing_on ? c->cur_slot : -1;
   c->commit_plan();
   return PHPRNG_OK;
 }

@@ -341,6 +341,42 @@ def test_tuning_does_not_change_results(ph, ctx):
     ctx.set_tuning(**orig)
 
 
+def test_timing_off_and_on(ph, ctx):
+    """With per-call timing off the draws are the same, last_kernel_ms
+    refuses, and the running totals count only the timed calls."""
+    import torch
+    ids = [int(i) for i in ctx.seed_instances(32, SEED0 + 110, 3, (9, 17), 0, 1 << 40)]
+    ids += [int(i) for i in ctx.seed_instances(64, SEED0 + 111, 2, (9, 17), 0, 1 << 24)]
+    saved = [ctx.get_state(i) for i in ids]
+    counts = [5000, 1, 20000, 3000, 9000]
+    offs = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    reqs = ph.make_requests(ids, counts, offs)
+    total = int(sum(counts))
+    outs = []
+    try:
+        for on in (False, True):
+            for i, st in zip(ids, saved):
+                ctx.set_state(i, st[0], st[1], st[3])
+            ctx.set_timing(on)
+            ctx.timing_reset()
+            o = alloc_outputs(total)
+            for _ in range(3):
+                ctx.generate(reqs, *o)  # three calls in a row; the arrays keep the third
+            torch.cuda.synchronize()
+            outs.append(o)
+            _, calls = ctx.timing_read()
+            if on:
+                assert calls == 3 and ctx.last_kernel_ms() > 0.0
+            else:
+                assert calls == 0
+                with pytest.raises(ph.PhprngError):
+                    ctx.last_kernel_ms()
+    finally:
+        ctx.set_timing(True)
+    for x, y in zip(*outs):
+        assert torch.equal(x, y)
+
+
 def test_rejected_calls_change_nothing(ph, ctx):
     import torch
     ids = ctx.seed_instances(32, SEED0 + 110, 2, (9, 17), 0, 1 << 40)
