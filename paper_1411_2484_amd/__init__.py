@@ -172,6 +172,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libphprng.so is not built: run `python -m paper_1411_2484_amd.build`")
+        # torch ships its own HIP runtime under the same soname as ROCm's.
+        # Loaded first, it is the one the library binds to and both share the
+        # device; loaded after a context has started ROCm's, torch finds no
+        # GPU.  So torch, when installed, is imported before the library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
