@@ -11,9 +11,9 @@ plain, then the allocation-free entry point) check that every instance
 continues from where the previous call left it.
 """
 
+import os
 import random
 
-import numpy as np
 import pytest
 
 from tests.gpu_helpers import alloc_outputs, compare_request, to_host
@@ -119,7 +119,11 @@ def _batch(ph, ctx, orc, insts, rng, mode):
         assert (m, s) == (inst[4], inst[5]), "state of instance %d after the call" % inst[0]
 
 
-@pytest.mark.parametrize("seed", [11, 12, 13, 14])
+# four seeds by default; PHPRNG_EXTRA_SEEDS=k adds seeds 100 .. 100 + k - 1
+SEEDS = [11, 12, 13, 14] + list(range(100, 100 + int(os.environ.get("PHPRNG_EXTRA_SEEDS", "0"))))
+
+
+@pytest.mark.parametrize("seed", SEEDS)
 def test_random_mixed_batches(ph, orc, tab32, tab64, seed):
     rng = random.Random(0x5EED0000 + seed)
     ctx = ph.Context(0, max_instances=64)
