@@ -181,6 +181,10 @@ uint64_t phprng_instance_count(const phprng_ctx *ctx);
  * each continues where the previous one ends.  Positions advance on the host
  * at call time; the kernels run asynchronously on `stream` (a hipStream_t, or
  * NULL for the null stream) and the outputs are valid once it completes.
+ * Successive calls may use different streams without synchronizing: the
+ * device-side message a call commits for its width-64 instances is waited
+ * for by the next call's kernels that read it (one event), so streams
+ * continue correctly in any stream order of the calls.
  * mode: PHPRNG_MODE_PERSISTENT (one work-stealing launch for the whole batch)
  * or PHPRNG_MODE_PLAIN (one launch per request).  A request with count 0 is
  * allowed and does nothing.  The requests are planned on the host during
